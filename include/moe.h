@@ -1,0 +1,184 @@
+/*
+ * moe.h -- C ABI of the MI355X (gfx950) mixture-of-experts layer library.
+ *
+ * The paper this library accompanies defines no mixture-of-experts layer,
+ * so no passage of it can be cited for these calls.  Each entry point
+ * states the definition it implements instead.  Shared definitions:
+ *
+ *   T tokens of width d, E experts, top-k, SwiGLU width f = d_ff,
+ *   capacity C tokens per expert, N = T*k slots.
+ *
+ *   Routing problem: scores s[T,E] (FP32 router logits); choose k distinct
+ *   experts per token maximising the summed scores with no expert above C
+ *   tokens.  Capacity prices p[E] >= 0 are the LP dual variables of the
+ *   capacity rows; given p, every token takes its top-k of a = s - p.
+ *
+ *   Sortable key of an FP32 value with bit pattern u: ~u if the sign bit is
+ *   set, else u | 0x80000000; ranking is by key descending, ties to the
+ *   lower expert index (token side) or the lower token index (expert side).
+ *
+ *   Slot order: slots are sorted by expert, then by token ascending.
+ *
+ * Conventions for every call:
+ *   - every pointer argument is a caller-owned DEVICE pointer unless marked
+ *     "host"; tensors are dense and row-major; pointers must be 16-byte
+ *     aligned; the library never allocates device memory and never
+ *     synchronises the device;
+ *   - ``stream`` is a hipStream_t (NULL = the legacy default stream); all
+ *     work is enqueued on it;
+ *   - a call validates its arguments on the host and returns a negative
+ *     moe_status without launching anything if they are bad; problems only
+ *     the device can see (a non-finite logit, a failed capacity repair) are
+ *     written to the device ``info`` array of moe_route;
+ *   - ``ws`` is a device workspace of at least moe_workspace_bytes() bytes;
+ *     it holds no state between calls, so one buffer can serve every call
+ *     issued in order on one stream;
+ *   - dtype codes: activations (X, X_perm, h, Y, out and their gradients)
+ *     are MOE_F32 or MOE_BF16 (cfg.act); expert weights are MOE_F32,
+ *     MOE_BF16 or MOE_FP8E4M3 (cfg.w).  The router (W_r, b_r, logits,
+ *     prices) is always FP32.
+ */
+#ifndef MOE_H
+#define MOE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MOE_OK = 0,
+  MOE_EINVAL = -1,       /* bad pointer, size, alignment or enum value */
+  MOE_EINFEASIBLE = -2,  /* k > E or E*C < T*k: no routing can exist */
+  MOE_EUNSUPPORTED = -3, /* valid but unsupported shape / dtype combination */
+  MOE_EWORKSPACE = -4,   /* workspace smaller than moe_workspace_bytes() */
+  MOE_EHIP = -5,         /* a HIP launch failed */
+  MOE_ENAN = -6,         /* (device, info[3]) a router logit is not finite */
+  MOE_ECAPACITY = -7     /* (device, info[3]) capacity repair placed no slot */
+} moe_status;
+
+typedef enum { MOE_F32 = 0, MOE_BF16 = 1, MOE_FP8E4M3 = 2 } moe_dtype;
+
+typedef enum {
+  MOE_PRICE_NONE = 0,  /* p = 0: plain top-k (then capacity repair)        */
+  MOE_PRICE_ACP = 1,   /* ascending clearing price from p = 0              */
+  MOE_PRICE_GIVEN = 2, /* p = price[] as passed, no update                  */
+  MOE_PRICE_WARM = 3   /* ascending clearing price from p = warm_gamma*price */
+} moe_price_mode;
+
+typedef struct {
+  int32_t T, d, E, k, d_ff;
+  int32_t capacity;   /* C */
+  int32_t max_iters;  /* cap on price updates (MOE_PRICE_ACP / _WARM) */
+  int32_t act;        /* moe_dtype of activations: MOE_F32 or MOE_BF16 */
+  int32_t w;          /* moe_dtype of expert weights */
+  int32_t price_mode; /* moe_price_mode */
+  float warm_gamma;   /* MOE_PRICE_WARM scale of the given prices */
+} moe_cfg;
+
+/* info[] layout written by moe_route (device int32[8]). */
+enum {
+  MOE_INFO_ITERS = 0,     /* price updates performed */
+  MOE_INFO_CONVERGED = 1, /* 1 if the last ranking respected every capacity */
+  MOE_INFO_OVERFLOW = 2,  /* sum_e max(0, load_e - C) before capacity repair */
+  MOE_INFO_STATUS = 3,    /* MOE_OK, MOE_ENAN or MOE_ECAPACITY */
+  MOE_INFO_ROUNDS = 4,    /* proposal rounds of the capacity repair */
+  MOE_INFO_SIGMA = 5,     /* bits of the FP32 score std sigma_s */
+  MOE_INFO_EPS = 6,       /* bits of the FP32 bid increment eps */
+  MOE_INFO_REPAIRED = 7   /* 1 if the capacity repair ran */
+};
+#define MOE_INFO_LEN 8
+
+/* Bytes of workspace every call below needs for this configuration. */
+moe_status moe_workspace_bytes(const moe_cfg* cfg /* host */, size_t* bytes /* host out */);
+
+/*
+ * moe_route -- router logits, capacity prices and capacity-aware top-k.
+ *
+ *   logits = X W_r^T + b_r                              (FP32 accumulate)
+ *   sigma_s = population std of all logits (fixed-order FP64 reduction,
+ *             rounded to FP32); eps = fl32(fl32(1e-3) * sigma_s)
+ *   price update (MOE_PRICE_ACP / _WARM), all FP32, one rounding per op:
+ *     repeat: a = s - p; rank every token's experts; S_t = best k,
+ *       kappa1_t / kappa2_t = a at ranks k / k+1; load_e = #{t: e in S_t};
+ *       stop if every load_e <= C or after max_iters updates; for each
+ *       overloaded e, q = (C+1)-th largest of the margins
+ *       m_t = s_te - (e in S_t ? kappa2_t : kappa1_t) and
+ *       p_e = max(p_e, nextafter(q, +inf) + eps).
+ *   routing: topk_idx[t, 0..k-1] = S_t in rank order (best first);
+ *     topk_w[t, j] = softmax over the k chosen experts of the raw logits.
+ *   If the final ranking still overloads an expert, a capacity repair runs:
+ *     each overloaded expert keeps its C best holders by (key(a) desc,
+ *     token asc); in rounds, each short token proposes to its best untried
+ *     unheld experts and each expert accepts proposals in (key(a) desc,
+ *     token asc) order while it has room.
+ *
+ *   X       [T,d] cfg.act          Wr [E,d] f32       br [E] f32
+ *   logits  [T,E] f32 out          price [E] f32 in/out (final p)
+ *   topk_idx[T,k] i32 out          topk_w [T,k] f32 out
+ *   load    [E] i32 out (final loads)
+ *   info    [MOE_INFO_LEN] i32 out (see MOE_INFO_*)
+ */
+moe_status moe_route(const moe_cfg* cfg, const void* X, const float* Wr, const float* br,
+                     float* logits, float* price, int32_t* topk_idx, float* topk_w,
+                     int32_t* load, int32_t* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * moe_dispatch -- histogram / prefix-scan permute of the tokens into slots.
+ *   offsets[e] = first slot of expert e (exclusive scan of the loads),
+ *   offsets[E] = N; row_map[slot] = token of the slot; inv_map[t, j] = slot
+ *   of (t, topk_idx[t, j]); X_perm[slot] = X[row_map[slot]].
+ *   X [T,d] act; topk_idx [T,k] i32; offsets [E+1] i32 out;
+ *   row_map [N] i32 out; inv_map [T,k] i32 out; X_perm [N,d] act out.
+ */
+moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int32_t* topk_idx,
+                        int32_t* offsets, int32_t* row_map, int32_t* inv_map, void* X_perm,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * moe_expert_ffn -- grouped SwiGLU experts over uneven per-expert row counts.
+ *   For the rows r of expert e (offsets[e] <= r < offsets[e+1]):
+ *     A = X_perm[r] W1_e^T, B = X_perm[r] W3_e^T, h = silu(A) * B,
+ *     Y[r] = h W2_e^T, silu(z) = z / (1 + exp(-z)); FP32 accumulation, h
+ *     stored in cfg.act between the two products.
+ *   W13 [E, 2f, d] cfg.w (rows 0..f-1 = W1_e, rows f..2f-1 = W3_e);
+ *   W2 [E, d, f] cfg.w; X_perm [N,d] act; Y [N,d] act out.
+ *   W13_scale / W2_scale: per-128x128-block FP32 scales when cfg.w is
+ *   MOE_FP8E4M3, else ignored (may be NULL).
+ */
+moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm, const int32_t* offsets,
+                          const void* W13, const float* W13_scale, const void* W2,
+                          const float* W2_scale, void* Y, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/*
+ * moe_combine -- out[t] = sum_j topk_w[t,j] * Y[inv_map[t,j]], accumulated
+ *   in FP32 in j order, stored in cfg.act.
+ *   Y [N,d] act; inv_map [T,k] i32; topk_w [T,k] f32; out [T,d] act out.
+ */
+moe_status moe_combine(const moe_cfg* cfg, const void* Y, const int32_t* inv_map,
+                       const float* topk_w, void* out, void* stream);
+
+/*
+ * Optional per-kernel timing for benchmarks (host bookkeeping, not
+ * thread-safe).  When enabled, each instrumented kernel launch is bracketed
+ * by a HIP event pair on its stream.  moe_prof_get waits for the recorded
+ * events and returns the summed elapsed time and the launch count of one
+ * kernel name: "router_logits", "price_loop", "dispatch", "gemm1_swiglu",
+ * "gemm2", "combine".  moe_prof_reset forgets every record.
+ */
+moe_status moe_prof_enable(int on);
+moe_status moe_prof_reset(void);
+moe_status moe_prof_get(const char* kernel /* host */, double* total_ms /* host out */,
+                        int32_t* launches /* host out */);
+
+/* Status text (host, static storage). */
+const char* moe_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOE_H */

@@ -1,0 +1,136 @@
+"""ctypes binding of libmoe.so: the C ABI of include/moe.h, name for name.
+
+Argument marshalling only.  Pointers are passed as Python ints (device
+addresses, e.g. ``tensor.data_ptr()``), the stream as an int handle.  A
+missing library raises at load time: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmoe.so")
+
+MOE_OK = 0
+MOE_EINVAL = -1
+MOE_EINFEASIBLE = -2
+MOE_EUNSUPPORTED = -3
+MOE_EWORKSPACE = -4
+MOE_EHIP = -5
+MOE_ENAN = -6
+MOE_ECAPACITY = -7
+
+MOE_F32, MOE_BF16, MOE_FP8E4M3 = 0, 1, 2
+MOE_PRICE_NONE, MOE_PRICE_ACP, MOE_PRICE_GIVEN, MOE_PRICE_WARM = 0, 1, 2, 3
+
+INFO_ITERS, INFO_CONVERGED, INFO_OVERFLOW, INFO_STATUS = 0, 1, 2, 3
+INFO_ROUNDS, INFO_SIGMA, INFO_EPS, INFO_REPAIRED = 4, 5, 6, 7
+INFO_LEN = 8
+
+
+class MoeCfg(ctypes.Structure):
+    _fields_ = [
+        ("T", ctypes.c_int32), ("d", ctypes.c_int32), ("E", ctypes.c_int32),
+        ("k", ctypes.c_int32), ("d_ff", ctypes.c_int32), ("capacity", ctypes.c_int32),
+        ("max_iters", ctypes.c_int32), ("act", ctypes.c_int32), ("w", ctypes.c_int32),
+        ("price_mode", ctypes.c_int32), ("warm_gamma", ctypes.c_float),
+    ]
+
+
+class MoEError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} (status {status})")
+
+
+_P = ctypes.c_void_p
+_S = ctypes.c_size_t
+_CFG = ctypes.POINTER(MoeCfg)
+
+# name -> argtypes (every function returns int32 status unless noted)
+SIGNATURES = {
+    "moe_workspace_bytes": [_CFG, ctypes.POINTER(ctypes.c_size_t)],
+    "moe_route": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_dispatch": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_expert_ffn": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_combine": [_CFG, _P, _P, _P, _P, _P],
+    "moe_prof_enable": [ctypes.c_int],
+    "moe_prof_reset": [],
+    "moe_prof_get": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)],
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmoe.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2606_17065_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int32
+        L.moe_strerror.argtypes = [ctypes.c_int]
+        L.moe_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().moe_strerror(int(status)).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != MOE_OK:
+        raise MoEError(status, where)
+
+
+def make_cfg(T, d, E, k, d_ff, capacity, max_iters=50, act=MOE_BF16, w=MOE_BF16,
+             price_mode=MOE_PRICE_ACP, warm_gamma=0.9) -> MoeCfg:
+    return MoeCfg(T, d, E, k, d_ff, capacity, max_iters, act, w, price_mode, warm_gamma)
+
+
+def moe_workspace_bytes(cfg: MoeCfg) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().moe_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)), "moe_workspace_bytes")
+    return int(out.value)
+
+
+def moe_route(cfg, X, Wr, br, logits, price, topk_idx, topk_w, load, info, ws, ws_bytes, stream):
+    _check(lib().moe_route(ctypes.byref(cfg), X, Wr, br, logits, price, topk_idx, topk_w, load,
+                           info, ws, ws_bytes, stream), "moe_route")
+
+
+def moe_dispatch(cfg, X, topk_idx, offsets, row_map, inv_map, X_perm, ws, ws_bytes, stream):
+    _check(lib().moe_dispatch(ctypes.byref(cfg), X, topk_idx, offsets, row_map, inv_map, X_perm,
+                              ws, ws_bytes, stream), "moe_dispatch")
+
+
+def moe_expert_ffn(cfg, X_perm, offsets, W13, W13_scale, W2, W2_scale, Y, ws, ws_bytes, stream):
+    _check(lib().moe_expert_ffn(ctypes.byref(cfg), X_perm, offsets, W13, W13_scale, W2, W2_scale,
+                                Y, ws, ws_bytes, stream), "moe_expert_ffn")
+
+
+def moe_combine(cfg, Y, inv_map, topk_w, out, stream):
+    _check(lib().moe_combine(ctypes.byref(cfg), Y, inv_map, topk_w, out, stream), "moe_combine")
+
+
+def moe_prof_enable(on: bool) -> None:
+    _check(lib().moe_prof_enable(1 if on else 0), "moe_prof_enable")
+
+
+def moe_prof_reset() -> None:
+    _check(lib().moe_prof_reset(), "moe_prof_reset")
+
+
+def moe_prof_get(kernel: str):
+    """(total milliseconds, launches) recorded for one instrumented kernel."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int32(0)
+    _check(lib().moe_prof_get(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)), "moe_prof_get")
+    return float(ms.value), int(n.value)

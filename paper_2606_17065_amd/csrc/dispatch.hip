@@ -1,0 +1,221 @@
+// Token permute (histogram + prefix scan + stable scatter + row gather) and
+// the weighted combine, for gfx950.
+//
+// Slots are ordered by expert, then by token.  A token block of 256 owns a
+// contiguous run of every expert's slots: its base is the expert's offset
+// plus the counts of all earlier blocks, and a token's rank inside its
+// block comes from per-wavefront 64-bit occupancy masks.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+// Indices arriving from the caller are clamped so that malformed routing
+// tables give unspecified values, never an out-of-bounds access.
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+constexpr int TB = 256;  // tokens per block of the count / scatter kernels
+
+__global__ __launch_bounds__(TB) void dispatch_count(const int32_t* __restrict__ idx, int T,
+                                                     int E, int k, int32_t* __restrict__ cnt) {
+  __shared__ int hist[MOE_MAX_E];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < E; e += TB) hist[e] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * TB + tid;
+  if (t < T)
+    for (int j = 0; j < k; ++j) atomicAdd(&hist[clampi(idx[(size_t)t * k + j], 0, E - 1)], 1);
+  __syncthreads();
+  for (int e = tid; e < E; e += TB) cnt[(size_t)blockIdx.x * E + e] = hist[e];
+}
+
+// One block of up to 1024 threads: thread e walks its expert's column of
+// block counts; then an exclusive scan over the expert totals.
+__global__ __launch_bounds__(1024) void dispatch_scan(int32_t* __restrict__ cnt_base, int nb,
+                                                      int E, int32_t* __restrict__ offsets) {
+  __shared__ int tot[MOE_MAX_E];
+  __shared__ int off[MOE_MAX_E + 1];
+  const int e = threadIdx.x;
+  int run = 0;
+  if (e < E) {
+    for (int b = 0; b < nb; ++b) {
+      int c = cnt_base[(size_t)b * E + e];
+      cnt_base[(size_t)b * E + e] = run;
+      run += c;
+    }
+    tot[e] = run;
+  }
+  __syncthreads();
+  if (e == 0) {
+    int acc = 0;
+    for (int i = 0; i < E; ++i) {
+      off[i] = acc;
+      acc += tot[i];
+    }
+    off[E] = acc;
+  }
+  __syncthreads();
+  if (e < E) {
+    offsets[e] = off[e];
+    for (int b = 0; b < nb; ++b) cnt_base[(size_t)b * E + e] += off[e];
+  }
+  if (e == 0) offsets[E] = off[E];
+}
+
+__global__ __launch_bounds__(TB) void dispatch_scatter(const int32_t* __restrict__ idx, int T,
+                                                       int E, int k,
+                                                       const int32_t* __restrict__ base,
+                                                       int32_t* __restrict__ row_map,
+                                                       int32_t* __restrict__ inv_map) {
+  __shared__ unsigned long long occ[TB / 64][MOE_MAX_E];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < (TB / 64) * E; i += TB) occ[i / E][i % E] = 0ull;
+  __syncthreads();
+  const int t = blockIdx.x * TB + tid;
+  if (t < T)
+    for (int j = 0; j < k; ++j)
+      atomicOr(&occ[wv][clampi(idx[(size_t)t * k + j], 0, E - 1)], 1ull << lane);
+  __syncthreads();
+  if (t < T) {
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int j = 0; j < k; ++j) {
+      const int e = clampi(idx[(size_t)t * k + j], 0, E - 1);
+      int rank = __popcll(occ[wv][e] & lt);
+      for (int w = 0; w < wv; ++w) rank += __popcll(occ[w][e]);
+      const int slot = base[(size_t)blockIdx.x * E + e] + rank;
+      row_map[slot] = t;
+      inv_map[(size_t)t * k + j] = slot;
+    }
+  }
+}
+
+// One wavefront per token: read the row once (16-byte vectors), write it to
+// each of the token's k slots.
+__global__ __launch_bounds__(256) void dispatch_gather(const u32x4* __restrict__ X, int T,
+                                                       int row_vec, int k,
+                                                       const int32_t* __restrict__ inv_map,
+                                                       u32x4* __restrict__ Xp) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= T) return;
+  int slots[MOE_MAX_K];
+#pragma unroll
+  for (int j = 0; j < MOE_MAX_K; ++j)
+    slots[j] = j < k ? clampi(inv_map[(size_t)t * k + j], 0, T * k - 1) : 0;
+  for (int c = lane; c < row_vec; c += 64) {
+    const u32x4 v = X[(size_t)t * row_vec + c];
+#pragma unroll
+    for (int j = 0; j < MOE_MAX_K; ++j)
+      if (j < k) Xp[(size_t)slots[j] * row_vec + c] = v;
+  }
+}
+
+// out[t] = sum_j w[t,j] * Y[inv_map[t,j]], FP32 in j order; one wavefront
+// per token, 8 elements per lane per step.
+template <typename TA>
+__global__ __launch_bounds__(256) void combine_kernel(const TA* __restrict__ Y, int T, int d,
+                                                      int k, const int32_t* __restrict__ inv_map,
+                                                      const float* __restrict__ w,
+                                                      TA* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= T) return;
+  int slots[MOE_MAX_K];
+  float ws[MOE_MAX_K];
+#pragma unroll
+  for (int j = 0; j < MOE_MAX_K; ++j) {
+    slots[j] = j < k ? clampi(inv_map[(size_t)t * k + j], 0, T * k - 1) : 0;
+    ws[j] = j < k ? w[(size_t)t * k + j] : 0.0f;
+  }
+  for (int c0 = lane * 8; c0 < d; c0 += 64 * 8) {
+    float acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < MOE_MAX_K; ++j) {
+      if (j < k) {
+        const TA* yr = Y + (size_t)slots[j] * d + c0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = acc[i] + ws[j] * ActIO<TA>::ld(yr, i);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ActIO<TA>::st(out, (size_t)t * d + c0 + i, acc[i]);
+  }
+}
+
+struct DispWs {
+  int32_t* cnt;
+};
+
+DispWs carve_dispatch(const moe_cfg& c, void* base, size_t* total) {
+  WsCarve wc{(char*)base, 0};
+  DispWs r;
+  const size_t nb = ((size_t)c.T + TB - 1) / TB;
+  r.cnt = wc.take<int32_t>((nb > 0 ? nb : 1) * (size_t)c.E);
+  if (total) *total = align_up(wc.off, 256);
+  return r;
+}
+
+}  // namespace
+
+size_t dispatch_ws_bytes(const moe_cfg& c) {
+  size_t total = 0;
+  carve_dispatch(c, nullptr, &total);
+  return total;
+}
+
+extern "C" moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int32_t* topk_idx,
+                                   int32_t* offsets, int32_t* row_map, int32_t* inv_map,
+                                   void* X_perm, void* ws, size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (!offsets) return MOE_EINVAL;
+  if (c.T > 0 && (!X || !topk_idx || !row_map || !inv_map || !X_perm)) return MOE_EINVAL;
+  if (!aligned(X, 16) || !aligned(X_perm, 16) || !aligned(topk_idx, 4) || !aligned(offsets, 4) ||
+      !aligned(row_map, 4) || !aligned(inv_map, 4))
+    return MOE_EINVAL;
+  if (ws_bytes < dispatch_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  DispWs w = carve_dispatch(c, ws, nullptr);
+  const int nb = (c.T + TB - 1) / TB;
+  PROF_BEGIN("dispatch", st);
+  if (c.T > 0) {
+    hipLaunchKernelGGL(dispatch_count, dim3(nb), dim3(TB), 0, st, topk_idx, c.T, c.E, c.k, w.cnt);
+  }
+  hipLaunchKernelGGL(dispatch_scan, dim3(1), dim3(1024), 0, st, w.cnt, nb, c.E, offsets);
+  if (c.T > 0) {
+    hipLaunchKernelGGL(dispatch_scatter, dim3(nb), dim3(TB), 0, st, topk_idx, c.T, c.E, c.k, w.cnt,
+                       row_map, inv_map);
+    const int row_vec = c.d * act_bytes(c.act) / 16;
+    hipLaunchKernelGGL(dispatch_gather, dim3((c.T + 3) / 4), dim3(256), 0, st, (const u32x4*)X, c.T,
+                       row_vec, c.k, inv_map, (u32x4*)X_perm);
+  }
+  PROF_END("dispatch", st);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_combine(const moe_cfg* cfg, const void* Y, const int32_t* inv_map,
+                                  const float* topk_w, void* out, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.T == 0) return MOE_OK;
+  if (!Y || !inv_map || !topk_w || !out) return MOE_EINVAL;
+  if (!aligned(Y, 16) || !aligned(out, 16) || !aligned(inv_map, 4) || !aligned(topk_w, 4))
+    return MOE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  dim3 g((c.T + 3) / 4);
+  PROF_BEGIN("combine", st);
+  if (c.act == MOE_F32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_kernel<float>), g, dim3(256), 0, st, (const float*)Y,
+                       c.T, c.d, c.k, inv_map, topk_w, (float*)out);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_kernel<bf16_t>), g, dim3(256), 0, st,
+                       (const bf16_t*)Y, c.T, c.d, c.k, inv_map, topk_w, (bf16_t*)out);
+  PROF_END("combine", st);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}

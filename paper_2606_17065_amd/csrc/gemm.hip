@@ -1,0 +1,319 @@
+// Grouped expert GEMMs over uneven per-expert row counts, for gfx950.
+//
+//   GEMM 1 (SwiGLU):  h = silu(Xp W1_e^T) * (Xp W3_e^T)     [rows of e, f]
+//   GEMM 2:           Y = h W2_e^T                           [rows of e, d]
+//
+// Both products are "NT": the A rows (tokens) and the B rows (weight rows)
+// are contiguous along K, which is exactly the operand layout of the MFMA
+// fragments.  A tile scheduler maps blockIdx.x to (expert, row tile) from
+// the exclusive scan of ceil(rows_e / BM); blocks past the last tile exit.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+
+// tile_start[e] = sum_{e' < e} ceil(rows_e' / BM); tile_start[E] = total.
+__global__ __launch_bounds__(1024) void ffn_tiles(const int32_t* __restrict__ offsets, int E,
+                                                  int BM, int32_t* __restrict__ tile_start) {
+  __shared__ int buf[2][MOE_MAX_E + 1];
+  const int e = threadIdx.x;
+  int v = 0;
+  if (e < E) v = (offsets[e + 1] - offsets[e] + BM - 1) / BM;
+  buf[0][e] = v;
+  __syncthreads();
+  int cur = 0;
+  for (int off = 1; off < 1024; off <<= 1) {
+    int x = buf[cur][e];
+    if (e >= off) x += buf[cur][e - off];
+    buf[cur ^ 1][e] = x;
+    cur ^= 1;
+    __syncthreads();
+  }
+  // buf[cur][e] = inclusive sum
+  if (e < E) tile_start[e + 1] = buf[cur][e];
+  if (e == 0) tile_start[0] = 0;
+}
+
+__device__ __forceinline__ bool find_tile(const int32_t* __restrict__ tile_start,
+                                          const int32_t* __restrict__ offsets, int E, int BM,
+                                          int N, int mt, int& e_out, int& row0, int& rows) {
+  if (mt >= tile_start[E]) return false;
+  int lo = 0, hi = E - 1;  // largest e with tile_start[e] <= mt
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= mt) lo = mid;
+    else hi = mid - 1;
+  }
+  e_out = lo;
+  row0 = offsets[lo] + (mt - tile_start[lo]) * BM;
+  rows = min(BM, offsets[lo + 1] - row0);
+  // rows outside [0, N) are never touched, whatever the offsets hold
+  if (row0 < 0 || row0 >= N) return false;
+  rows = min(rows, N - row0);
+  return rows > 0;
+}
+
+// ---------------------------------------------------------------- BF16 MFMA
+// Block tile: 128 rows x 128 B-rows, K step 32; 4 wavefronts in 2 x 2, each
+// owning 64 rows x 64 B-rows as 2 x 2 tiles of v_mfma_f32_32x32x16_bf16.
+// SwiGLU mode: B-rows 0..63 are W1 rows n0..n0+63 and 64..127 the matching
+// W3 rows, so a wavefront's two column tiles are (W1 cols, W3 cols) of the
+// same 32 outputs and the epilogue combines them in registers.
+
+constexpr int BM = 128, BNE = 128, BK = 32, LDK = BK + 8;
+
+template <bool SWIGLU>
+__global__ __launch_bounds__(256) void gemm_bf16(const bf16_t* __restrict__ A,
+                                                 const bf16_t* __restrict__ B,
+                                                 bf16_t* __restrict__ C,
+                                                 const int32_t* __restrict__ offsets,
+                                                 const int32_t* __restrict__ tile_start, int E,
+                                                 int N, int K, int f, int Ncols) {
+  // K: reduction length; f: W1/W3 row split (SwiGLU); Ncols: C row length
+  __shared__ __attribute__((aligned(16))) bf16_t As[BM * LDK];
+  __shared__ __attribute__((aligned(16))) bf16_t Bs[BNE * LDK];
+  int e, row0, rows;
+  if (!find_tile(tile_start, offsets, E, BM, N, blockIdx.x, e, row0, rows)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int n0 = blockIdx.y * (SWIGLU ? 64 : 128);
+  const size_t Brows_e = SWIGLU ? (size_t)2 * f : (size_t)Ncols;
+  const bf16_t* Be = B + (size_t)e * Brows_e * K;
+
+  // global -> register staging: 2 chunks of 16 B for A and for B per thread
+  u32x4 ra[2], rb[2];
+  int a_row[2], a_col[2], b_src[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int c = tid + 256 * r;
+    a_row[r] = c >> 2;
+    a_col[r] = (c & 3) * 8;
+    const int br = c >> 2;
+    b_src[r] = SWIGLU ? (br < 64 ? n0 + br : f + n0 + (br - 64)) : n0 + br;
+  }
+#define GLOAD(k0)                                                                     \
+  _Pragma("unroll") for (int r = 0; r < 2; ++r) {                                     \
+    if (a_row[r] < rows)                                                              \
+      ra[r] = *(const u32x4*)(A + (size_t)(row0 + a_row[r]) * K + (k0) + a_col[r]);   \
+    else                                                                              \
+      ra[r] = u32x4{0u, 0u, 0u, 0u};                                                   \
+    rb[r] = *(const u32x4*)(Be + (size_t)b_src[r] * K + (k0) + a_col[r]);             \
+  }
+#define SSTORE()                                                    \
+  _Pragma("unroll") for (int r = 0; r < 2; ++r) {                    \
+    *(u32x4*)(As + a_row[r] * LDK + a_col[r]) = ra[r];               \
+    *(u32x4*)(Bs + a_row[r] * LDK + a_col[r]) = rb[r];               \
+  }
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
+
+  // B-row base of the wavefront's two column tiles
+  const int bro0 = SWIGLU ? wn * 32 : wn * 64;
+  const int bro1 = SWIGLU ? 64 + wn * 32 : wn * 64 + 32;
+  const int fr = lane & 31, fk = (lane >> 5) * 8;
+
+  GLOAD(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    SSTORE();
+    __syncthreads();
+    if (k0 + BK < K) { GLOAD(k0 + BK); }
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 16) {
+      bf16x8 af[2], bfr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        af[i] = *(const bf16x8*)(As + (wm * 64 + i * 32 + fr) * LDK + ks + fk);
+      bfr[0] = *(const bf16x8*)(Bs + (bro0 + fr) * LDK + ks + fk);
+      bfr[1] = *(const bf16x8*)(Bs + (bro1 + fr) * LDK + ks + fk);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#undef GLOAD
+#undef SSTORE
+
+  // epilogue: lane holds column fr, rows (q/4)*8 + (lane/32)*4 + q%4
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int rl = wm * 64 + i * 32 + (q >> 2) * 8 + (lane >> 5) * 4 + (q & 3);
+      if (rl >= rows) continue;
+      const size_t row = (size_t)(row0 + rl);
+      if (SWIGLU) {
+        const float a = acc[i][0][q], b = acc[i][1][q];
+        C[row * Ncols + n0 + wn * 32 + fr] = (bf16_t)(silu(a) * b);
+      } else {
+        C[row * Ncols + n0 + wn * 64 + fr] = (bf16_t)acc[i][0][q];
+        C[row * Ncols + n0 + wn * 64 + 32 + fr] = (bf16_t)acc[i][1][q];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- FP32 SIMT
+// Block tile 64 rows x 64 B-rows, K step 16, 256 threads with 4 x 4 outputs.
+// SwiGLU mode: B-rows 0..31 = W1 rows n0..n0+31, 32..63 = the W3 rows; a
+// thread's column pair {2tx, 2tx+1} is taken from both halves.
+
+constexpr int FBM = 64, FBK = 16;
+
+template <bool SWIGLU>
+__global__ __launch_bounds__(256) void gemm_f32(const float* __restrict__ A,
+                                                const float* __restrict__ B, float* __restrict__ C,
+                                                const int32_t* __restrict__ offsets,
+                                                const int32_t* __restrict__ tile_start, int E,
+                                                int N, int K, int f, int Ncols) {
+  __shared__ float As[FBK][FBM + 1];
+  __shared__ float Bs[FBK][64 + 1];
+  int e, row0, rows;
+  if (!find_tile(tile_start, offsets, E, FBM, N, blockIdx.x, e, row0, rows)) return;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int nspan = SWIGLU ? 32 : 64;
+  const int n0 = blockIdx.y * nspan;
+  const size_t Brows_e = SWIGLU ? (size_t)2 * f : (size_t)Ncols;
+  const float* Be = B + (size_t)e * Brows_e * K;
+  const int nlim = SWIGLU ? f : Ncols;
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+  for (int k0 = 0; k0 < K; k0 += FBK) {
+    for (int i = tid; i < FBM * FBK; i += 256) {
+      const int r = i / FBK, c = i % FBK, kk = k0 + c;
+      As[c][r] = (r < rows && kk < K) ? A[(size_t)(row0 + r) * K + kk] : 0.0f;
+      int n = SWIGLU ? (r < 32 ? n0 + r : n0 + r - 32) : n0 + r;
+      int src = SWIGLU ? (r < 32 ? n : f + n) : n;
+      Bs[c][r] = (n < nlim && kk < K) ? Be[(size_t)src * K + kk] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < FBK; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = SWIGLU ? (j < 2 ? tx * 2 + j : 32 + tx * 2 + (j - 2)) : tx * 4 + j;
+        b[j] = Bs[kk][col];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fmaf(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rl = ty * 4 + i;
+    if (rl >= rows) continue;
+    const size_t row = (size_t)(row0 + rl);
+    if (SWIGLU) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + tx * 2 + j;
+        if (n < f) C[row * Ncols + n] = silu(acc[i][j]) * acc[i][j + 2];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = n0 + tx * 4 + j;
+        if (n < Ncols) C[row * Ncols + n] = acc[i][j];
+      }
+    }
+  }
+}
+
+struct FfnWs {
+  int32_t* tile_start;
+  void* h;
+};
+
+FfnWs carve_ffn(const moe_cfg& c, void* base, size_t* total) {
+  WsCarve wc{(char*)base, 0};
+  FfnWs r;
+  r.tile_start = wc.take<int32_t>((size_t)c.E + 1);
+  const size_t N = (size_t)c.T * c.k;
+  r.h = wc.take<char>(N * (size_t)c.d_ff * act_bytes(c.act));
+  if (total) *total = align_up(wc.off, 256);
+  return r;
+}
+
+}  // namespace
+
+size_t ffn_ws_bytes(const moe_cfg& c) {
+  size_t total = 0;
+  carve_ffn(c, nullptr, &total);
+  return total;
+}
+
+extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
+                                     const int32_t* offsets, const void* W13,
+                                     const float* W13_scale, const void* W2,
+                                     const float* W2_scale, void* Y, void* ws, size_t ws_bytes,
+                                     void* stream) {
+  (void)W13_scale;
+  (void)W2_scale;
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (!offsets || !W13 || !W2) return MOE_EINVAL;
+  if (c.T > 0 && (!X_perm || !Y)) return MOE_EINVAL;
+  if (!aligned(X_perm, 16) || !aligned(W13, 16) || !aligned(W2, 16) || !aligned(Y, 16) ||
+      !aligned(offsets, 4))
+    return MOE_EINVAL;
+  const bool f32path = c.act == MOE_F32 && c.w == MOE_F32;
+  const bool bf16path = c.act == MOE_BF16 && c.w == MOE_BF16;
+  if (!f32path && !bf16path) return MOE_EUNSUPPORTED;
+  if (bf16path && (c.d_ff % 64 != 0 || c.d % 128 != 0)) return MOE_EUNSUPPORTED;
+  if (ws_bytes < ffn_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  if (c.T == 0) return MOE_OK;
+  hipStream_t st = (hipStream_t)stream;
+  FfnWs w = carve_ffn(c, ws, nullptr);
+  const int N = c.T * c.k;
+  if (bf16path) {
+    hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, BM, w.tile_start);
+    dim3 g1((N + BM - 1) / BM + c.E, c.d_ff / 64);
+    PROF_BEGIN("gemm1_swiglu", st);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16<true>), g1, dim3(256), 0, st,
+                       (const bf16_t*)X_perm, (const bf16_t*)W13, (bf16_t*)w.h, offsets,
+                       w.tile_start, c.E, N, c.d, c.d_ff, c.d_ff);
+    PROF_END("gemm1_swiglu", st);
+    dim3 g2((N + BM - 1) / BM + c.E, c.d / 128);
+    PROF_BEGIN("gemm2", st);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16<false>), g2, dim3(256), 0, st,
+                       (const bf16_t*)w.h, (const bf16_t*)W2, (bf16_t*)Y, offsets, w.tile_start,
+                       c.E, N, c.d_ff, c.d_ff, c.d);
+    PROF_END("gemm2", st);
+  } else {
+    hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, FBM, w.tile_start);
+    dim3 g1((N + FBM - 1) / FBM + c.E, (c.d_ff + 31) / 32);
+    PROF_BEGIN("gemm1_swiglu", st);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_f32<true>), g1, dim3(256), 0, st, (const float*)X_perm,
+                       (const float*)W13, (float*)w.h, offsets, w.tile_start, c.E, N, c.d, c.d_ff,
+                       c.d_ff);
+    PROF_END("gemm1_swiglu", st);
+    dim3 g2((N + FBM - 1) / FBM + c.E, (c.d + 63) / 64);
+    PROF_BEGIN("gemm2", st);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_f32<false>), g2, dim3(256), 0, st, (const float*)w.h,
+                       (const float*)W2, (float*)Y, offsets, w.tile_start, c.E, N, c.d_ff, c.d_ff,
+                       c.d);
+    PROF_END("gemm2", st);
+  }
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}

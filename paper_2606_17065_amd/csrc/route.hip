@@ -1,0 +1,756 @@
+// Router logits, capacity prices (ascending clearing price) and
+// capacity-aware top-k for gfx950.
+//
+// This translation unit is compiled with -ffp-contract=off: every FP32 and
+// FP64 operation of the price loop is rounded on its own, so the sequence
+// of operations below is the definition the FP32 replica reproduces.
+//
+// Data flow of moe_route (one stream, no host synchronisation):
+//   route_init        state words, load buffers, starting prices
+//   router_logits     s[T,E] = X W_r^T + b_r, and its transpose sT[E,T]
+//   score_partials    per-256-token FP64 partial sums of s and s^2
+//   score_sigma       sigma_s, eps, non-finite check
+//   (acp_rank, acp_select) x (max_iters + 1)   price loop, early-exit flags
+//   capacity_repair   only if the final ranking still overloads an expert
+//   route_finalize    info[] from the state words
+#include <math.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int SIG_BLOCK = 256;   // token block of the fixed-order reduction
+constexpr int RANK_THREADS = 64; // one wavefront: 64 tokens, one per lane
+constexpr int SEL_THREADS = 512;
+constexpr int REP_THREADS = 1024;
+
+// ------------------------------------------------------------------ init
+
+__global__ void route_init(int32_t* state, int32_t* loadbuf, int E, float* price, int mode,
+                           float gamma) {
+  int tid = threadIdx.x;
+  if (tid < ST_LEN) state[tid] = 0;
+  for (int e = tid; e < 2 * E; e += blockDim.x) loadbuf[e] = 0;
+  for (int e = tid; e < E; e += blockDim.x) {
+    if (mode == MOE_PRICE_NONE || mode == MOE_PRICE_ACP) price[e] = 0.0f;
+    else if (mode == MOE_PRICE_WARM) price[e] = gamma * price[e];
+  }
+}
+
+// ------------------------------------------------------------ router GEMM
+// 64 tokens x 64 experts per block, 256 threads, 4x4 outputs per thread,
+// FP32 fused multiply-add accumulation over d in chunks of 32.
+
+template <typename TX>
+__global__ __launch_bounds__(256) void router_logits(const TX* __restrict__ X,
+                                                     const float* __restrict__ Wr,
+                                                     const float* __restrict__ br,
+                                                     float* __restrict__ s, float* __restrict__ sT,
+                                                     int T, int d, int E) {
+  __shared__ float Xs[32][64 + 1];
+  __shared__ float Ws[32][64 + 1];
+  __shared__ float Ts[64][64 + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int t0 = blockIdx.x * 64, e0 = blockIdx.y * 64;
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+  for (int k0 = 0; k0 < d; k0 += 32) {
+    for (int i = tid; i < 64 * 32; i += 256) {
+      int r = i >> 5, c = i & 31;
+      int t = t0 + r, kk = k0 + c;
+      Xs[c][r] = (t < T && kk < d) ? ActIO<TX>::ld(X, (size_t)t * d + kk) : 0.0f;
+      int e = e0 + r;
+      Ws[c][r] = (e < E && kk < d) ? Wr[(size_t)e * d + kk] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = Xs[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Ws[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fmaf(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int t = t0 + ty * 4 + i;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int e = e0 + tx * 4 + j;
+      float v = acc[i][j] + ((e < E) ? br[e] : 0.0f);
+      if (t < T && e < E) s[(size_t)t * E + e] = v;
+      Ts[tx * 4 + j][ty * 4 + i] = v;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < 64 * 64; i += 256) {
+    int el = i >> 6, tl = i & 63;
+    int e = e0 + el, t = t0 + tl;
+    if (e < E && t < T) sT[(size_t)e * T + t] = Ts[el][tl];
+  }
+}
+
+// ------------------------------------------------- sigma_s, fixed order
+// Block b owns tokens [256b, 256b+256); thread i accumulates its token's
+// row from expert 0 upward in FP64, then the block halves (stride 128..1).
+
+__global__ __launch_bounds__(SIG_BLOCK) void score_partials(const float* __restrict__ sT, int T,
+                                                            int E, double* part) {
+  __shared__ double v1[SIG_BLOCK];
+  __shared__ double v2[SIG_BLOCK];
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x * SIG_BLOCK + tid;
+  double r1 = 0.0, r2 = 0.0;
+  if (t < T) {
+    for (int e = 0; e < E; ++e) {
+      double v = (double)sT[(size_t)e * T + t];
+      r1 = r1 + v;
+      r2 = r2 + v * v;
+    }
+  }
+  v1[tid] = r1;
+  v2[tid] = r2;
+  __syncthreads();
+  for (int st = SIG_BLOCK / 2; st >= 1; st >>= 1) {
+    if (tid < st) {
+      v1[tid] = v1[tid] + v1[tid + st];
+      v2[tid] = v2[tid] + v2[tid + st];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[2 * blockIdx.x] = v1[0];
+    part[2 * blockIdx.x + 1] = v2[0];
+  }
+}
+
+// Running sum i takes block totals i, i+256, ... in order; then halving.
+// mean = S1/n, var = max(S2/n - mean*mean, 0), sigma = fl32(sqrt(var)),
+// eps = fl32(fl32(1e-3) * sigma).
+__global__ __launch_bounds__(SIG_BLOCK) void score_sigma(const double* part, int nb, double n,
+                                                         int32_t* state) {
+  __shared__ double v1[SIG_BLOCK];
+  __shared__ double v2[SIG_BLOCK];
+  const int tid = threadIdx.x;
+  double a1 = 0.0, a2 = 0.0;
+  for (int j = tid; j < nb; j += SIG_BLOCK) {
+    a1 = a1 + part[2 * j];
+    a2 = a2 + part[2 * j + 1];
+  }
+  v1[tid] = a1;
+  v2[tid] = a2;
+  __syncthreads();
+  for (int st = SIG_BLOCK / 2; st >= 1; st >>= 1) {
+    if (tid < st) {
+      v1[tid] = v1[tid] + v1[tid + st];
+      v2[tid] = v2[tid] + v2[tid + st];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double S1 = v1[0], S2 = v2[0];
+    if (!isfinite(S1) || !isfinite(S2)) {
+      state[ST_STATUS] = MOE_ENAN;
+      state[ST_DONE] = 1;
+      return;
+    }
+    double mean = S1 / n;
+    double m2 = mean * mean;
+    double var = S2 / n - m2;
+    if (var < 0.0) var = 0.0;
+    float sigma = (float)sqrt(var);
+    float eps = 1.0e-3f * sigma;
+    state[ST_SIGMA] = __float_as_int(sigma);
+    state[ST_EPS] = __float_as_int(eps);
+  }
+}
+
+// ----------------------------------------------------- top-L insertion
+// Composite 64-bit rank key: (sortable key of a) << 32 | (0xFFFFFFFF - e),
+// so the maximum is the best expert and equal keys prefer the lower e.
+
+__device__ __forceinline__ uint64_t rank_key(float a, int e) {
+  return ((uint64_t)f32_key(a) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)e);
+}
+
+template <int L>
+__device__ __forceinline__ void insert_top(uint64_t (&v)[L], uint64_t x) {
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    uint64_t hi = x > v[j] ? x : v[j];
+    uint64_t lo = x > v[j] ? v[j] : x;
+    v[j] = hi;
+    x = lo;
+  }
+}
+
+template <int L>
+__device__ __forceinline__ uint64_t pick(const uint64_t (&v)[L], int j) {
+  uint64_t r = 0;
+#pragma unroll
+  for (int i = 0; i < L; ++i)
+    if (i == j) r = v[i];
+  return r;
+}
+
+__device__ __forceinline__ int key_expert(uint64_t v) { return (int)(0xFFFFFFFFu - (uint32_t)v); }
+
+// One ranking pass of the price loop (iteration ``it``): lane = token.
+// Writes the routing and gate weights for the current prices, the margin
+// keys mT[e][t] of every expert, and adds the block's loads to
+// loadbuf[it & 1].
+template <int L>
+__global__ __launch_bounds__(RANK_THREADS) void acp_rank(
+    const float* __restrict__ sT, const float* __restrict__ logits, const float* __restrict__ price,
+    int T, int E, int k, int it, const int32_t* __restrict__ state, uint32_t* __restrict__ mT,
+    int32_t* __restrict__ idx, float* __restrict__ w, int32_t* __restrict__ loadbuf) {
+  if (state[ST_DONE]) return;
+  __shared__ int hist[MOE_MAX_E];
+  __shared__ float ps[MOE_MAX_E];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < E; e += RANK_THREADS) {
+    hist[e] = 0;
+    ps[e] = price[e];
+  }
+  __syncthreads();
+  const int t = blockIdx.x * RANK_THREADS + tid;
+  if (t < T) {
+    uint64_t v[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) v[j] = 0;
+    int e = 0;
+    for (; e + 4 <= E; e += 4) {
+      float s0 = sT[(size_t)e * T + t], s1 = sT[(size_t)(e + 1) * T + t];
+      float s2 = sT[(size_t)(e + 2) * T + t], s3 = sT[(size_t)(e + 3) * T + t];
+      insert_top<L>(v, rank_key(s0 - ps[e], e));
+      insert_top<L>(v, rank_key(s1 - ps[e + 1], e + 1));
+      insert_top<L>(v, rank_key(s2 - ps[e + 2], e + 2));
+      insert_top<L>(v, rank_key(s3 - ps[e + 3], e + 3));
+    }
+    for (; e < E; ++e) insert_top<L>(v, rank_key(sT[(size_t)e * T + t] - ps[e], e));
+    const uint64_t kth = pick<L>(v, k - 1);
+    const float kap1 = key_f32((uint32_t)(kth >> 32));
+    const float kap2 = (k < E) ? key_f32((uint32_t)(pick<L>(v, k) >> 32)) : -INFINITY;
+    // routing and softmax gate weights over the raw logits of the chosen
+    float mx = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+      if (j < k) mx = fmaxf(mx, logits[(size_t)t * E + key_expert(v[j])]);
+    float ex[L];
+    float den = 0.0f;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      ex[j] = 0.0f;
+      if (j < k) {
+        ex[j] = expf(logits[(size_t)t * E + key_expert(v[j])] - mx);
+        den = den + ex[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      if (j < k) {
+        int ej = key_expert(v[j]);
+        idx[(size_t)t * k + j] = ej;
+        w[(size_t)t * k + j] = ex[j] / den;
+        atomicAdd(&hist[ej], 1);
+      }
+    }
+    // margins m = s - (held ? kappa2 : kappa1), stored as sortable keys
+    for (e = 0; e < E; ++e) {
+      float s = sT[(size_t)e * T + t];
+      bool held = rank_key(s - ps[e], e) >= kth;
+      float m = s - (held ? kap2 : kap1);
+      mT[(size_t)e * T + t] = f32_key(m);
+    }
+  }
+  __syncthreads();
+  int32_t* lb = loadbuf + (it & 1) * E;
+  for (int e = tid; e < E; e += RANK_THREADS)
+    if (hist[e]) atomicAdd(&lb[e], hist[e]);
+}
+
+// ------------------------------------------------ block radix selection
+// r-th largest (1-based) key among the items i in [0, n) for which get(i,
+// key) is true.  Digits of 11, 11 and 10 bits, a 2048-bin LDS histogram
+// per pass.  Requires 1 <= r <= number of such items.  Returns the key and
+// writes the number of items with a strictly larger key to *greater.
+
+struct SelScratch {
+  uint32_t hist[2048];
+  int pick_digit;
+  uint32_t pick_above;
+};
+
+template <typename Get>
+__device__ uint32_t block_select_rth(int n, int r, Get get, SelScratch& sc, int* greater) {
+  const int tid = threadIdx.x, bd = blockDim.x;
+  uint32_t prefix = 0, mask = 0;
+  int rr = r;
+#pragma unroll 1
+  for (int pass = 0; pass < 3; ++pass) {
+    const int sh = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+    const uint32_t dm = pass == 2 ? 1023u : 2047u;
+    for (int i = tid; i < 2048; i += bd) sc.hist[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += bd) {
+      uint32_t key;
+      if (get(i, key) && (key & mask) == prefix) atomicAdd(&sc.hist[(key >> sh) & dm], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int l = tid;
+      uint32_t sum = 0;
+      for (int j = 0; j < 32; ++j) sum += sc.hist[l * 32 + ((j + l) & 31)];
+      uint32_t suf = sum;
+      for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_down(suf, off, 64);
+        if (l + off < 64) suf += o;
+      }
+      const uint32_t above = suf - sum;
+      if (above < (uint32_t)rr && (uint32_t)rr <= suf) {
+        uint32_t acc = above;
+        for (int j = 31; j >= 0; --j) {
+          uint32_t h = sc.hist[l * 32 + j];
+          if (acc + h >= (uint32_t)rr) {
+            sc.pick_digit = l * 32 + j;
+            sc.pick_above = acc;
+            break;
+          }
+          acc += h;
+        }
+      }
+    }
+    __syncthreads();
+    const int dsel = sc.pick_digit;
+    const uint32_t above = sc.pick_above;
+    __syncthreads();
+    rr -= (int)above;
+    prefix |= (uint32_t)dsel << sh;
+    mask |= dm << sh;
+  }
+  *greater = r - rr;
+  return prefix;
+}
+
+__device__ int block_sum(int v, int* red) {
+  // red: LDS int[32]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_down(v, off, 64);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  int tot = 0;
+  for (int i = 0; i < nw; ++i) tot += red[i];
+  __syncthreads();
+  return tot;
+}
+
+// Exclusive prefix count of ``flag`` over the threads of the block, in
+// thread order; *total receives the block total.
+__device__ int block_excl_scan(int flag, int* red, int* total) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (blockDim.x + 63) >> 6;
+  uint64_t bal = __ballot(flag);
+  int in_wave = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+  __syncthreads();
+  if (lane == 0) red[wv] = __popcll(bal);
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    if (i < wv) before += red[i];
+    tot += red[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return before + in_wave;
+}
+
+// --------------------------------------------------------- price update
+// One block per expert.  All blocks first agree, from the loads of this
+// iteration, whether the loop ends here; block 0 then records the outcome.
+
+__global__ __launch_bounds__(SEL_THREADS) void acp_select(
+    const uint32_t* __restrict__ mT, float* __restrict__ price, int T, int E, int C, int it,
+    int max_iters, int32_t* __restrict__ state, int32_t* __restrict__ loadbuf,
+    int32_t* __restrict__ load_out) {
+  if (state[ST_DONE]) return;
+  __shared__ SelScratch sc;
+  __shared__ int red[32];
+  const int tid = threadIdx.x;
+  const int32_t* ld = loadbuf + (it & 1) * E;
+  int over = 0, excess = 0;
+  for (int e = tid; e < E; e += SEL_THREADS) {
+    int x = ld[e] - C;
+    if (x > 0) {
+      over = 1;
+      excess += x;
+    }
+  }
+  const int n_over = block_sum(over, red);
+  const int e = blockIdx.x;
+  if (n_over == 0 || it >= max_iters) {
+    if (e == 0) {
+      const int tot_excess = block_sum(excess, red);
+      for (int i = tid; i < E; i += SEL_THREADS) load_out[i] = ld[i];
+      if (tid == 0) {
+        state[ST_ITERS] = it;
+        state[ST_CONVERGED] = n_over == 0;
+        state[ST_OVERFLOW] = tot_excess;
+        state[ST_NEED_REPAIR] = n_over != 0;
+        state[ST_DONE] = 1;
+      }
+    }
+    return;
+  }
+  if (e == 0)
+    for (int i = tid; i < E; i += SEL_THREADS) loadbuf[((it + 1) & 1) * E + i] = 0;
+  if (ld[e] <= C) return;
+  const uint32_t* col = mT + (size_t)e * T;
+  int greater;
+  uint32_t q = block_select_rth(
+      T, C + 1,
+      [&](int i, uint32_t& key) {
+        key = col[i];
+        return true;
+      },
+      sc, &greater);
+  if (tid == 0) {
+    const float eps = __int_as_float(state[ST_EPS]);
+    const float qf = key_f32(q);
+    const float cand = nextafterf(qf, INFINITY) + eps;
+    const float old = price[e];
+    price[e] = cand > old ? cand : old;
+  }
+}
+
+// ----------------------------------------------------- capacity repair
+// Single block; runs only when the price loop ended with an overloaded
+// expert.  Bitmasks of W = ceil(E/32) words per token live in the workspace.
+
+struct RepairLds {
+  SelScratch sc;
+  int load[MOE_MAX_E];
+  int props[MOE_MAX_E];
+  int red[32];
+  int flag;
+};
+
+template <int L>
+__global__ __launch_bounds__(REP_THREADS) void capacity_repair(
+    const float* __restrict__ sT, const float* __restrict__ logits,
+    const float* __restrict__ price, int T, int E, int k, int C, int32_t* __restrict__ state,
+    int32_t* __restrict__ idx, float* __restrict__ w, int32_t* __restrict__ load_out,
+    uint32_t* __restrict__ held, uint32_t* __restrict__ tried, uint32_t* __restrict__ prop,
+    int32_t* __restrict__ missing) {
+  if (!state[ST_NEED_REPAIR] || state[ST_STATUS] != MOE_OK) return;
+  __shared__ RepairLds S;
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const int W = (E + 31) >> 5;
+  auto keyof = [&](int t, int e) -> uint32_t { return f32_key(sT[(size_t)e * T + t] - price[e]); };
+  auto has = [&](const uint32_t* m, int t, int e) -> bool {
+    return (m[(size_t)t * W + (e >> 5)] >> (e & 31)) & 1u;
+  };
+  for (int e = tid; e < E; e += bd) {
+    S.load[e] = 0;
+    S.props[e] = 0;
+  }
+  __syncthreads();
+  for (int t = tid; t < T; t += bd) {
+    for (int j = 0; j < W; ++j) {
+      held[(size_t)t * W + j] = 0;
+      prop[(size_t)t * W + j] = 0;
+    }
+    for (int j = 0; j < k; ++j) {
+      int e = idx[(size_t)t * k + j];
+      held[(size_t)t * W + (e >> 5)] |= 1u << (e & 31);
+      atomicAdd(&S.load[e], 1);
+    }
+    for (int j = 0; j < W; ++j) tried[(size_t)t * W + j] = held[(size_t)t * W + j];
+    missing[t] = 0;
+  }
+  __syncthreads();
+  // 1) overloaded experts keep their C best holders (key desc, token asc)
+  for (int e = 0; e < E; ++e) {
+    if (S.load[e] <= C) continue;
+    int greater;
+    uint32_t kstar = block_select_rth(
+        T, C,
+        [&](int t, uint32_t& key) {
+          if (!has(held, t, e)) return false;
+          key = keyof(t, e);
+          return true;
+        },
+        S.sc, &greater);
+    const int need = C - greater;
+    int run = 0;
+    for (int t0 = 0; t0 < T; t0 += bd) {
+      const int t = t0 + tid;
+      bool h = t < T && has(held, t, e);
+      uint32_t key = h ? keyof(t, e) : 0u;
+      int tot;
+      int rank = block_excl_scan(h && key == kstar, S.red, &tot);
+      if (h && !(key > kstar || (key == kstar && run + rank < need))) {
+        held[(size_t)t * W + (e >> 5)] &= ~(1u << (e & 31));
+        missing[t] += 1;
+      }
+      run += tot;
+    }
+    __syncthreads();
+    if (tid == 0) S.load[e] = C;
+    __syncthreads();
+  }
+  // 2) proposal rounds
+  int rounds = 0;
+  for (;;) {
+    if (tid == 0) S.flag = 0;
+    for (int e = tid; e < E; e += bd) S.props[e] = 0;
+    __syncthreads();
+    int short_tokens = 0;
+    for (int t = tid; t < T; t += bd) {
+      int need = missing[t];
+      if (need == 0) continue;
+      short_tokens = 1;
+      for (int q = 0; q < need; ++q) {
+        uint64_t best = 0;
+        for (int e = 0; e < E; ++e) {
+          if (has(tried, t, e)) continue;
+          uint64_t rk = ((uint64_t)keyof(t, e) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)e);
+          if (rk > best) best = rk;
+        }
+        if (best == 0) {
+          atomicOr(&S.flag, 1);
+          break;
+        }
+        int e = key_expert(best);
+        tried[(size_t)t * W + (e >> 5)] |= 1u << (e & 31);
+        prop[(size_t)t * W + (e >> 5)] |= 1u << (e & 31);
+        atomicAdd(&S.props[e], 1);
+      }
+    }
+    const int any_short = block_sum(short_tokens, S.red);
+    if (S.flag) {
+      if (tid == 0) state[ST_STATUS] = MOE_ECAPACITY;
+      break;
+    }
+    if (any_short == 0) break;
+    ++rounds;
+    for (int e = 0; e < E; ++e) {
+      const int P = S.props[e];
+      if (P == 0) continue;
+      const int room = C - S.load[e];
+      uint32_t kstar = 0;
+      int need = 0;
+      bool all = P <= room;
+      if (!all && room > 0) {
+        int greater;
+        kstar = block_select_rth(
+            T, room,
+            [&](int t, uint32_t& key) {
+              if (!has(prop, t, e)) return false;
+              key = keyof(t, e);
+              return true;
+            },
+            S.sc, &greater);
+        need = room - greater;
+      }
+      int run = 0, accepted = 0;
+      for (int t0 = 0; t0 < T; t0 += bd) {
+        const int t = t0 + tid;
+        bool p = t < T && has(prop, t, e);
+        uint32_t key = p ? keyof(t, e) : 0u;
+        int tot;
+        int rank = block_excl_scan(p && key == kstar, S.red, &tot);
+        bool acc = p && room > 0 && (all || key > kstar || (key == kstar && run + rank < need));
+        if (p) prop[(size_t)t * W + (e >> 5)] &= ~(1u << (e & 31));
+        if (acc) {
+          held[(size_t)t * W + (e >> 5)] |= 1u << (e & 31);
+          missing[t] -= 1;
+        }
+        accepted += acc;
+        run += tot;
+      }
+      const int acc_tot = block_sum(accepted, S.red);
+      if (tid == 0) S.load[e] += acc_tot;
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // 3) rebuild every token's list in rank order, and its gate weights
+  if (state[ST_STATUS] == MOE_OK) {
+    for (int e = tid; e < E; e += bd) S.load[e] = 0;
+    __syncthreads();
+    for (int t = tid; t < T; t += bd) {
+      uint64_t v[L];
+#pragma unroll
+      for (int j = 0; j < L; ++j) v[j] = 0;
+      for (int e = 0; e < E; ++e)
+        if (has(held, t, e))
+          insert_top<L>(v, ((uint64_t)keyof(t, e) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)e));
+      float mx = -INFINITY;
+#pragma unroll
+      for (int j = 0; j < L; ++j)
+        if (j < k) mx = fmaxf(mx, logits[(size_t)t * E + key_expert(v[j])]);
+      float ex[L];
+      float den = 0.0f;
+#pragma unroll
+      for (int j = 0; j < L; ++j) {
+        ex[j] = 0.0f;
+        if (j < k) {
+          ex[j] = expf(logits[(size_t)t * E + key_expert(v[j])] - mx);
+          den = den + ex[j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < L; ++j)
+        if (j < k) {
+          int ej = key_expert(v[j]);
+          idx[(size_t)t * k + j] = ej;
+          w[(size_t)t * k + j] = ex[j] / den;
+          atomicAdd(&S.load[ej], 1);
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < E; e += bd) load_out[e] = S.load[e];
+  }
+  if (tid == 0) {
+    state[ST_ROUNDS] = rounds;
+    state[ST_REPAIRED] = 1;
+  }
+}
+
+__global__ void route_finalize(const int32_t* state, int32_t* info, int32_t* load_out, int E,
+                               int empty) {
+  const int tid = threadIdx.x;
+  if (empty)
+    for (int e = tid; e < E; e += blockDim.x) load_out[e] = 0;
+  if (tid == 0) {
+    info[MOE_INFO_ITERS] = state[ST_ITERS];
+    info[MOE_INFO_CONVERGED] = empty ? 1 : state[ST_CONVERGED];
+    info[MOE_INFO_OVERFLOW] = state[ST_OVERFLOW];
+    info[MOE_INFO_STATUS] = state[ST_STATUS];
+    info[MOE_INFO_ROUNDS] = state[ST_ROUNDS];
+    info[MOE_INFO_SIGMA] = state[ST_SIGMA];
+    info[MOE_INFO_EPS] = state[ST_EPS];
+    info[MOE_INFO_REPAIRED] = state[ST_REPAIRED];
+  }
+}
+
+struct RouteWs {
+  float* sT;
+  uint32_t* mT;
+  int32_t* state;
+  int32_t* loadbuf;
+  double* part;
+  uint32_t *held, *tried, *prop;
+  int32_t* missing;
+};
+
+RouteWs carve_route(const moe_cfg& c, void* base, size_t* total) {
+  WsCarve wc{(char*)base, 0};
+  RouteWs r;
+  const size_t T = (size_t)c.T, E = (size_t)c.E;
+  const size_t W = (E + 31) / 32;
+  const size_t nb = (T + SIG_BLOCK - 1) / SIG_BLOCK;
+  r.sT = wc.take<float>(T * E);
+  r.mT = wc.take<uint32_t>(T * E);
+  r.state = wc.take<int32_t>(ST_LEN);
+  r.loadbuf = wc.take<int32_t>(2 * E);
+  r.part = wc.take<double>(2 * (nb > 0 ? nb : 1));
+  r.held = wc.take<uint32_t>(T * W);
+  r.tried = wc.take<uint32_t>(T * W);
+  r.prop = wc.take<uint32_t>(T * W);
+  r.missing = wc.take<int32_t>(T);
+  if (total) *total = align_up(wc.off, 256);
+  return r;
+}
+
+template <int L>
+void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float* logits,
+                               float* price, int32_t* idx, float* w, int32_t* load,
+                               int max_iters, hipStream_t st) {
+  const int T = c.T, E = c.E, k = c.k, C = c.capacity;
+  const int nblk = (T + RANK_THREADS - 1) / RANK_THREADS;
+  for (int it = 0; it <= max_iters; ++it) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L>), dim3(nblk), dim3(RANK_THREADS), 0, st,
+                       ws.sT, logits, price, T, E, k, it, ws.state, ws.mT, idx, w, ws.loadbuf);
+    hipLaunchKernelGGL(acp_select, dim3(E), dim3(SEL_THREADS), 0, st, ws.mT, price, T, E, C, it,
+                       max_iters, ws.state, ws.loadbuf, load);
+  }
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(capacity_repair<L>), dim3(1), dim3(REP_THREADS), 0, st,
+                     ws.sT, logits, price, T, E, k, C, ws.state, idx, w, load, ws.held, ws.tried,
+                     ws.prop, ws.missing);
+}
+
+}  // namespace
+
+size_t route_ws_bytes(const moe_cfg& c) {
+  size_t total = 0;
+  carve_route(c, nullptr, &total);
+  return total;
+}
+
+extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* Wr,
+                                const float* br, float* logits, float* price, int32_t* topk_idx,
+                                float* topk_w, int32_t* load, int32_t* info, void* ws,
+                                size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.price_mode < MOE_PRICE_NONE || c.price_mode > MOE_PRICE_WARM) return MOE_EINVAL;
+  if (c.max_iters < 0) return MOE_EINVAL;
+  if (!price || !load || !info) return MOE_EINVAL;
+  if (c.T > 0 && (!X || !Wr || !br || !logits || !topk_idx || !topk_w)) return MOE_EINVAL;
+  if (!aligned(X, 16) || !aligned(Wr, 4) || !aligned(br, 4) || !aligned(logits, 4) ||
+      !aligned(price, 4) || !aligned(topk_idx, 4) || !aligned(topk_w, 4) || !aligned(load, 4) ||
+      !aligned(info, 4))
+    return MOE_EINVAL;
+  if (ws_bytes < route_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  RouteWs w = carve_route(c, ws, nullptr);
+  hipLaunchKernelGGL(route_init, dim3(1), dim3(256), 0, st, w.state, w.loadbuf, c.E, price,
+                     c.price_mode, c.warm_gamma);
+  if (c.T == 0) {
+    hipLaunchKernelGGL(route_finalize, dim3(1), dim3(256), 0, st, w.state, info, load, c.E, 1);
+    MOE_LAUNCH_CHECK();
+    return MOE_OK;
+  }
+  dim3 g((c.T + 63) / 64, (c.E + 63) / 64);
+  PROF_BEGIN("router_logits", st);
+  if (c.act == MOE_F32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits<float>), g, dim3(256), 0, st,
+                       (const float*)X, Wr, br, logits, w.sT, c.T, c.d, c.E);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits<bf16_t>), g, dim3(256), 0, st,
+                       (const bf16_t*)X, Wr, br, logits, w.sT, c.T, c.d, c.E);
+  PROF_END("router_logits", st);
+  const int nb = (c.T + SIG_BLOCK - 1) / SIG_BLOCK;
+  hipLaunchKernelGGL(score_partials, dim3(nb), dim3(SIG_BLOCK), 0, st, w.sT, c.T, c.E, w.part);
+  hipLaunchKernelGGL(score_sigma, dim3(1), dim3(SIG_BLOCK), 0, st, w.part, nb,
+                     (double)c.T * (double)c.E, w.state);
+  const int iters =
+      (c.price_mode == MOE_PRICE_ACP || c.price_mode == MOE_PRICE_WARM) ? c.max_iters : 0;
+  const int L = c.k + 1;
+  PROF_BEGIN("price_loop", st);
+  if (L <= 3)
+    launch_rank_select_repair<3>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
+  else if (L <= 5)
+    launch_rank_select_repair<5>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
+  else if (L <= 9)
+    launch_rank_select_repair<9>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
+  else
+    launch_rank_select_repair<17>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
+  PROF_END("price_loop", st);
+  hipLaunchKernelGGL(route_finalize, dim3(1), dim3(64), 0, st, w.state, info, load, c.E, 0);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}

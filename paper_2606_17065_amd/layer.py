@@ -1,0 +1,118 @@
+"""Torch-facing wrappers over the C ABI: allocate outputs, pass pointers and
+the current stream, raise on a bad status.  Every step of the layer runs in
+libmoe's HIP kernels; torch only supplies device memory and the stream.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+_DT = {L.MOE_F32: torch.float32, L.MOE_BF16: torch.bfloat16, L.MOE_FP8E4M3: torch.uint8}
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def _need(t, name, dtype, shape=None):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Workspace:
+    """One device buffer of moe_workspace_bytes(cfg), grown on demand."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, cfg, device) -> torch.Tensor:
+        n = max(L.moe_workspace_bytes(cfg), 256)
+        if self.buf is None or self.buf.numel() < n or self.buf.device != device:
+            self.buf = torch.empty(n, dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_WS = Workspace()
+
+
+def route(cfg, X, Wr, br, price=None, ws=None):
+    T, d, E, k = cfg.T, cfg.d, cfg.E, cfg.k
+    _need(X, "X", _DT[cfg.act], (T, d))
+    _need(Wr, "Wr", torch.float32, (E, d))
+    _need(br, "br", torch.float32, (E,))
+    dev = X.device
+    if price is None:
+        price = torch.zeros(E, dtype=torch.float32, device=dev)
+    else:
+        _need(price, "price", torch.float32, (E,))
+    out = dict(
+        logits=torch.empty(T, E, dtype=torch.float32, device=dev), price=price,
+        idx=torch.empty(T, k, dtype=torch.int32, device=dev),
+        w=torch.empty(T, k, dtype=torch.float32, device=dev),
+        load=torch.empty(E, dtype=torch.int32, device=dev),
+        info=torch.zeros(L.INFO_LEN, dtype=torch.int32, device=dev))
+    ws = _WS.get(cfg, dev) if ws is None else ws
+    L.moe_route(cfg, _p(X), _p(Wr), _p(br), _p(out["logits"]), _p(price), _p(out["idx"]),
+                _p(out["w"]), _p(out["load"]), _p(out["info"]), _p(ws), ws.numel(), _stream())
+    return out
+
+
+def dispatch(cfg, X, idx, ws=None):
+    T, d, E, k = cfg.T, cfg.d, cfg.E, cfg.k
+    _need(X, "X", _DT[cfg.act], (T, d))
+    _need(idx, "topk_idx", torch.int32, (T, k))
+    dev = X.device
+    out = dict(offsets=torch.empty(E + 1, dtype=torch.int32, device=dev),
+               row_map=torch.empty(T * k, dtype=torch.int32, device=dev),
+               inv_map=torch.empty(T, k, dtype=torch.int32, device=dev),
+               X_perm=torch.empty(T * k, d, dtype=X.dtype, device=dev))
+    ws = _WS.get(cfg, dev) if ws is None else ws
+    L.moe_dispatch(cfg, _p(X), _p(idx), _p(out["offsets"]), _p(out["row_map"]),
+                   _p(out["inv_map"]), _p(out["X_perm"]), _p(ws), ws.numel(), _stream())
+    return out
+
+
+def expert_ffn(cfg, X_perm, offsets, W13, W2, W13_scale=None, W2_scale=None, ws=None):
+    N, d, E, f = cfg.T * cfg.k, cfg.d, cfg.E, cfg.d_ff
+    _need(X_perm, "X_perm", _DT[cfg.act], (N, d))
+    _need(offsets, "offsets", torch.int32, (E + 1,))
+    _need(W13, "W13", _DT[cfg.w], (E, 2 * f, d))
+    _need(W2, "W2", _DT[cfg.w], (E, d, f))
+    Y = torch.empty(N, d, dtype=X_perm.dtype, device=X_perm.device)
+    ws = _WS.get(cfg, X_perm.device) if ws is None else ws
+    L.moe_expert_ffn(cfg, _p(X_perm), _p(offsets), _p(W13), _p(W13_scale), _p(W2), _p(W2_scale),
+                     _p(Y), _p(ws), ws.numel(), _stream())
+    return Y
+
+
+def combine(cfg, Y, inv_map, w):
+    T, d, k = cfg.T, cfg.d, cfg.k
+    _need(Y, "Y", _DT[cfg.act], (T * k, d))
+    _need(inv_map, "inv_map", torch.int32, (T, k))
+    _need(w, "topk_w", torch.float32, (T, k))
+    out = torch.empty(T, d, dtype=Y.dtype, device=Y.device)
+    L.moe_combine(cfg, _p(Y), _p(inv_map), _p(w), _p(out), _stream())
+    return out
+
+
+def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None):
+    """The whole layer forward; returns every intermediate."""
+    r = route(cfg, X, Wr, br, price)
+    dsp = dispatch(cfg, X, r["idx"])
+    Y = expert_ffn(cfg, dsp["X_perm"], dsp["offsets"], W13, W2, W13_scale, W2_scale)
+    out = combine(cfg, Y, dsp["inv_map"], r["w"])
+    r.update(dsp)
+    r["Y"] = Y
+    r["out"] = out
+    return r

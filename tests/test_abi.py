@@ -1,0 +1,95 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/moe.h declares, and rejects bad arguments before launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2606_17065_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(moe_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = _declared()
+    assert "moe_route" in names and "moe_combine" in names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_the_header():
+    bound = set(L.SIGNATURES) | {"moe_strerror"}
+    assert _declared() <= bound
+
+
+def test_strerror_texts():
+    assert L.strerror(0) == "ok"
+    assert "infeasible" in L.strerror(L.MOE_EINFEASIBLE)
+    assert L.strerror(12345) == "unknown status"
+
+
+def _cfg(**kw):
+    base = dict(T=512, d=128, E=8, k=2, d_ff=256, capacity=160, max_iters=50,
+                act=L.MOE_F32, w=L.MOE_F32, price_mode=L.MOE_PRICE_ACP)
+    base.update(kw)
+    return L.make_cfg(**base)
+
+
+def test_workspace_bytes_and_shape_checks():
+    n = L.moe_workspace_bytes(_cfg())
+    assert n > 512 * 8 * 4 * 2  # transposed logits and margin keys at least
+    with pytest.raises(L.MoEError) as e:
+        L.moe_workspace_bytes(_cfg(k=9))
+    assert e.value.status == L.MOE_EINFEASIBLE
+    with pytest.raises(L.MoEError) as e:
+        L.moe_workspace_bytes(_cfg(capacity=127))  # 8*127 < 512*2
+    assert e.value.status == L.MOE_EINFEASIBLE
+    with pytest.raises(L.MoEError) as e:
+        L.moe_workspace_bytes(_cfg(d=100))
+    assert e.value.status == L.MOE_EUNSUPPORTED
+    with pytest.raises(L.MoEError) as e:
+        L.moe_workspace_bytes(_cfg(act=7))
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:
+        L.moe_workspace_bytes(_cfg(E=2000, capacity=100))
+    assert e.value.status == L.MOE_EUNSUPPORTED
+
+
+def test_entry_points_reject_bad_arguments_on_the_host():
+    cfg = _cfg()
+    fake = 1 << 20  # never dereferenced: every call below fails its host checks
+    with pytest.raises(L.MoEError) as e:
+        L.moe_route(cfg, None, fake, fake, fake, fake, fake, fake, fake, fake, fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:
+        L.moe_route(cfg, fake + 4, fake, fake, fake, fake, fake, fake, fake, fake, fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL  # X misaligned
+    with pytest.raises(L.MoEError) as e:
+        L.moe_route(cfg, fake, fake, fake, fake, fake, fake, fake, fake, fake, fake, 16, None)
+    assert e.value.status == L.MOE_EWORKSPACE
+    bad = _cfg(price_mode=9)
+    with pytest.raises(L.MoEError) as e:
+        L.moe_route(bad, fake, fake, fake, fake, fake, fake, fake, fake, fake, fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:
+        L.moe_dispatch(cfg, fake, fake, fake, fake, fake, fake, fake, 0, None)
+    assert e.value.status == L.MOE_EWORKSPACE
+    with pytest.raises(L.MoEError) as e:
+        L.moe_expert_ffn(_cfg(act=L.MOE_F32, w=L.MOE_BF16), fake, fake, fake, None, fake, None, fake,
+                         fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EUNSUPPORTED
+    with pytest.raises(L.MoEError) as e:
+        L.moe_combine(cfg, None, fake, fake, fake, None)
+    assert e.value.status == L.MOE_EINVAL
