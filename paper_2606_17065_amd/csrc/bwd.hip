@@ -1,0 +1,249 @@
+// Backward of the layer with the routing held fixed, for gfx950 (the
+// expert-GEMM part lives in gemm.hip).  No floating-point atomics: every
+// reduction has one owner thread and a fixed order, so repeated calls are
+// bit-identical.
+//
+//   combine:   dY[slot(t,j)] = w_tj * dOut_t,  dw_tj = <dOut_t, Y[slot(t,j)]>
+//   dispatch:  dX_t = sum_j dX_perm[slot(t,j)]            (j order)
+//   gate:      ds_tj = w_tj (dw_tj - sum_i w_ti dw_ti)     (softmax over the
+//              chosen experts; no gradient into prices or the selection)
+//   router:    dX_t += sum_j ds_tj W_r[e_j];  dW_r[e] = sum over the slots of
+//              e (token order) of ds * X_t;  db_r[e] = sum of the same ds.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// One wavefront per token: dw by a fixed-order dot product (lane partials in
+// ascending column order, then a fixed butterfly), dY rows scaled by w.
+template <typename TA>
+__global__ __launch_bounds__(256) void combine_bwd_kernel(const TA* __restrict__ dOut,
+                                                          const TA* __restrict__ Y, int T, int d,
+                                                          int k, const int32_t* __restrict__ inv_map,
+                                                          const float* __restrict__ w,
+                                                          TA* __restrict__ dY,
+                                                          float* __restrict__ dw) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= T) return;
+  const int N = T * k;
+  for (int j = 0; j < k; ++j) {
+    const int slot = clampi(inv_map[(size_t)t * k + j], 0, N - 1);
+    const float wj = w[(size_t)t * k + j];
+    float part = 0.0f;
+    for (int c0 = lane * 8; c0 < d; c0 += 64 * 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float g = ActIO<TA>::ld(dOut, (size_t)t * d + c0 + i);
+        part = __builtin_fmaf(g, ActIO<TA>::ld(Y, (size_t)slot * d + c0 + i), part);
+        ActIO<TA>::st(dY, (size_t)slot * d + c0 + i, wj * g);
+      }
+    }
+    for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
+    if (lane == 0) dw[(size_t)t * k + j] = part;
+  }
+}
+
+// dX_t = sum_j dX_perm[slot(t,j)] + sum_j ds_tj W_r[e_j] (FP32 out).  The
+// second sum is the router backward into the tokens; ds is formed here from
+// w and dw.  One wavefront per token.
+template <typename TA>
+__global__ __launch_bounds__(256) void dispatch_bwd_kernel(
+    const TA* __restrict__ dXp, int T, int d, int k, int E, const int32_t* __restrict__ inv_map,
+    const int32_t* __restrict__ idx, const float* __restrict__ w, const float* __restrict__ dw,
+    const float* __restrict__ Wr, float* __restrict__ dX, float* __restrict__ ds_out) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= T) return;
+  const int N = T * k;
+  int slots[MOE_MAX_K], ex[MOE_MAX_K];
+  float ds[MOE_MAX_K];
+  float sw = 0.0f;
+#pragma unroll
+  for (int j = 0; j < MOE_MAX_K; ++j)
+    if (j < k) sw = sw + w[(size_t)t * k + j] * dw[(size_t)t * k + j];
+#pragma unroll
+  for (int j = 0; j < MOE_MAX_K; ++j) {
+    slots[j] = j < k ? clampi(inv_map[(size_t)t * k + j], 0, N - 1) : 0;
+    ex[j] = j < k ? clampi(idx[(size_t)t * k + j], 0, E - 1) : 0;
+    ds[j] = j < k ? w[(size_t)t * k + j] * (dw[(size_t)t * k + j] - sw) : 0.0f;
+  }
+  if (ds_out && lane < k) {
+#pragma unroll
+    for (int j = 0; j < MOE_MAX_K; ++j)
+      if (j == lane) ds_out[(size_t)t * k + j] = ds[j];
+  }
+  for (int c0 = lane * 4; c0 < d; c0 += 64 * 4) {
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < MOE_MAX_K; ++j) {
+      if (j < k) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = acc[i] + ActIO<TA>::ld(dXp, (size_t)slots[j] * d + c0 + i);
+      }
+    }
+    if (Wr) {
+#pragma unroll
+      for (int j = 0; j < MOE_MAX_K; ++j) {
+        if (j < k) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            acc[i] = __builtin_fmaf(ds[j], Wr[(size_t)ex[j] * d + c0 + i], acc[i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dX[(size_t)t * d + c0 + i] = acc[i];
+  }
+}
+
+// dW_r[e, c] = sum over the slots r of expert e (slot order) of
+// ds(slot) * X[row_map[r], c];  db_r[e] = sum of ds(slot).  Block = (expert,
+// 256 columns); each thread owns one column and walks the expert's slots.
+template <typename TA>
+__global__ __launch_bounds__(256) void router_wgrad_kernel(
+    const TA* __restrict__ X, int T, int d, int k, int E, const int32_t* __restrict__ row_map,
+    const int32_t* __restrict__ offsets, const int32_t* __restrict__ slot_src,
+    const float* __restrict__ ds_tk, float* __restrict__ dWr, float* __restrict__ dbr) {
+  const int e = blockIdx.x;
+  const int c = blockIdx.y * 256 + threadIdx.x;
+  const int N = T * k;
+  const int r0 = clampi(offsets[e], 0, N), r1 = clampi(offsets[e + 1], r0, N);
+  float acc = 0.0f, accb = 0.0f;
+  for (int r = r0; r < r1; ++r) {
+    const float g = ds_tk[clampi(slot_src[r], 0, N - 1)];
+    const int t = clampi(row_map[r], 0, T - 1);
+    if (c < d) acc = __builtin_fmaf(g, ActIO<TA>::ld(X, (size_t)t * d + c), acc);
+    accb = accb + g;
+  }
+  if (c < d) dWr[(size_t)e * d + c] = acc;
+  if (blockIdx.y == 0 && threadIdx.x == 0) dbr[e] = accb;
+}
+
+// slot_src[inv_map[t,j]] = t*k + j: the (token, choice) behind each slot.
+__global__ __launch_bounds__(256) void slot_source(const int32_t* __restrict__ inv_map, int N,
+                                                   int32_t* __restrict__ slot_src) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < N) slot_src[clampi(inv_map[i], 0, N - 1)] = i;
+}
+
+struct RouteBwdWs {
+  int32_t* slot_src;
+  float* ds;
+};
+
+RouteBwdWs carve_route_bwd(const moe_cfg& c, void* base, size_t* total) {
+  WsCarve wc{(char*)base, 0};
+  RouteBwdWs r;
+  const size_t N = (size_t)c.T * c.k;
+  r.slot_src = wc.take<int32_t>(N > 0 ? N : 1);
+  r.ds = wc.take<float>(N > 0 ? N : 1);
+  if (total) *total = align_up(wc.off, 256);
+  return r;
+}
+
+}  // namespace
+
+size_t route_bwd_ws_bytes(const moe_cfg& c) {
+  size_t total = 0;
+  carve_route_bwd(c, nullptr, &total);
+  return total;
+}
+
+extern "C" moe_status moe_combine_bwd(const moe_cfg* cfg, const void* dOut, const void* Y,
+                                      const int32_t* inv_map, const float* topk_w, void* dY,
+                                      float* dtopk_w, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.T == 0) return MOE_OK;
+  if (!dOut || !Y || !inv_map || !topk_w || !dY || !dtopk_w) return MOE_EINVAL;
+  if (!aligned(dOut, 16) || !aligned(Y, 16) || !aligned(dY, 16) || !aligned(inv_map, 4) ||
+      !aligned(topk_w, 4) || !aligned(dtopk_w, 4))
+    return MOE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  PROF_BEGIN("combine_bwd", st);
+  if (c.act == MOE_F32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_bwd_kernel<float>), dim3((c.T + 3) / 4), dim3(256),
+                       0, st, (const float*)dOut, (const float*)Y, c.T, c.d, c.k, inv_map, topk_w,
+                       (float*)dY, dtopk_w);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_bwd_kernel<bf16_t>), dim3((c.T + 3) / 4), dim3(256),
+                       0, st, (const bf16_t*)dOut, (const bf16_t*)Y, c.T, c.d, c.k, inv_map,
+                       topk_w, (bf16_t*)dY, dtopk_w);
+  PROF_END("combine_bwd", st);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_dispatch_bwd(const moe_cfg* cfg, const void* dX_perm,
+                                       const int32_t* inv_map, float* dX, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.T == 0) return MOE_OK;
+  if (!dX_perm || !inv_map || !dX) return MOE_EINVAL;
+  if (!aligned(dX_perm, 16) || !aligned(dX, 16) || !aligned(inv_map, 4)) return MOE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  PROF_BEGIN("dispatch_bwd", st);
+  if (c.act == MOE_F32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float>), dim3((c.T + 3) / 4), dim3(256),
+                       0, st, (const float*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr, nullptr,
+                       nullptr, nullptr, dX, nullptr);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t>), dim3((c.T + 3) / 4), dim3(256),
+                       0, st, (const bf16_t*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr,
+                       nullptr, nullptr, nullptr, dX, nullptr);
+  PROF_END("dispatch_bwd", st);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const float* Wr,
+                                    const int32_t* topk_idx, const float* topk_w,
+                                    const float* dtopk_w, const int32_t* row_map,
+                                    const int32_t* offsets, const int32_t* inv_map,
+                                    const void* dX_perm, float* dX, float* dWr, float* dbr,
+                                    void* ws, size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (!dWr || !dbr || !offsets) return MOE_EINVAL;
+  if (c.T > 0 && (!X || !Wr || !topk_idx || !topk_w || !dtopk_w || !row_map || !inv_map ||
+                  !dX_perm || !dX))
+    return MOE_EINVAL;
+  if (!aligned(X, 16) || !aligned(dX_perm, 16) || !aligned(dX, 16) || !aligned(dWr, 4) ||
+      !aligned(dbr, 4) || !aligned(Wr, 4))
+    return MOE_EINVAL;
+  if (ws_bytes < route_bwd_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  RouteBwdWs w = carve_route_bwd(c, ws, nullptr);
+  const int N = c.T * c.k;
+  PROF_BEGIN("route_bwd", st);
+  if (c.T > 0) {
+    hipLaunchKernelGGL(slot_source, dim3((N + 255) / 256), dim3(256), 0, st, inv_map, N,
+                       w.slot_src);
+    if (c.act == MOE_F32)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float>), dim3((c.T + 3) / 4),
+                         dim3(256), 0, st, (const float*)dX_perm, c.T, c.d, c.k, c.E, inv_map,
+                         topk_idx, topk_w, dtopk_w, Wr, dX, w.ds);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t>), dim3((c.T + 3) / 4),
+                         dim3(256), 0, st, (const bf16_t*)dX_perm, c.T, c.d, c.k, c.E, inv_map,
+                         topk_idx, topk_w, dtopk_w, Wr, dX, w.ds);
+  }
+  dim3 g(c.E, (c.d + 255) / 256);
+  if (c.act == MOE_F32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_wgrad_kernel<float>), g, dim3(256), 0, st,
+                       (const float*)X, c.T, c.d, c.k, c.E, row_map, offsets, w.slot_src, w.ds, dWr,
+                       dbr);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_wgrad_kernel<bf16_t>), g, dim3(256), 0, st,
+                       (const bf16_t*)X, c.T, c.d, c.k, c.E, row_map, offsets, w.slot_src, w.ds,
+                       dWr, dbr);
+  PROF_END("route_bwd", st);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}

@@ -29,37 +29,59 @@ __global__ __launch_bounds__(TB) void dispatch_count(const int32_t* __restrict__
   for (int e = tid; e < E; e += TB) cnt[(size_t)blockIdx.x * E + e] = hist[e];
 }
 
-// One block of up to 1024 threads: thread e walks its expert's column of
-// block counts; then an exclusive scan over the expert totals.
+// One block of 1024 threads.  Thread (e, p) owns expert e and the p-th of
+// P = 1024 / E contiguous runs of token blocks: it sums its run, the runs of
+// an expert are scanned in order, the expert totals are scanned into
+// offsets, and each thread finally rewrites its run's counts as absolute
+// bases (offset of e + counts of all earlier blocks).
 __global__ __launch_bounds__(1024) void dispatch_scan(int32_t* __restrict__ cnt_base, int nb,
                                                       int E, int32_t* __restrict__ offsets) {
-  __shared__ int tot[MOE_MAX_E];
-  __shared__ int off[MOE_MAX_E + 1];
-  const int e = threadIdx.x;
+  __shared__ int runsum[1024];
+  __shared__ int tot[2][MOE_MAX_E];
+  const int tid = threadIdx.x;
+  const int P = 1024 / E;
+  const int e = tid % E, p = tid / E;
+  const bool own = p < P;
+  const int chunk = (nb + P - 1) / P;
+  const int b0 = own ? min(nb, p * chunk) : nb, b1 = own ? min(nb, b0 + chunk) : nb;
   int run = 0;
-  if (e < E) {
-    for (int b = 0; b < nb; ++b) {
-      int c = cnt_base[(size_t)b * E + e];
-      cnt_base[(size_t)b * E + e] = run;
-      run += c;
-    }
-    tot[e] = run;
+  for (int b = b0; b < b1; b += 8) {
+    int c[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = b + i < b1 ? cnt_base[(size_t)(b + i) * E + e] : 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) run += c[i];
   }
+  runsum[tid] = run;
   __syncthreads();
-  if (e == 0) {
-    int acc = 0;
-    for (int i = 0; i < E; ++i) {
-      off[i] = acc;
-      acc += tot[i];
+  int before = 0, total = 0;
+  if (own)
+    for (int q = 0; q < P; ++q) {
+      const int v = runsum[q * E + e];
+      if (q < p) before += v;
+      total += v;
     }
-    off[E] = acc;
-  }
+  if (own && p == 0) tot[0][e] = total;
   __syncthreads();
-  if (e < E) {
-    offsets[e] = off[e];
-    for (int b = 0; b < nb; ++b) cnt_base[(size_t)b * E + e] += off[e];
+  // inclusive scan of the expert totals (Hillis-Steele over E <= 1024)
+  int cur = 0;
+  for (int off = 1; off < E; off <<= 1) {
+    if (tid < E) tot[cur ^ 1][tid] = tot[cur][tid] + (tid >= off ? tot[cur][tid - off] : 0);
+    cur ^= 1;
+    __syncthreads();
   }
-  if (e == 0) offsets[E] = off[E];
+  if (own) {
+    const int incl = tot[cur][e];
+    const int off_e = incl - total;
+    if (p == 0) offsets[e] = off_e;
+    if (p == 0 && e == E - 1) offsets[E] = incl;
+    int acc = off_e + before;
+    for (int b = b0; b < b1; ++b) {
+      const int c = cnt_base[(size_t)b * E + e];
+      cnt_base[(size_t)b * E + e] = acc;
+      acc += c;
+    }
+  }
 }
 
 __global__ __launch_bounds__(TB) void dispatch_scatter(const int32_t* __restrict__ idx, int T,

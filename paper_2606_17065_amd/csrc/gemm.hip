@@ -55,6 +55,40 @@ __device__ __forceinline__ bool find_tile(const int32_t* __restrict__ tile_start
   return rows > 0;
 }
 
+// Logical tile order of the 256-row kernels: expert by expert; inside an
+// expert, groups of NG column tiles, and inside a group row tile by row
+// tile with the NG column tiles of a row tile adjacent.  A run of
+// consecutive tiles (what one XCD's CUs hold at once) then covers all row
+// tiles of an expert against a few weight slices, so both operands are
+// re-read from that XCD's L2 rather than from HBM.
+constexpr int NG = 4;
+
+__device__ __forceinline__ bool find_tile_grouped(const int32_t* __restrict__ tile_start,
+                                                  const int32_t* __restrict__ offsets, int E,
+                                                  int BMr, int N, int n_tiles, int Lt, int& e_out,
+                                                  int& row0, int& rows, int& nt) {
+  if (Lt >= tile_start[E] * n_tiles) return false;
+  int lo = 0, hi = E - 1;  // largest e with tile_start[e] * n_tiles <= Lt
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] * n_tiles <= Lt) lo = mid;
+    else hi = mid - 1;
+  }
+  const int mc = tile_start[lo + 1] - tile_start[lo];
+  const int local = Lt - tile_start[lo] * n_tiles;
+  const int g = local / (mc * NG);
+  const int rem = local - g * mc * NG;
+  const int ng = min(NG, n_tiles - g * NG);
+  const int mt = rem / ng;
+  nt = g * NG + (rem - mt * ng);
+  e_out = lo;
+  row0 = offsets[lo] + mt * BMr;
+  rows = min(BMr, offsets[lo + 1] - row0);
+  if (row0 < 0 || row0 >= N) return false;
+  rows = min(rows, N - row0);
+  return rows > 0;
+}
+
 // ---------------------------------------------------------------- BF16 MFMA
 // Block tile: 128 rows x 128 B-rows, K step 32; 4 wavefronts in 2 x 2, each
 // owning 64 rows x 64 B-rows as 2 x 2 tiles of v_mfma_f32_32x32x16_bf16.
@@ -163,6 +197,218 @@ __global__ __launch_bounds__(256) void gemm_bf16(const bf16_t* __restrict__ A,
   }
 }
 
+// ------------------------------------------------------- BF16 MFMA, 256x128
+// Macro tile 256 token rows x 128 weight rows, 4 wavefronts (2 x 2) each
+// owning 128 x 64 as 4 x 2 tiles of v_mfma_f32_32x32x16_bf16; two blocks
+// share a CU (LDS and registers are sized for it), so one block's
+// prologue, barriers and epilogue overlap the other's MFMA work.
+// Operands move HBM -> LDS with gfx950's direct-to-LDS loads
+// (global_load_lds_dwordx4: a wavefront instruction deposits 64 x 16 bytes
+// contiguously) through a ring of three K-steps of 32; no VGPRs are spent
+// on staging.  A stage holds 64 bytes per row; the 16-byte chunk c of row R
+// sits at position c ^ swz(R), which keeps the fragment reads of 8- and of
+// 16-lane groups on distinct LDS banks.  A lane loads the global chunk that
+// belongs at its fixed LDS slot.
+// The MFMA takes the weight fragment as its first operand, so each lane
+// ends up holding one token row and runs of 4 consecutive output columns;
+// the epilogue stages the tile through LDS and writes 16-byte row segments.
+// SwiGLU mode: weight rows 0..63 are W1 rows n0..n0+63, 64..127 the
+// matching W3 rows; a wavefront's column tiles 0 and 1 are the two halves
+// of the same 32 outputs.  Rows of a partial row tile load a clamped
+// (valid) row; their results are never stored.
+// Blocks are remapped so that each XCD (the hardware deals blocks to the 8
+// XCDs round-robin) walks a contiguous run of the grouped tile order.
+
+constexpr int GBM = 256, GBN = 128, GBK = 32, NSTAGE = 3;
+constexpr int STAGE_A = GBM * GBK * 2;   // bytes of the token operand in a stage
+constexpr int STAGE_B = GBN * GBK * 2;   // bytes of the weight operand
+constexpr int STAGE_BYTES = STAGE_A + STAGE_B;
+constexpr int EPI_BYTES = GBM * (128 + 8) * 2;
+constexpr int DMA_LDS = NSTAGE * STAGE_BYTES > EPI_BYTES ? NSTAGE * STAGE_BYTES : EPI_BYTES;
+constexpr int A_INS = GBM / 4 / 16;      // DMA instructions per wavefront per stage
+constexpr int B_INS = GBN / 4 / 16;
+constexpr int VM_PER_STAGE = A_INS + B_INS;
+
+__device__ __forceinline__ int swz(int R) { return ((R >> 1) ^ (R >> 2)) & 3; }
+
+// s_waitcnt vmcnt(n) lgkmcnt(0) (gfx9 encoding: vmcnt[3:0] in bits 3:0,
+// vmcnt[5:4] in bits 15:14, expcnt in 6:4 left at its maximum, lgkmcnt in
+// 11:8 = 0).
+#define WAIT_VM_LGKM0(n) __builtin_amdgcn_s_waitcnt((((n) & 15) | (((n) >> 4) << 14)) | (7 << 4))
+
+// Workgroup barrier without the release fence of __syncthreads (which would
+// wait for every outstanding direct-to-LDS load); the inline-asm memory
+// clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void stage_barrier() {
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <bool SWIGLU>
+__global__ __launch_bounds__(256, 2) void gemm_bf16_big(
+    const bf16_t* __restrict__ A, const bf16_t* __restrict__ B, bf16_t* __restrict__ C,
+    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start, int E, int N,
+    int K, int f, int Ncols, int n_tiles, int grid_total) {
+  __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
+  const int b = blockIdx.x;
+  const int per = grid_total >> 3;
+  const int Lt = (b & 7) * per + (b >> 3);
+  int e, row0, rows, nt;
+  if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int n0 = nt * (SWIGLU ? 64 : 128);
+  const size_t Brows_e = SWIGLU ? (size_t)2 * f : (size_t)Ncols;
+  const bf16_t* Be = B + (size_t)e * Brows_e * K;
+
+  // DMA sources of this lane: wavefront wv fills token rows wv*64.. (A_INS
+  // instructions of 16 rows x 4 chunks) and weight rows wv*32.. (B_INS);
+  // lane -> (row + lane/4, slot lane%4)
+  const bf16_t* asrc[A_INS];
+  const bf16_t* bsrc[B_INS];
+#pragma unroll
+  for (int i = 0; i < A_INS; ++i) {
+    const int R = wv * (GBM / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    asrc[i] = A + (size_t)(row0 + min(R, rows - 1)) * K + c * 8;
+  }
+#pragma unroll
+  for (int i = 0; i < B_INS; ++i) {
+    const int R = wv * (GBN / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    const int wrow = SWIGLU ? (R < 64 ? n0 + R : f + n0 + (R - 64)) : n0 + R;
+    bsrc[i] = Be + (size_t)wrow * K + c * 8;
+  }
+  typedef __attribute__((address_space(3))) void lds_void;
+  auto issue = [&](int kstep) {
+    char* st = lds + (kstep % NSTAGE) * STAGE_BYTES;
+    const int k0 = kstep * GBK;
+#pragma unroll
+    for (int i = 0; i < A_INS; ++i)
+      __builtin_amdgcn_global_load_lds(asrc[i] + k0,
+                                       (lds_void*)(st + (wv * (GBM / 4) + i * 16) * 64), 16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < B_INS; ++i)
+      __builtin_amdgcn_global_load_lds(
+          bsrc[i] + k0, (lds_void*)(st + STAGE_A + (wv * (GBN / 4) + i * 16) * 64), 16, 0, 0);
+  };
+
+  f32x16 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
+
+  const int fr = lane & 31, fh = lane >> 5;
+  int aoff[4], boff[2], asw[4], bsw[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int R = wm * 128 + i * 32 + fr;
+    aoff[i] = R * 64;
+    asw[i] = swz(R);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int R = SWIGLU ? (j == 0 ? wn * 32 : 64 + wn * 32) : wn * 64 + j * 32;
+    boff[j] = STAGE_A + (R + fr) * 64;
+    bsw[j] = swz(R + fr);
+  }
+
+  // Software pipeline over K steps of 32 = two MFMA sub-steps (ks = 0, 1)
+  // with fragment sets F0 (ks 0) and F1 (ks 1): the reads of the next
+  // fragments are in flight while the current ones feed the MFMAs; the
+  // stage barrier sits between the two halves of a step, and the load of
+  // step kt+3 goes into the stage step kt has just vacated.
+  const int nk = K / GBK;
+#define READ_FRAGS(AF, BF, stp, ks)                                                      \
+  {                                                                                      \
+    const char* st_ = lds + ((stp) % NSTAGE) * STAGE_BYTES;                              \
+    const int c_ = (ks) * 2 + fh;                                                        \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) AF[i] =                                \
+        *(const bf16x8*)(st_ + aoff[i] + ((c_ ^ asw[i]) << 4));                          \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) BF[j] =                                \
+        *(const bf16x8*)(st_ + boff[j] + ((c_ ^ bsw[j]) << 4));                          \
+  }
+#define MFMA8(AF, BF)                                                                    \
+  _Pragma("unroll") for (int i = 0; i < 4; ++i) _Pragma("unroll") for (int j = 0; j < 2; \
+                                                                       ++j) acc[i][j] =  \
+      __builtin_amdgcn_mfma_f32_32x32x16_bf16(BF[j], AF[i], acc[i][j], 0, 0, 0);
+  bf16x8 a0[4], b0[2], a1[4], b1[2];
+  issue(0);
+  if (nk > 1) issue(1);
+  if (nk > 2) issue(2);
+  if (nk > 2) {
+    WAIT_VM_LGKM0(2 * VM_PER_STAGE);
+  } else if (nk > 1) {
+    WAIT_VM_LGKM0(VM_PER_STAGE);
+  } else {
+    WAIT_VM_LGKM0(0);
+  }
+  stage_barrier();
+  READ_FRAGS(a0, b0, 0, 0);
+  for (int kt = 0; kt + 1 < nk; ++kt) {
+    READ_FRAGS(a1, b1, kt, 1);
+    MFMA8(a0, b0);
+    // step kt+1 must have landed: at most step kt+2 remains in flight
+    if (kt + 2 < nk) {
+      WAIT_VM_LGKM0(VM_PER_STAGE);
+    } else {
+      WAIT_VM_LGKM0(0);
+    }
+    stage_barrier();  // every wavefront's reads of stage kt are done
+    if (kt + 3 < nk) issue(kt + 3);
+    READ_FRAGS(a0, b0, kt + 1, 0);
+    MFMA8(a1, b1);
+  }
+  READ_FRAGS(a1, b1, nk - 1, 1);
+  MFMA8(a0, b0);
+  MFMA8(a1, b1);
+#undef READ_FRAGS
+#undef MFMA8
+  WAIT_VM_LGKM0(0);
+  stage_barrier();
+
+  // epilogue through LDS: lane owns token row (i*32 + fr) and columns
+  // 8*(q/4) + 4*(lane/32) + (q%4) of each 32-wide column tile
+  constexpr int CS = SWIGLU ? 64 : 128;
+  constexpr int CLD = CS + 8;
+  bf16_t* Cs = (bf16_t*)lds;
+  const int cbase = fh * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rl = wm * 128 + i * 32 + fr;
+#pragma unroll
+    for (int j = 0; j < (SWIGLU ? 1 : 2); ++j) {
+      const int col0 = SWIGLU ? wn * 32 : wn * 64 + j * 32;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        bf16x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float x = acc[i][j][g * 4 + q];
+          if (SWIGLU) {
+            const float y = acc[i][1][g * 4 + q];
+            v[q] = (bf16_t)(silu(x) * y);
+          } else {
+            v[q] = (bf16_t)x;
+          }
+        }
+        *(bf16x4*)(Cs + rl * CLD + col0 + g * 8 + cbase) = v;
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int CPR = CS / 8;  // 16-byte chunks per row
+  const int n0c = nt * CS;
+  for (int c = tid; c < GBM * CPR; c += 256) {
+    const int rr = c / CPR, cc = (c - rr * CPR) * 8;
+    if (rr < rows)
+      *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + n0c + cc) = *(const u32x4*)(Cs + rr * CLD + cc);
+  }
+}
+
 // ---------------------------------------------------------------- FP32 SIMT
 // Block tile 64 rows x 64 B-rows, K step 16, 256 threads with 4 x 4 outputs.
 // SwiGLU mode: B-rows 0..31 = W1 rows n0..n0+31, 32..63 = the W3 rows; a
@@ -240,6 +486,7 @@ __global__ __launch_bounds__(256) void gemm_f32(const float* __restrict__ A,
 
 struct FfnWs {
   int32_t* tile_start;
+  int32_t* tile_start_big;
   void* h;
 };
 
@@ -247,6 +494,7 @@ FfnWs carve_ffn(const moe_cfg& c, void* base, size_t* total) {
   WsCarve wc{(char*)base, 0};
   FfnWs r;
   r.tile_start = wc.take<int32_t>((size_t)c.E + 1);
+  r.tile_start_big = wc.take<int32_t>((size_t)c.E + 1);
   const size_t N = (size_t)c.T * c.k;
   r.h = wc.take<char>(N * (size_t)c.d_ff * act_bytes(c.act));
   if (total) *total = align_up(wc.off, 256);
@@ -286,18 +534,41 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
   FfnWs w = carve_ffn(c, ws, nullptr);
   const int N = c.T * c.k;
   if (bf16path) {
-    hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, BM, w.tile_start);
-    dim3 g1((N + BM - 1) / BM + c.E, c.d_ff / 64);
+    // 256-row tiles where the shape allows them, 128-row tiles otherwise
+    const bool big1 = c.d_ff % 64 == 0 && c.d % GBK == 0;
+    const bool big2 = c.d % 128 == 0 && c.d_ff % GBK == 0;
+    if (big1 || big2)
+      hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
+    if (!big1 || !big2)
+      hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, BM, w.tile_start);
+    const int mt_big = (N + GBM - 1) / GBM + c.E;
     PROF_BEGIN("gemm1_swiglu", st);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16<true>), g1, dim3(256), 0, st,
-                       (const bf16_t*)X_perm, (const bf16_t*)W13, (bf16_t*)w.h, offsets,
-                       w.tile_start, c.E, N, c.d, c.d_ff, c.d_ff);
+    if (big1) {
+      const int nt = c.d_ff / 64;
+      const int G = (mt_big * nt + 7) / 8 * 8;
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<true>), dim3(G), dim3(256), 0, st,
+                         (const bf16_t*)X_perm, (const bf16_t*)W13, (bf16_t*)w.h, offsets,
+                         w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt, G);
+    } else {
+      dim3 g1((N + BM - 1) / BM + c.E, c.d_ff / 64);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16<true>), g1, dim3(256), 0, st,
+                         (const bf16_t*)X_perm, (const bf16_t*)W13, (bf16_t*)w.h, offsets,
+                         w.tile_start, c.E, N, c.d, c.d_ff, c.d_ff);
+    }
     PROF_END("gemm1_swiglu", st);
-    dim3 g2((N + BM - 1) / BM + c.E, c.d / 128);
     PROF_BEGIN("gemm2", st);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16<false>), g2, dim3(256), 0, st,
-                       (const bf16_t*)w.h, (const bf16_t*)W2, (bf16_t*)Y, offsets, w.tile_start,
-                       c.E, N, c.d_ff, c.d_ff, c.d);
+    if (big2) {
+      const int nt = c.d / 128;
+      const int G = (mt_big * nt + 7) / 8 * 8;
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<false>), dim3(G), dim3(256), 0, st,
+                         (const bf16_t*)w.h, (const bf16_t*)W2, (bf16_t*)Y, offsets,
+                         w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt, G);
+    } else {
+      dim3 g2((N + BM - 1) / BM + c.E, c.d / 128);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16<false>), g2, dim3(256), 0, st,
+                         (const bf16_t*)w.h, (const bf16_t*)W2, (bf16_t*)Y, offsets, w.tile_start,
+                         c.E, N, c.d_ff, c.d_ff, c.d);
+    }
     PROF_END("gemm2", st);
   } else {
     hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, FBM, w.tile_start);

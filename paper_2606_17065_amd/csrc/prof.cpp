@@ -37,7 +37,7 @@ void prof_mark(const char* name, void* stream, bool begin) {
   if (!g_on) return;
   hipEvent_t e = take_event();
   if (!e) return;
-  hipEventRecord(e, (hipStream_t)stream);
+  if (hipEventRecord(e, (hipStream_t)stream) != hipSuccess) return;
   Slot& s = g_slots[name];
   (begin ? s.start : s.stop).push_back(e);
 }

@@ -21,17 +21,14 @@
 namespace {
 
 constexpr int SIG_BLOCK = 256;   // token block of the fixed-order reduction
-constexpr int RANK_THREADS = 64; // one wavefront: 64 tokens, one per lane
-constexpr int SEL_THREADS = 512;
+constexpr int SEL_THREADS = 1024;
 constexpr int REP_THREADS = 1024;
 
 // ------------------------------------------------------------------ init
 
-__global__ void route_init(int32_t* state, int32_t* loadbuf, int E, float* price, int mode,
-                           float gamma) {
+__global__ void route_init(int32_t* state, int E, float* price, int mode, float gamma) {
   int tid = threadIdx.x;
   if (tid < ST_LEN) state[tid] = 0;
-  for (int e = tid; e < 2 * E; e += blockDim.x) loadbuf[e] = 0;
   for (int e = tid; e < E; e += blockDim.x) {
     if (mode == MOE_PRICE_NONE || mode == MOE_PRICE_ACP) price[e] = 0.0f;
     else if (mode == MOE_PRICE_WARM) price[e] = gamma * price[e];
@@ -101,6 +98,110 @@ __global__ __launch_bounds__(256) void router_logits(const TX* __restrict__ X,
   }
 }
 
+// -------------------------------------------- router GEMM, BF16 tokens
+// W_r is split into three BF16 planes hi, mid, lo (each the round-to-
+// nearest-even of what the previous planes leave over), so that
+// X W_r^T = X hi^T + X mid^T + X lo^T with exact BF16 x BF16 products
+// accumulated in FP32 by v_mfma_f32_32x32x16_bf16.
+
+__global__ __launch_bounds__(256) void router_split(const float* __restrict__ Wr, int n,
+                                                    bf16_t* __restrict__ W3) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float x = Wr[i];
+  const bf16_t h = (bf16_t)x;
+  const float r1 = x - (float)h;
+  const bf16_t m = (bf16_t)r1;
+  const float r2 = r1 - (float)m;
+  W3[i] = h;
+  W3[n + i] = m;
+  W3[2 * n + i] = (bf16_t)r2;
+}
+
+// Block: 128 tokens (32 per wavefront) x 64 experts, K step 32.  The three
+// weight planes of the block's experts go through LDS; each wavefront reads
+// its own token fragments straight from HBM.
+constexpr int RLDK = 32 + 8;
+
+__global__ __launch_bounds__(256) void router_logits_mfma(const bf16_t* __restrict__ X,
+                                                          const bf16_t* __restrict__ W3,
+                                                          const float* __restrict__ br,
+                                                          float* __restrict__ s,
+                                                          float* __restrict__ sT, int T, int d,
+                                                          int E) {
+  __shared__ __attribute__((aligned(16))) bf16_t Ws[3 * 64 * RLDK];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t0 = blockIdx.x * 128 + wv * 32;
+  const int e0 = blockIdx.y * 64;
+  const size_t plane = (size_t)E * d;
+  const int fr = lane & 31, fk = (lane >> 5) * 8;
+  const int trow = t0 + fr;
+  const bf16_t* xr = X + (size_t)min(trow, T - 1) * d + fk;
+  const bool tvalid = trow < T;
+  // weight tile chunks: 3 planes x 64 rows x 4 chunks of 16 B = 768
+  int wrow[3], wcol[3], wpl[3];
+  bool wok[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int c = tid + 256 * r;
+    wpl[r] = c / 256;
+    wrow[r] = (c % 256) >> 2;
+    wcol[r] = (c & 3) * 8;
+    wok[r] = e0 + wrow[r] < E;
+  }
+  u32x4 wreg[3];
+  bf16x8 xa0, xa1;
+#define RLOAD(k0)                                                                         \
+  _Pragma("unroll") for (int r = 0; r < 3; ++r) wreg[r] =                                 \
+      wok[r] ? *(const u32x4*)(W3 + wpl[r] * plane + (size_t)(e0 + wrow[r]) * d + (k0) +  \
+                               wcol[r])                                                   \
+             : u32x4{0u, 0u, 0u, 0u};                                                     \
+  xa0 = *(const bf16x8*)(xr + (k0));                                                      \
+  xa1 = *(const bf16x8*)(xr + (k0) + 16);
+  f32x16 acc[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[j][q] = 0.0f;
+  RLOAD(0);
+  for (int k0 = 0; k0 < d; k0 += 32) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) *(u32x4*)(Ws + (wpl[r] * 64 + wrow[r]) * RLDK + wcol[r]) = wreg[r];
+    const bf16x8 x0 = tvalid ? xa0 : bf16x8{}, x1 = tvalid ? xa1 : bf16x8{};
+    __syncthreads();
+    if (k0 + 32 < d) { RLOAD(k0 + 32); }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int pl = 0; pl < 3; ++pl) {
+        const bf16x8 w0 = *(const bf16x8*)(Ws + (pl * 64 + j * 32 + fr) * RLDK + fk);
+        const bf16x8 w1 = *(const bf16x8*)(Ws + (pl * 64 + j * 32 + fr) * RLDK + 16 + fk);
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, x0, acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, x1, acc[j], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+#undef RLOAD
+  // lane holds token trow and experts e0 + 32 j + 8 (q/4) + 4 (lane/32) + q%4
+  if (tvalid) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int eb = e0 + j * 32 + g * 8 + (lane >> 5) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = eb + q;
+          if (e < E) {
+            const float v = acc[j][g * 4 + q] + br[e];
+            s[(size_t)trow * E + e] = v;
+            sT[(size_t)e * T + trow] = v;
+          }
+        }
+      }
+  }
+}
+
 // ------------------------------------------------- sigma_s, fixed order
 // Block b owns tokens [256b, 256b+256); thread i accumulates its token's
 // row from expert 0 upward in FP64, then the block halves (stride 128..1).
@@ -113,10 +214,19 @@ __global__ __launch_bounds__(SIG_BLOCK) void score_partials(const float* __restr
   const int t = blockIdx.x * SIG_BLOCK + tid;
   double r1 = 0.0, r2 = 0.0;
   if (t < T) {
-    for (int e = 0; e < E; ++e) {
-      double v = (double)sT[(size_t)e * T + t];
-      r1 = r1 + v;
-      r2 = r2 + v * v;
+    // loads batched 16 at a time; the additions keep expert order
+    for (int e0 = 0; e0 < E; e0 += 16) {
+      float xv[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xv[i] = e0 + i < E ? sT[(size_t)(e0 + i) * T + t] : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (e0 + i < E) {
+          const double v = (double)xv[i];
+          r1 = r1 + v;
+          r2 = r2 + v * v;
+        }
+      }
     }
   }
   v1[tid] = r1;
@@ -206,78 +316,186 @@ __device__ __forceinline__ uint64_t pick(const uint64_t (&v)[L], int j) {
 
 __device__ __forceinline__ int key_expert(uint64_t v) { return (int)(0xFFFFFFFFu - (uint32_t)v); }
 
-// One ranking pass of the price loop (iteration ``it``): lane = token.
-// Writes the routing and gate weights for the current prices, the margin
-// keys mT[e][t] of every expert, and adds the block's loads to
-// loadbuf[it & 1].
+// One ranking pass of the price loop.  A block owns TG groups of 64 tokens
+// (one token per lane) and splits the experts into four contiguous ranges,
+// one wavefront per (token group, range); each wavefront keeps its logits
+// in registers and builds a partial top-L list per token.  One wavefront
+// per token group merges the four sorted lists (k+1 steps) and writes the
+// routing for the current prices; then every wavefront writes the margin
+// keys mT[e][t] of its experts.  The block's per-expert counts go to row
+// blockIdx.x of cnt[nblk][E] (no global atomics).
+constexpr int RANK_WAVES = 4;
+
+// Top-L list as parallel arrays of sortable keys and expert indices, best
+// first.  Experts are inserted in increasing index order, so a strict
+// comparison keeps the lower expert ahead of an equal key.
 template <int L>
-__global__ __launch_bounds__(RANK_THREADS) void acp_rank(
-    const float* __restrict__ sT, const float* __restrict__ logits, const float* __restrict__ price,
-    int T, int E, int k, int it, const int32_t* __restrict__ state, uint32_t* __restrict__ mT,
-    int32_t* __restrict__ idx, float* __restrict__ w, int32_t* __restrict__ loadbuf) {
+__device__ __forceinline__ void insert_kv(uint32_t (&K)[L], int (&X)[L], uint32_t key, int e) {
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const bool gt = key > K[j];
+    const uint32_t hi = max(key, K[j]), lo = min(key, K[j]);
+    const int eh = gt ? e : X[j], el = gt ? X[j] : e;
+    K[j] = hi;
+    X[j] = eh;
+    key = lo;
+    e = el;
+  }
+}
+
+template <int L, int NV, int TG>
+__global__ __launch_bounds__(64 * RANK_WAVES * TG) void acp_rank(
+    const float* __restrict__ sT, const float* __restrict__ price, int T, int E, int k,
+    const int32_t* __restrict__ state, uint32_t* __restrict__ mT, int32_t* __restrict__ idx,
+    int32_t* __restrict__ cnt) {
   if (state[ST_DONE]) return;
   __shared__ int hist[MOE_MAX_E];
   __shared__ float ps[MOE_MAX_E];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < E; e += RANK_THREADS) {
+  __shared__ uint32_t partk[TG][RANK_WAVES][L][64];
+  __shared__ int parte[TG][RANK_WAVES][L][64];
+  __shared__ uint32_t kthk_s[TG][64];
+  __shared__ int kthe_s[TG][64];
+  __shared__ float k1_s[TG][64], k2_s[TG][64];
+  constexpr int NT = 64 * RANK_WAVES * TG;
+  const int tid = threadIdx.x, lane = tid & 63, wv = (tid >> 6) & (RANK_WAVES - 1);
+  const int tg = tid / (64 * RANK_WAVES);
+  for (int e = tid; e < E; e += NT) {
     hist[e] = 0;
     ps[e] = price[e];
   }
   __syncthreads();
-  const int t = blockIdx.x * RANK_THREADS + tid;
-  if (t < T) {
-    uint64_t v[L];
+  const int t = (blockIdx.x * TG + tg) * 64 + lane;
+  const bool valid = t < T;
+  const int tl = valid ? t : T - 1;  // out-of-range lanes read a valid row, write nothing
+  const int per = (E + RANK_WAVES - 1) / RANK_WAVES;
+  const int e_lo = wv * per;
+  const int ne = max(0, min(E, e_lo + per) - e_lo);
+  const bool cached = ne <= NV;
+  float sv[NV];
+  uint32_t K[L];
+  int X[L];
 #pragma unroll
-    for (int j = 0; j < L; ++j) v[j] = 0;
-    int e = 0;
-    for (; e + 4 <= E; e += 4) {
-      float s0 = sT[(size_t)e * T + t], s1 = sT[(size_t)(e + 1) * T + t];
-      float s2 = sT[(size_t)(e + 2) * T + t], s3 = sT[(size_t)(e + 3) * T + t];
-      insert_top<L>(v, rank_key(s0 - ps[e], e));
-      insert_top<L>(v, rank_key(s1 - ps[e + 1], e + 1));
-      insert_top<L>(v, rank_key(s2 - ps[e + 2], e + 2));
-      insert_top<L>(v, rank_key(s3 - ps[e + 3], e + 3));
+  for (int j = 0; j < L; ++j) {
+    K[j] = 0u;
+    X[j] = 0;
+  }
+  if (cached) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sv[i] = sT[(size_t)(e_lo + min(i, max(ne - 1, 0))) * T + tl];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const uint32_t key = i < ne ? f32_key(sv[i] - ps[e_lo + min(i, max(ne - 1, 0))]) : 0u;
+      insert_kv<L>(K, X, key, e_lo + i);
     }
-    for (; e < E; ++e) insert_top<L>(v, rank_key(sT[(size_t)e * T + t] - ps[e], e));
-    const uint64_t kth = pick<L>(v, k - 1);
-    const float kap1 = key_f32((uint32_t)(kth >> 32));
-    const float kap2 = (k < E) ? key_f32((uint32_t)(pick<L>(v, k) >> 32)) : -INFINITY;
-    // routing and softmax gate weights over the raw logits of the chosen
-    float mx = -INFINITY;
+  } else {
+    for (int c0 = 0; c0 < ne; c0 += NV) {
 #pragma unroll
-    for (int j = 0; j < L; ++j)
-      if (j < k) mx = fmaxf(mx, logits[(size_t)t * E + key_expert(v[j])]);
-    float ex[L];
-    float den = 0.0f;
+      for (int i = 0; i < NV; ++i) sv[i] = sT[(size_t)(e_lo + min(c0 + i, ne - 1)) * T + tl];
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-      ex[j] = 0.0f;
-      if (j < k) {
-        ex[j] = expf(logits[(size_t)t * E + key_expert(v[j])] - mx);
-        den = den + ex[j];
+      for (int i = 0; i < NV; ++i) {
+        const uint32_t key = c0 + i < ne ? f32_key(sv[i] - ps[e_lo + min(c0 + i, ne - 1)]) : 0u;
+        insert_kv<L>(K, X, key, e_lo + c0 + i);
       }
-    }
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-      if (j < k) {
-        int ej = key_expert(v[j]);
-        idx[(size_t)t * k + j] = ej;
-        w[(size_t)t * k + j] = ex[j] / den;
-        atomicAdd(&hist[ej], 1);
-      }
-    }
-    // margins m = s - (held ? kappa2 : kappa1), stored as sortable keys
-    for (e = 0; e < E; ++e) {
-      float s = sT[(size_t)e * T + t];
-      bool held = rank_key(s - ps[e], e) >= kth;
-      float m = s - (held ? kap2 : kap1);
-      mT[(size_t)e * T + t] = f32_key(m);
     }
   }
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    partk[tg][wv][j][lane] = K[j];
+    parte[tg][wv][j][lane] = X[j];
+  }
   __syncthreads();
-  int32_t* lb = loadbuf + (it & 1) * E;
-  for (int e = tid; e < E; e += RANK_THREADS)
-    if (hist[e]) atomicAdd(&lb[e], hist[e]);
+  if (wv == 0 && valid) {
+    // merge the four sorted lists (k+1 steps); on equal keys the list of
+    // the lower expert range wins
+    int h0 = 0, h1 = 0, h2 = 0, h3 = 0;
+    uint32_t kk1 = 0, kk2 = 0;
+    int ek1 = 0;
+    for (int j = 0; j <= k && j < L; ++j) {
+      const uint32_t c0 = h0 < L ? partk[tg][0][h0][lane] : 0u;
+      const uint32_t c1 = h1 < L ? partk[tg][1][h1][lane] : 0u;
+      const uint32_t c2 = h2 < L ? partk[tg][2][h2][lane] : 0u;
+      const uint32_t c3 = h3 < L ? partk[tg][3][h3][lane] : 0u;
+      int src = 0;
+      uint32_t m = c0;
+      if (c1 > m) { m = c1; src = 1; }
+      if (c2 > m) { m = c2; src = 2; }
+      if (c3 > m) { m = c3; src = 3; }
+      const int hs = src == 0 ? h0 : (src == 1 ? h1 : (src == 2 ? h2 : h3));
+      const int ej = parte[tg][src][hs][lane];
+      if (src == 0) ++h0;
+      else if (src == 1) ++h1;
+      else if (src == 2) ++h2;
+      else ++h3;
+      if (j < k) {
+        idx[(size_t)t * k + j] = ej;
+        atomicAdd(&hist[ej], 1);
+      }
+      if (j == k - 1) {
+        kk1 = m;
+        ek1 = ej;
+      }
+      if (j == k) kk2 = m;
+    }
+    kthk_s[tg][lane] = kk1;
+    kthe_s[tg][lane] = ek1;
+    k1_s[tg][lane] = key_f32(kk1);
+    k2_s[tg][lane] = (k < E) ? key_f32(kk2) : -INFINITY;
+  }
+  __syncthreads();
+  // margins m = s - (held ? kappa2 : kappa1), stored as sortable keys;
+  // e is held iff (key(a_te), -e) >= (key of rank k, -its expert)
+  if (valid) {
+    const uint32_t kk1 = kthk_s[tg][lane];
+    const int ek1 = kthe_s[tg][lane];
+    const float kap1 = k1_s[tg][lane], kap2 = k2_s[tg][lane];
+    if (cached) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        if (i < ne) {
+          const int e = e_lo + i;
+          const uint32_t key = f32_key(sv[i] - ps[e]);
+          const bool held = key > kk1 || (key == kk1 && e <= ek1);
+          mT[(size_t)e * T + t] = f32_key(sv[i] - (held ? kap2 : kap1));
+        }
+      }
+    } else {
+      for (int i = 0; i < ne; ++i) {
+        const int e = e_lo + i;
+        const float s = sT[(size_t)e * T + t];
+        const uint32_t key = f32_key(s - ps[e]);
+        const bool held = key > kk1 || (key == kk1 && e <= ek1);
+        mT[(size_t)e * T + t] = f32_key(s - (held ? kap2 : kap1));
+      }
+    }
+  }
+  for (int e = tid; e < E; e += NT) cnt[(size_t)blockIdx.x * E + e] = hist[e];
+}
+
+// Gate weights of the final routing: softmax of the raw logits over each
+// token's k chosen experts (FP32, max-subtracted).
+__global__ __launch_bounds__(256) void route_weights(const float* __restrict__ logits,
+                                                     const int32_t* __restrict__ idx, int T, int E,
+                                                     int k, const int32_t* __restrict__ state,
+                                                     float* __restrict__ w) {
+  if (state[ST_STATUS] != MOE_OK) return;
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= T) return;
+  float z[MOE_MAX_K];
+  float mx = -INFINITY;
+#pragma unroll
+  for (int j = 0; j < MOE_MAX_K; ++j) {
+    z[j] = j < k ? logits[(size_t)t * E + idx[(size_t)t * k + j]] : -INFINITY;
+    mx = fmaxf(mx, z[j]);
+  }
+  float den = 0.0f;
+#pragma unroll
+  for (int j = 0; j < MOE_MAX_K; ++j) {
+    z[j] = j < k ? expf(z[j] - mx) : 0.0f;
+    den = den + z[j];
+  }
+#pragma unroll
+  for (int j = 0; j < MOE_MAX_K; ++j)
+    if (j < k) w[(size_t)t * k + j] = z[j] / den;
 }
 
 // ------------------------------------------------ block radix selection
@@ -378,16 +596,73 @@ __device__ int block_excl_scan(int flag, int* red, int* total) {
 // --------------------------------------------------------- price update
 // One block per expert.  All blocks first agree, from the loads of this
 // iteration, whether the loop ends here; block 0 then records the outcome.
+// An overloaded expert finds the (C+1)-th largest margin key by a 3-pass
+// radix selection (11, 11, 10 bits) whose keys stay in registers when T is
+// at most SEL_THREADS * SEL_KPT.  Only keys at or above a floor a little
+// below the expert's current price enter the histograms (the tokens that
+// do not hold the expert have margins below its price); if fewer than C+1
+// keys pass the floor, the selection restarts with no floor, so the result
+// is always the exact order statistic over all T margins.
+constexpr int SEL_KPT = 16;
+
+// Digit holding the rr-th largest key of a 2048-bin histogram, found by the
+// 1024 threads of the block (two bins each) with a block suffix scan.
+// Writes the digit (or -1 if fewer than rr keys were counted) and the count
+// of keys in higher digits.
+__device__ void block_pick_digit(const uint32_t* hist, int rr, int* red, int* pick_digit,
+                                 uint32_t* pick_above) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t lo = hist[2 * tid], hi = hist[2 * tid + 1];
+  const uint32_t loc = lo + hi;
+  uint32_t suf = loc;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_down(suf, off, 64);
+    if (lane + off < 64) suf += o;
+  }
+  if (lane == 0) red[wv] = (int)suf;
+  if (tid == 0) *pick_digit = -1;
+  __syncthreads();
+  uint32_t after = 0;
+  for (int w = wv + 1; w < SEL_THREADS / 64; ++w) after += (uint32_t)red[w];
+  const uint32_t S = suf + after;
+  const uint32_t above = S - loc;
+  if (above < (uint32_t)rr && (uint32_t)rr <= S) {
+    if (above + hi >= (uint32_t)rr) {
+      *pick_digit = 2 * tid + 1;
+      *pick_above = above;
+    } else {
+      *pick_digit = 2 * tid;
+      *pick_above = above + hi;
+    }
+  }
+  __syncthreads();
+}
 
 __global__ __launch_bounds__(SEL_THREADS) void acp_select(
     const uint32_t* __restrict__ mT, float* __restrict__ price, int T, int E, int C, int it,
-    int max_iters, int32_t* __restrict__ state, int32_t* __restrict__ loadbuf,
+    int max_iters, int nblk, const int32_t* __restrict__ cnt, int32_t* __restrict__ state,
     int32_t* __restrict__ load_out) {
   if (state[ST_DONE]) return;
   __shared__ SelScratch sc;
   __shared__ int red[32];
+  __shared__ int ld[MOE_MAX_E];
   const int tid = threadIdx.x;
-  const int32_t* ld = loadbuf + (it & 1) * E;
+  // loads of this iteration: column sums of the per-block count matrix
+  for (int e = tid; e < E; e += SEL_THREADS) ld[e] = 0;
+  __syncthreads();
+  {
+    const int lanes_per_e = max(1, SEL_THREADS / E);
+    for (int e0 = 0; e0 < E; e0 += SEL_THREADS) {
+      const int e = e0 + tid % min(E, SEL_THREADS);
+      const int r0 = tid / min(E, SEL_THREADS);
+      if (e < E && r0 < lanes_per_e) {
+        int sum = 0;
+        for (int r = r0; r < nblk; r += lanes_per_e) sum += cnt[(size_t)r * E + e];
+        atomicAdd(&ld[e], sum);
+      }
+    }
+  }
+  __syncthreads();
   int over = 0, excess = 0;
   for (int e = tid; e < E; e += SEL_THREADS) {
     int x = ld[e] - C;
@@ -412,21 +687,61 @@ __global__ __launch_bounds__(SEL_THREADS) void acp_select(
     }
     return;
   }
-  if (e == 0)
-    for (int i = tid; i < E; i += SEL_THREADS) loadbuf[((it + 1) & 1) * E + i] = 0;
   if (ld[e] <= C) return;
   const uint32_t* col = mT + (size_t)e * T;
-  int greater;
-  uint32_t q = block_select_rth(
-      T, C + 1,
-      [&](int i, uint32_t& key) {
-        key = col[i];
-        return true;
-      },
-      sc, &greater);
+  const bool cached = T <= SEL_THREADS * SEL_KPT;
+  uint32_t kk[SEL_KPT];
+  if (cached) {
+#pragma unroll
+    for (int i = 0; i < SEL_KPT; ++i) {
+      const int j = i * SEL_THREADS + tid;
+      kk[i] = j < T ? col[j] : 0u;
+    }
+  }
+  const uint32_t pkey = f32_key(price[e]);
+  uint32_t floor_key = pkey > 4096u ? pkey - 4096u : 0u;
+  uint32_t prefix = 0, mask = 0;
+  int rr = C + 1;
+#pragma unroll 1
+  for (int pass = 0; pass < 3; ++pass) {
+    const int sh = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+    const uint32_t dm = pass == 2 ? 1023u : 2047u;
+    for (int i = tid; i < 2048; i += SEL_THREADS) sc.hist[i] = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < T; c0 += SEL_THREADS * SEL_KPT) {
+      if (!cached) {
+#pragma unroll
+        for (int i = 0; i < SEL_KPT; ++i) {
+          const int j = c0 + i * SEL_THREADS + tid;
+          kk[i] = j < T ? col[j] : 0u;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < SEL_KPT; ++i) {
+        if ((c0 + i * SEL_THREADS + tid < T) && kk[i] >= floor_key && ((kk[i] & mask) == prefix))
+          atomicAdd(&sc.hist[(kk[i] >> sh) & dm], 1u);
+      }
+    }
+    __syncthreads();
+    block_pick_digit(sc.hist, rr, red, &sc.pick_digit, &sc.pick_above);
+    const int dsel = sc.pick_digit;
+    const uint32_t above = sc.pick_above;
+    __syncthreads();
+    if (dsel < 0) {
+      // fewer than C+1 keys above the floor: restart over all keys (a
+      // second miss cannot happen while load_e > C; leave the price as is)
+      if (floor_key == 0u) return;
+      floor_key = 0u;
+      pass = -1;
+      continue;
+    }
+    rr -= (int)above;
+    prefix |= (uint32_t)dsel << sh;
+    mask |= dm << sh;
+  }
   if (tid == 0) {
     const float eps = __int_as_float(state[ST_EPS]);
-    const float qf = key_f32(q);
+    const float qf = key_f32(prefix);
     const float cand = nextafterf(qf, INFINITY) + eps;
     const float old = price[e];
     price[e] = cand > old ? cand : old;
@@ -646,10 +961,11 @@ __global__ void route_finalize(const int32_t* state, int32_t* info, int32_t* loa
 }
 
 struct RouteWs {
+  bf16_t* W3;
   float* sT;
   uint32_t* mT;
   int32_t* state;
-  int32_t* loadbuf;
+  int32_t* cnt;
   double* part;
   uint32_t *held, *tried, *prop;
   int32_t* missing;
@@ -661,10 +977,11 @@ RouteWs carve_route(const moe_cfg& c, void* base, size_t* total) {
   const size_t T = (size_t)c.T, E = (size_t)c.E;
   const size_t W = (E + 31) / 32;
   const size_t nb = (T + SIG_BLOCK - 1) / SIG_BLOCK;
+  r.W3 = wc.take<bf16_t>(3 * E * (size_t)c.d);
   r.sT = wc.take<float>(T * E);
   r.mT = wc.take<uint32_t>(T * E);
   r.state = wc.take<int32_t>(ST_LEN);
-  r.loadbuf = wc.take<int32_t>(2 * E);
+  r.cnt = wc.take<int32_t>(((T + 127) / 128 + 1) * E);
   r.part = wc.take<double>(2 * (nb > 0 ? nb : 1));
   r.held = wc.take<uint32_t>(T * W);
   r.tried = wc.take<uint32_t>(T * W);
@@ -679,13 +996,25 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
                                float* price, int32_t* idx, float* w, int32_t* load,
                                int max_iters, hipStream_t st) {
   const int T = c.T, E = c.E, k = c.k, C = c.capacity;
-  const int nblk = (T + RANK_THREADS - 1) / RANK_THREADS;
+  constexpr int TG = L <= 9 ? 4 : 2;
+  const int nblk = (T + 64 * TG - 1) / (64 * TG);
+  const int per = (E + RANK_WAVES - 1) / RANK_WAVES;
   for (int it = 0; it <= max_iters; ++it) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L>), dim3(nblk), dim3(RANK_THREADS), 0, st,
-                       ws.sT, logits, price, T, E, k, it, ws.state, ws.mT, idx, w, ws.loadbuf);
+    const dim3 rb(64 * RANK_WAVES * TG);
+    if (per <= 4)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 4, TG>), dim3(nblk), rb, 0, st, ws.sT, price,
+                         T, E, k, ws.state, ws.mT, idx, ws.cnt);
+    else if (per <= 16)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 16, TG>), dim3(nblk), rb, 0, st, ws.sT, price,
+                         T, E, k, ws.state, ws.mT, idx, ws.cnt);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 64, TG>), dim3(nblk), rb, 0, st, ws.sT, price,
+                         T, E, k, ws.state, ws.mT, idx, ws.cnt);
     hipLaunchKernelGGL(acp_select, dim3(E), dim3(SEL_THREADS), 0, st, ws.mT, price, T, E, C, it,
-                       max_iters, ws.state, ws.loadbuf, load);
+                       max_iters, nblk, ws.cnt, ws.state, load);
   }
+  hipLaunchKernelGGL(route_weights, dim3((T + 255) / 256), dim3(256), 0, st, logits, idx, T, E, k,
+                     ws.state, w);
   hipLaunchKernelGGL(HIP_KERNEL_NAME(capacity_repair<L>), dim3(1), dim3(REP_THREADS), 0, st,
                      ws.sT, logits, price, T, E, k, C, ws.state, idx, w, load, ws.held, ws.tried,
                      ws.prop, ws.missing);
@@ -717,7 +1046,7 @@ extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* 
   if (ws_bytes < route_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   RouteWs w = carve_route(c, ws, nullptr);
-  hipLaunchKernelGGL(route_init, dim3(1), dim3(256), 0, st, w.state, w.loadbuf, c.E, price,
+  hipLaunchKernelGGL(route_init, dim3(1), dim3(256), 0, st, w.state, c.E, price,
                      c.price_mode, c.warm_gamma);
   if (c.T == 0) {
     hipLaunchKernelGGL(route_finalize, dim3(1), dim3(256), 0, st, w.state, info, load, c.E, 1);
@@ -729,9 +1058,15 @@ extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* 
   if (c.act == MOE_F32)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits<float>), g, dim3(256), 0, st,
                        (const float*)X, Wr, br, logits, w.sT, c.T, c.d, c.E);
-  else
+  else if (c.d % 32 != 0)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits<bf16_t>), g, dim3(256), 0, st,
                        (const bf16_t*)X, Wr, br, logits, w.sT, c.T, c.d, c.E);
+  else {
+    const int n = c.E * c.d;
+    hipLaunchKernelGGL(router_split, dim3((n + 255) / 256), dim3(256), 0, st, Wr, n, w.W3);
+    hipLaunchKernelGGL(router_logits_mfma, dim3((c.T + 127) / 128, (c.E + 63) / 64), dim3(256), 0,
+                       st, (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+  }
   PROF_END("router_logits", st);
   const int nb = (c.T + SIG_BLOCK - 1) / SIG_BLOCK;
   hipLaunchKernelGGL(score_partials, dim3(nb), dim3(SIG_BLOCK), 0, st, w.sT, c.T, c.E, w.part);

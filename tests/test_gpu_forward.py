@@ -22,6 +22,8 @@ pytestmark = pytest.mark.gpu
 
 MID = synth.MoEShape("bf16-ragged", T=3000, d=256, E=16, k=4, f=192, zipf=1.2, act="bf16", w="bf16")
 SMALL_BF16 = synth.MoEShape("bf16-tiny", T=200, d=128, E=8, k=2, f=64, zipf=1.0, act="bf16", w="bf16")
+# every expert GEMM on the 256-row tile path, several ragged row tiles per expert
+BIG_TILES = synth.MoEShape("bf16-bigtile", T=2100, d=512, E=8, k=2, f=384, zipf=1.1, act="bf16", w="bf16")
 
 
 def _run_route(shape, config, mode=L.MOE_PRICE_ACP, max_iters=None, price=None, rep=0):
@@ -132,6 +134,10 @@ def test_layer_forward_fp32_small_config():
 
 def test_layer_forward_bf16_ragged():
     _layer_check(MID, 18, 1.5e-2)
+
+
+def test_layer_forward_bf16_big_tiles():
+    _layer_check(BIG_TILES, 21, 1.5e-2)
 
 
 def test_layer_forward_bf16_tiny():
