@@ -162,12 +162,71 @@ moe_status moe_combine(const moe_cfg* cfg, const void* Y, const int32_t* inv_map
                        const float* topk_w, void* out, void* stream);
 
 /*
+ * Backward of the layer with the routing held fixed: the chosen experts and
+ * the prices that chose them are constants, so no gradient flows into the
+ * prices or through the selection; everything below is the exact derivative
+ * of the forward definitions above on that piece.
+ */
+
+/*
+ * moe_combine_bwd -- derivative of moe_combine.
+ *   dY[inv_map[t,j]] = topk_w[t,j] * dOut[t]          (act dtype)
+ *   dtopk_w[t,j]     = <dOut[t], Y[inv_map[t,j]]>     (FP32, fixed order)
+ *   dOut [T,d] act; Y [N,d] act (the forward's); dY [N,d] act out;
+ *   dtopk_w [T,k] f32 out.
+ */
+moe_status moe_combine_bwd(const moe_cfg* cfg, const void* dOut, const void* Y,
+                           const int32_t* inv_map, const float* topk_w, void* dY,
+                           float* dtopk_w, void* stream);
+
+/*
+ * moe_expert_ffn_bwd -- derivative of moe_expert_ffn for an upstream dY in
+ * slot order.  The permuted tokens are recomputed from X through row_map
+ * (not read from a saved X_perm), as are A = Xp W1^T and B = Xp W3^T:
+ *   U = dY W2_e,  dA = U * B * silu'(A),  dB = U * silu(A),  h = silu(A) * B
+ *   dX_perm = dA W1_e + dB W3_e              [N,d] act out
+ *   dW13[e] = [dA | dB]^T Xp                 [E,2f,d] f32 out
+ *   dW2[e]  = dY^T h                         [E,d,f] f32 out
+ * with silu'(z) = s + z s (1 - s), s = 1/(1+exp(-z)).  Requires BF16
+ * activations and weights, d_ff % 128 == 0 and d % 256 == 0 (otherwise
+ * MOE_EUNSUPPORTED).  X [T,d]; row_map [N]; offsets [E+1] from moe_dispatch.
+ */
+moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X, const int32_t* row_map,
+                              const int32_t* offsets, const void* dY, const void* W13,
+                              const void* W2, void* dX_perm, float* dW13, float* dW2, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/*
+ * moe_dispatch_bwd -- derivative of moe_dispatch's permute:
+ *   dX[t] = sum_j dX_perm[inv_map[t,j]]   (j order, FP32 out [T,d]).
+ */
+moe_status moe_dispatch_bwd(const moe_cfg* cfg, const void* dX_perm, const int32_t* inv_map,
+                            float* dX, void* stream);
+
+/*
+ * moe_route_bwd -- gate and router backward, fused with the permute
+ * backward into one dX:
+ *   ds[t,j] = w[t,j] (dw[t,j] - sum_i w[t,i] dw[t,i])   (softmax over the
+ *             chosen experts' raw logits; dw = dtopk_w)
+ *   dX[t]   = sum_j dX_perm[inv_map[t,j]] + sum_j ds[t,j] W_r[e_j]   (f32 out)
+ *   dWr[e]  = sum over the slots of e, in slot order, of ds * X[t]   [E,d] f32
+ *   dbr[e]  = sum of the same ds                                      [E] f32
+ *   (topk_idx, topk_w, row_map, offsets, inv_map as produced by the forward.)
+ */
+moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const float* Wr,
+                         const int32_t* topk_idx, const float* topk_w, const float* dtopk_w,
+                         const int32_t* row_map, const int32_t* offsets, const int32_t* inv_map,
+                         const void* dX_perm, float* dX, float* dWr, float* dbr, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/*
  * Optional per-kernel timing for benchmarks (host bookkeeping, not
  * thread-safe).  When enabled, each instrumented kernel launch is bracketed
  * by a HIP event pair on its stream.  moe_prof_get waits for the recorded
  * events and returns the summed elapsed time and the launch count of one
  * kernel name: "router_logits", "price_loop", "dispatch", "gemm1_swiglu",
- * "gemm2", "combine".  moe_prof_reset forgets every record.
+ * "gemm2", "combine", "combine_bwd", "ffn_bwd", "dispatch_bwd", "route_bwd".
+ * moe_prof_reset forgets every record.
  */
 moe_status moe_prof_enable(int on);
 moe_status moe_prof_reset(void);

@@ -55,6 +55,10 @@ SIGNATURES = {
     "moe_dispatch": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_expert_ffn": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_combine": [_CFG, _P, _P, _P, _P, _P],
+    "moe_combine_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P],
+    "moe_expert_ffn_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_dispatch_bwd": [_CFG, _P, _P, _P, _P],
+    "moe_route_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_prof_enable": [ctypes.c_int],
     "moe_prof_reset": [],
     "moe_prof_get": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)],
@@ -118,6 +122,28 @@ def moe_expert_ffn(cfg, X_perm, offsets, W13, W13_scale, W2, W2_scale, Y, ws, ws
 
 def moe_combine(cfg, Y, inv_map, topk_w, out, stream):
     _check(lib().moe_combine(ctypes.byref(cfg), Y, inv_map, topk_w, out, stream), "moe_combine")
+
+
+def moe_combine_bwd(cfg, dOut, Y, inv_map, topk_w, dY, dtopk_w, stream):
+    _check(lib().moe_combine_bwd(ctypes.byref(cfg), dOut, Y, inv_map, topk_w, dY, dtopk_w, stream),
+           "moe_combine_bwd")
+
+
+def moe_expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, dX_perm, dW13, dW2, ws, ws_bytes,
+                       stream):
+    _check(lib().moe_expert_ffn_bwd(ctypes.byref(cfg), X, row_map, offsets, dY, W13, W2, dX_perm,
+                                    dW13, dW2, ws, ws_bytes, stream), "moe_expert_ffn_bwd")
+
+
+def moe_dispatch_bwd(cfg, dX_perm, inv_map, dX, stream):
+    _check(lib().moe_dispatch_bwd(ctypes.byref(cfg), dX_perm, inv_map, dX, stream), "moe_dispatch_bwd")
+
+
+def moe_route_bwd(cfg, X, Wr, topk_idx, topk_w, dtopk_w, row_map, offsets, inv_map, dX_perm, dX,
+                  dWr, dbr, ws, ws_bytes, stream):
+    _check(lib().moe_route_bwd(ctypes.byref(cfg), X, Wr, topk_idx, topk_w, dtopk_w, row_map,
+                               offsets, inv_map, dX_perm, dX, dWr, dbr, ws, ws_bytes, stream),
+           "moe_route_bwd")
 
 
 def moe_prof_enable(on: bool) -> None:

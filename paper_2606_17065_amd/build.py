@@ -33,6 +33,7 @@ SOURCES = [
     ("route.hip", ["-ffp-contract=off"]),
     ("dispatch.hip", []),
     ("gemm.hip", []),
+    ("bwd.hip", []),
     ("api.cpp", []),
     ("prof.cpp", []),
 ]

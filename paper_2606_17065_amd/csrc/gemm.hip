@@ -10,7 +10,7 @@
 #include "common.h"
 #include "internal.h"
 
-namespace {
+namespace moe_gemm {
 
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
 
@@ -244,84 +244,27 @@ __device__ __forceinline__ void stage_barrier() {
   asm volatile("" ::: "memory");
 }
 
-template <bool SWIGLU>
-__global__ __launch_bounds__(256, 2) void gemm_bf16_big(
-    const bf16_t* __restrict__ A, const bf16_t* __restrict__ B, bf16_t* __restrict__ C,
-    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start, int E, int N,
-    int K, int f, int Ncols, int n_tiles, int grid_total) {
-  __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
-  const int b = blockIdx.x;
-  const int per = grid_total >> 3;
-  const int Lt = (b & 7) * per + (b >> 3);
-  int e, row0, rows, nt;
-  if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
-  const int n0 = nt * (SWIGLU ? 64 : 128);
-  const size_t Brows_e = SWIGLU ? (size_t)2 * f : (size_t)Ncols;
-  const bf16_t* Be = B + (size_t)e * Brows_e * K;
-
-  // DMA sources of this lane: wavefront wv fills token rows wv*64.. (A_INS
-  // instructions of 16 rows x 4 chunks) and weight rows wv*32.. (B_INS);
-  // lane -> (row + lane/4, slot lane%4)
-  const bf16_t* asrc[A_INS];
-  const bf16_t* bsrc[B_INS];
-#pragma unroll
-  for (int i = 0; i < A_INS; ++i) {
-    const int R = wv * (GBM / 4) + i * 16 + (lane >> 2);
-    const int c = (lane & 3) ^ swz(R);
-    asrc[i] = A + (size_t)(row0 + min(R, rows - 1)) * K + c * 8;
-  }
-#pragma unroll
-  for (int i = 0; i < B_INS; ++i) {
-    const int R = wv * (GBN / 4) + i * 16 + (lane >> 2);
-    const int c = (lane & 3) ^ swz(R);
-    const int wrow = SWIGLU ? (R < 64 ? n0 + R : f + n0 + (R - 64)) : n0 + R;
-    bsrc[i] = Be + (size_t)wrow * K + c * 8;
-  }
+// The pipelined main loop shared by every 256x128 kernel.  Each lane
+// brings its DMA source pointers (one per 16-row instruction, already at
+// its K-chunk); the loop adds kstep*32 elements to them.
+template <int AI, int BI>
+__device__ __forceinline__ void mma_pipeline(char* lds, const bf16_t* (&asrc)[AI],
+                                             const bf16_t* (&bsrc)[BI], int nk, int wv,
+                                             int lane, const int (&aoff)[4], const int (&asw)[4],
+                                             const int (&boff)[2], const int (&bsw)[2],
+                                             f32x16 (&acc)[4][2]) {
   typedef __attribute__((address_space(3))) void lds_void;
-  auto issue = [&](int kstep) {
-    char* st = lds + (kstep % NSTAGE) * STAGE_BYTES;
-    const int k0 = kstep * GBK;
-#pragma unroll
-    for (int i = 0; i < A_INS; ++i)
-      __builtin_amdgcn_global_load_lds(asrc[i] + k0,
-                                       (lds_void*)(st + (wv * (GBM / 4) + i * 16) * 64), 16, 0, 0);
-#pragma unroll
-    for (int i = 0; i < B_INS; ++i)
-      __builtin_amdgcn_global_load_lds(
-          bsrc[i] + k0, (lds_void*)(st + STAGE_A + (wv * (GBN / 4) + i * 16) * 64), 16, 0, 0);
-  };
-
-  f32x16 acc[4][2];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
-
-  const int fr = lane & 31, fh = lane >> 5;
-  int aoff[4], boff[2], asw[4], bsw[2];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int R = wm * 128 + i * 32 + fr;
-    aoff[i] = R * 64;
-    asw[i] = swz(R);
+  constexpr int VMS = AI + BI;
+  const int fh = lane >> 5;
+#define ISSUE(kstep)                                                                           \
+  {                                                                                            \
+    char* st_ = lds + ((kstep) % NSTAGE) * STAGE_BYTES;                                        \
+    const int k0_ = (kstep) * GBK;                                                             \
+    _Pragma("unroll") for (int i = 0; i < AI; ++i) __builtin_amdgcn_global_load_lds(           \
+        asrc[i] + k0_, (lds_void*)(st_ + (wv * (GBM / 4) + i * 16) * 64), 16, 0, 0);           \
+    _Pragma("unroll") for (int i = 0; i < BI; ++i) __builtin_amdgcn_global_load_lds(           \
+        bsrc[i] + k0_, (lds_void*)(st_ + STAGE_A + (wv * (GBN / 4) + i * 16) * 64), 16, 0, 0); \
   }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int R = SWIGLU ? (j == 0 ? wn * 32 : 64 + wn * 32) : wn * 64 + j * 32;
-    boff[j] = STAGE_A + (R + fr) * 64;
-    bsw[j] = swz(R + fr);
-  }
-
-  // Software pipeline over K steps of 32 = two MFMA sub-steps (ks = 0, 1)
-  // with fragment sets F0 (ks 0) and F1 (ks 1): the reads of the next
-  // fragments are in flight while the current ones feed the MFMAs; the
-  // stage barrier sits between the two halves of a step, and the load of
-  // step kt+3 goes into the stage step kt has just vacated.
-  const int nk = K / GBK;
 #define READ_FRAGS(AF, BF, stp, ks)                                                      \
   {                                                                                      \
     const char* st_ = lds + ((stp) % NSTAGE) * STAGE_BYTES;                              \
@@ -335,14 +278,15 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_big(
   _Pragma("unroll") for (int i = 0; i < 4; ++i) _Pragma("unroll") for (int j = 0; j < 2; \
                                                                        ++j) acc[i][j] =  \
       __builtin_amdgcn_mfma_f32_32x32x16_bf16(BF[j], AF[i], acc[i][j], 0, 0, 0);
+  if (nk <= 0) return;
   bf16x8 a0[4], b0[2], a1[4], b1[2];
-  issue(0);
-  if (nk > 1) issue(1);
-  if (nk > 2) issue(2);
+  ISSUE(0);
+  if (nk > 1) ISSUE(1);
+  if (nk > 2) ISSUE(2);
   if (nk > 2) {
-    WAIT_VM_LGKM0(2 * VM_PER_STAGE);
+    WAIT_VM_LGKM0(2 * VMS);
   } else if (nk > 1) {
-    WAIT_VM_LGKM0(VM_PER_STAGE);
+    WAIT_VM_LGKM0(VMS);
   } else {
     WAIT_VM_LGKM0(0);
   }
@@ -353,42 +297,129 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_big(
     MFMA8(a0, b0);
     // step kt+1 must have landed: at most step kt+2 remains in flight
     if (kt + 2 < nk) {
-      WAIT_VM_LGKM0(VM_PER_STAGE);
+      WAIT_VM_LGKM0(VMS);
     } else {
       WAIT_VM_LGKM0(0);
     }
     stage_barrier();  // every wavefront's reads of stage kt are done
-    if (kt + 3 < nk) issue(kt + 3);
+    if (kt + 3 < nk) ISSUE(kt + 3);
     READ_FRAGS(a0, b0, kt + 1, 0);
     MFMA8(a1, b1);
   }
   READ_FRAGS(a1, b1, nk - 1, 1);
   MFMA8(a0, b0);
   MFMA8(a1, b1);
+#undef ISSUE
 #undef READ_FRAGS
 #undef MFMA8
+}
+
+// Fragment LDS offsets of a wavefront (wm, wn): token rows wm*128 + 32i +
+// lane%32; weight rows from the two column tiles brow0, brow1.
+__device__ __forceinline__ void frag_offsets(int wm, int brow0, int brow1, int lane,
+                                             int (&aoff)[4], int (&asw)[4], int (&boff)[2],
+                                             int (&bsw)[2]) {
+  const int fr = lane & 31;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int R = wm * 128 + i * 32 + fr;
+    aoff[i] = R * 64;
+    asw[i] = swz(R);
+  }
+  boff[0] = STAGE_A + (brow0 + fr) * 64;
+  bsw[0] = swz(brow0 + fr);
+  boff[1] = STAGE_A + (brow1 + fr) * 64;
+  bsw[1] = swz(brow1 + fr);
+}
+
+__device__ __forceinline__ void zero_acc(f32x16 (&acc)[4][2]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
+}
+
+// Epilogue modes of the row-grouped kernel.
+enum { EPI_SWIGLU = 0, EPI_PLAIN = 1, EPI_AB = 2 };
+
+// Row-grouped kernel (rows of each expert against that expert's weights).
+//   EPI_SWIGLU: B-tile = 64 W1 rows + the 64 matching W3 rows; stores
+//               h = silu(A) * B (bf16, row length f).
+//   EPI_PLAIN : B-tile = 128 weight rows; stores the product (bf16).
+//   EPI_AB    : as EPI_SWIGLU but stores A and B themselves (bf16, row
+//               length 2f: A at column n, B at column f + n).
+// GATHER: token row r of the A operand is X[row_map[r]] (the permute is
+// recomputed instead of read).
+template <int EPI, bool GATHER>
+__global__ __launch_bounds__(256, 2) void gemm_bf16_big(
+    const bf16_t* __restrict__ A, const int32_t* __restrict__ row_map, int T,
+    const bf16_t* __restrict__ B, bf16_t* __restrict__ C, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ tile_start, int E, int N, int K, int f, int Ncols, int n_tiles,
+    int grid_total) {
+  constexpr bool PAIRED = EPI != EPI_PLAIN;  // B-tile holds W1/W3 halves
+  __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
+  const int b = blockIdx.x;
+  const int per = grid_total >> 3;
+  const int Lt = (b & 7) * per + (b >> 3);
+  int e, row0, rows, nt;
+  if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int n0 = nt * (PAIRED ? 64 : 128);
+  const size_t Brows_e = PAIRED ? (size_t)2 * f : (size_t)Ncols;
+  const bf16_t* Be = B + (size_t)e * Brows_e * K;
+
+  // DMA sources: wavefront wv fills token rows wv*64.. (A_INS instructions
+  // of 16 rows x 4 chunks) and weight rows wv*32.. (B_INS); lane -> (row +
+  // lane/4, slot lane%4)
+  const bf16_t* asrc[A_INS];
+  const bf16_t* bsrc[B_INS];
+#pragma unroll
+  for (int i = 0; i < A_INS; ++i) {
+    const int R = wv * (GBM / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    const int r = row0 + min(R, rows - 1);
+    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
+    asrc[i] = A + arow * K + c * 8;
+  }
+#pragma unroll
+  for (int i = 0; i < B_INS; ++i) {
+    const int R = wv * (GBN / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    const int wrow = PAIRED ? (R < 64 ? n0 + R : f + n0 + (R - 64)) : n0 + R;
+    bsrc[i] = Be + (size_t)wrow * K + c * 8;
+  }
+  int aoff[4], asw[4], boff[2], bsw[2];
+  frag_offsets(wm, PAIRED ? wn * 32 : wn * 64, PAIRED ? 64 + wn * 32 : wn * 64 + 32, lane, aoff,
+               asw, boff, bsw);
+  f32x16 acc[4][2];
+  zero_acc(acc);
+  mma_pipeline<A_INS, B_INS>(lds, asrc, bsrc, K / GBK, wv, lane, aoff, asw, boff, bsw, acc);
   WAIT_VM_LGKM0(0);
   stage_barrier();
 
-  // epilogue through LDS: lane owns token row (i*32 + fr) and columns
+  // epilogue through LDS: lane owns token row (i*32 + lane%32) and columns
   // 8*(q/4) + 4*(lane/32) + (q%4) of each 32-wide column tile
-  constexpr int CS = SWIGLU ? 64 : 128;
+  constexpr int CS = EPI == EPI_SWIGLU ? 64 : 128;
   constexpr int CLD = CS + 8;
   bf16_t* Cs = (bf16_t*)lds;
-  const int cbase = fh * 4;
+  const int fr = lane & 31, cbase = (lane >> 5) * 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int rl = wm * 128 + i * 32 + fr;
 #pragma unroll
-    for (int j = 0; j < (SWIGLU ? 1 : 2); ++j) {
-      const int col0 = SWIGLU ? wn * 32 : wn * 64 + j * 32;
+    for (int j = 0; j < (EPI == EPI_SWIGLU ? 1 : 2); ++j) {
+      // EPI_AB keeps the A half in columns 0..63 and the B half in 64..127
+      const int col0 = EPI == EPI_SWIGLU ? wn * 32 : (EPI == EPI_AB ? j * 64 + wn * 32 : wn * 64 + j * 32);
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         bf16x4 v;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const float x = acc[i][j][g * 4 + q];
-          if (SWIGLU) {
+          if (EPI == EPI_SWIGLU) {
             const float y = acc[i][1][g * 4 + q];
             v[q] = (bf16_t)(silu(x) * y);
           } else {
@@ -401,12 +432,271 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_big(
   }
   __syncthreads();
   constexpr int CPR = CS / 8;  // 16-byte chunks per row
-  const int n0c = nt * CS;
   for (int c = tid; c < GBM * CPR; c += 256) {
     const int rr = c / CPR, cc = (c - rr * CPR) * 8;
-    if (rr < rows)
-      *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + n0c + cc) = *(const u32x4*)(Cs + rr * CLD + cc);
+    if (rr >= rows) continue;
+    size_t col;
+    if (EPI == EPI_AB) col = cc < 64 ? (size_t)n0 + cc : (size_t)f + n0 + (cc - 64);
+    else col = (size_t)nt * CS + cc;
+    *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + col) = *(const u32x4*)(Cs + rr * CLD + cc);
   }
+}
+
+// Explicit instantiations: clang's host pass does not emit the launch stubs
+// of these kernel templates when they are only instantiated implicitly.
+#define MOE_INST_BIG(EPI, GATHER)                                                          \
+  template __global__ void gemm_bf16_big<EPI, GATHER>(                                     \
+      const bf16_t* __restrict__, const int32_t* __restrict__, int, const bf16_t* __restrict__, \
+      bf16_t* __restrict__, const int32_t* __restrict__, const int32_t* __restrict__, int, int, \
+      int, int, int, int, int);
+MOE_INST_BIG(EPI_SWIGLU, false)
+MOE_INST_BIG(EPI_PLAIN, false)
+MOE_INST_BIG(EPI_AB, true)
+#undef MOE_INST_BIG
+
+// ------------------------------------------------------------- backward
+// Recompute-based backward of the expert FFN for the rows of each expert
+// (dY = w * dOut in slot order, supplied by the combine backward):
+//   [A|B] = Xp W13^T               (gemm_bf16_big<EPI_AB, gather>)
+//   U = dY W2  -> h = silu(A) B, dA = U B silu'(A), dB = U silu(A)
+//                                   (gemm_dgrad1, reading [A|B])
+//   dX_perm = [dA|dB] W13          (gemm_bf16_big<EPI_PLAIN> on W13^T)
+//   dW13_e = [dA|dB]^T Xp,  dW2_e = dY^T h          (gemm_wgrad)
+// Every product is "NT" with both operands contiguous along the reduction:
+// the weights are transposed once per call, and the activations that the
+// weight gradients reduce over are written transposed [channel][slot] with
+// each expert's slot range padded to a multiple of 32 with zeros.
+
+// One epilogue pass of gemm_dgrad1: PASS 0 = dA, 1 = dB, 2 = h.  Values
+// go to LDS transposed [column][row]; dA and dB also go row-major to dAB.
+template <int PASS>
+__device__ __forceinline__ void dgrad1_pass(const f32x16 (&acc)[4][2], char* lds,
+                                            const bf16_t* __restrict__ AB, bf16_t* __restrict__ dAB,
+                                            bf16_t* __restrict__ dst, int ldT, int row0, int rows,
+                                            int n0, int f, size_t pcol0, int wm, int wn, int tid,
+                                            int lane) {
+  constexpr int TLD = GBM + 8;
+  bf16_t* Ls = (bf16_t*)lds;
+  const int fr = lane & 31, cbase = (lane >> 5) * 4;
+  const size_t ld2f = (size_t)2 * f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rl = wm * 128 + i * 32 + fr;
+    const size_t row = (size_t)(row0 + min(rl, rows - 1));
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int cl = wn * 64 + j * 32 + g * 8 + cbase;
+        const int n = n0 + cl;
+        const bf16x4 av = *(const bf16x4*)(AB + row * ld2f + n);
+        const bf16x4 bv = *(const bf16x4*)(AB + row * ld2f + f + n);
+        bf16x4 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float u = acc[i][j][g * 4 + q];
+          const float a = (float)av[q], bb = (float)bv[q];
+          const float sg = 1.0f / (1.0f + __expf(-a));
+          const float sa = a * sg;
+          float v;
+          if (PASS == 0) v = u * bb * (sg + sa * (1.0f - sg));  // dA
+          else if (PASS == 1) v = u * sa;                       // dB
+          else v = sa * bb;                                      // h
+          o[q] = (bf16_t)v;
+          Ls[(cl + q) * TLD + rl] = o[q];
+        }
+        if (PASS < 2 && rl < rows)
+          *(bf16x4*)(dAB + (size_t)(row0 + rl) * ld2f + (PASS == 0 ? 0 : f) + n) = o;
+      }
+      // keep the loads of later groups from being hoisted here (they would
+      // not fit in registers next to the accumulators)
+      asm volatile("" ::: "memory");
+    }
+  }
+  __syncthreads();
+  const size_t rbase = PASS == 1 ? (size_t)f + n0 : (size_t)n0;
+  for (int cidx = tid; cidx < 128 * (GBM / 8); cidx += 256) {
+    const int cl = cidx / (GBM / 8), r8 = (cidx - cl * (GBM / 8)) * 8;
+    if (r8 < rows)
+      *(u32x4*)(dst + (rbase + cl) * ldT + pcol0 + r8) = *(const u32x4*)(Ls + cl * TLD + r8);
+  }
+  __syncthreads();
+}
+
+// U tile = dY rows x 128 columns of f (weight rows of W2^T_e); epilogue
+// computes dA, dB, h and writes dAB row-major plus dAB^T and h^T.
+__global__ __launch_bounds__(256, 1) void gemm_dgrad1(
+    const bf16_t* __restrict__ dY, const bf16_t* __restrict__ W2T, const bf16_t* __restrict__ AB,
+    bf16_t* __restrict__ dAB, bf16_t* __restrict__ dABT, bf16_t* __restrict__ hT, int ldT,
+    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start,
+    const int32_t* __restrict__ ptile, int E, int N, int d, int f, int n_tiles, int grid_total) {
+  __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
+  const int b = blockIdx.x;
+  const int per = grid_total >> 3;
+  const int Lt = (b & 7) * per + (b >> 3);
+  int e, row0, rows, nt;
+  if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int n0 = nt * 128;
+  const bf16_t* Be = W2T + (size_t)e * f * d;
+  const bf16_t* asrc[A_INS];
+  const bf16_t* bsrc[B_INS];
+#pragma unroll
+  for (int i = 0; i < A_INS; ++i) {
+    const int R = wv * (GBM / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    asrc[i] = dY + (size_t)(row0 + min(R, rows - 1)) * d + c * 8;
+  }
+#pragma unroll
+  for (int i = 0; i < B_INS; ++i) {
+    const int R = wv * (GBN / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    bsrc[i] = Be + (size_t)(n0 + R) * d + c * 8;
+  }
+  int aoff[4], asw[4], boff[2], bsw[2];
+  frag_offsets(wm, wn * 64, wn * 64 + 32, lane, aoff, asw, boff, bsw);
+  f32x16 acc[4][2];
+  zero_acc(acc);
+  mma_pipeline<A_INS, B_INS>(lds, asrc, bsrc, d / GBK, wv, lane, aoff, asw, boff, bsw, acc);
+  WAIT_VM_LGKM0(0);
+  stage_barrier();
+
+  // three passes through LDS (dA, dB, h), each staged transposed [col][row]
+  const size_t pcol0 = (size_t)ptile[e] * 32 + (size_t)(row0 - offsets[e]);
+  dgrad1_pass<0>(acc, lds, AB, dAB, dABT, ldT, row0, rows, n0, f, pcol0, wm, wn, tid, lane);
+  dgrad1_pass<1>(acc, lds, AB, dAB, dABT, ldT, row0, rows, n0, f, pcol0, wm, wn, tid, lane);
+  dgrad1_pass<2>(acc, lds, AB, dAB, hT, ldT, row0, rows, n0, f, pcol0, wm, wn, tid, lane);
+}
+
+// Weight gradient of one expert: out_e[m][n] = sum over the expert's padded
+// slot range of At[m][k] * Bt[n][k] (both [rows][ldT], contiguous along k;
+// pads are zero).  Tile 256 x 128, FP32 results stored directly.
+__global__ __launch_bounds__(256, 2) void gemm_wgrad(const bf16_t* __restrict__ At,
+                                                     const bf16_t* __restrict__ Bt, int ldT,
+                                                     const int32_t* __restrict__ ptile, int E,
+                                                     int M, int Nn, float* __restrict__ out,
+                                                     int m_tiles, int n_tiles, int grid_total) {
+  __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
+  const int b = blockIdx.x;
+  const int per = grid_total >> 3;
+  const int Lt = (b & 7) * per + (b >> 3);
+  const int tiles_e = m_tiles * n_tiles;
+  if (Lt >= E * tiles_e) return;
+  const int e = Lt / tiles_e, rem = Lt - e * tiles_e;
+  const int mt = rem / n_tiles, nt = rem - mt * n_tiles;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const size_t k0 = (size_t)ptile[e] * 32;
+  const int nk = ptile[e + 1] - ptile[e];
+  const bf16_t* asrc[A_INS];
+  const bf16_t* bsrc[B_INS];
+#pragma unroll
+  for (int i = 0; i < A_INS; ++i) {
+    const int R = wv * (GBM / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    asrc[i] = At + (size_t)(mt * GBM + R) * ldT + k0 + c * 8;
+  }
+#pragma unroll
+  for (int i = 0; i < B_INS; ++i) {
+    const int R = wv * (GBN / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    bsrc[i] = Bt + (size_t)(nt * GBN + R) * ldT + k0 + c * 8;
+  }
+  int aoff[4], asw[4], boff[2], bsw[2];
+  frag_offsets(wm, wn * 64, wn * 64 + 32, lane, aoff, asw, boff, bsw);
+  f32x16 acc[4][2];
+  zero_acc(acc);
+  mma_pipeline<A_INS, B_INS>(lds, asrc, bsrc, nk, wv, lane, aoff, asw, boff, bsw, acc);
+  const int fr = lane & 31, cbase = (lane >> 5) * 4;
+  float* oe = out + (size_t)e * M * Nn;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const size_t m = (size_t)mt * GBM + wm * 128 + i * 32 + fr;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int n = nt * GBN + wn * 64 + j * 32 + g * 8 + cbase;
+        f32x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = acc[i][j][g * 4 + q];
+        *(f32x4*)(oe + m * Nn + n) = v;
+      }
+  }
+}
+
+// out[b][c][r] = in[b][r][c], 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void batched_transpose(const bf16_t* __restrict__ in,
+                                                         bf16_t* __restrict__ out, int R, int C) {
+  __shared__ bf16_t tile[64][64 + 2];
+  const size_t base = (size_t)blockIdx.z * R * C;
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int r = i >> 6, c = i & 63;
+    if (r0 + r < R && c0 + c < C) tile[r][c] = in[base + (size_t)(r0 + r) * C + c0 + c];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int c = i >> 6, r = i & 63;
+    if (r0 + r < R && c0 + c < C) out[base + (size_t)(c0 + c) * R + r0 + r] = tile[r][c];
+  }
+}
+
+// outT[c][p] for padded slot positions p: the source row of slot
+// offsets[e] + (p - pad_off[e]) (through row_map when gathering), or zero in
+// an expert's pad.  64 positions x 64 channels per block.
+__global__ __launch_bounds__(256) void slot_transpose(const bf16_t* __restrict__ src,
+                                                      const int32_t* __restrict__ row_map, int T,
+                                                      int C, const int32_t* __restrict__ offsets,
+                                                      const int32_t* __restrict__ ptile, int E,
+                                                      bf16_t* __restrict__ outT, int ldT) {
+  __shared__ bf16_t tile[64][64 + 2];
+  __shared__ int srow[64];
+  const int p0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const int total = ptile[E] * 32;
+  if (p0 >= total) return;
+  if (threadIdx.x < 64) {
+    const int p = p0 + threadIdx.x;
+    int r = -1;
+    if (p < total) {
+      int lo = 0, hi = E - 1;  // largest e with pad_off[e] <= p
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ptile[mid] * 32 <= p) lo = mid;
+        else hi = mid - 1;
+      }
+      const int i = p - ptile[lo] * 32;
+      if (i < offsets[lo + 1] - offsets[lo]) {
+        r = offsets[lo] + i;
+        if (row_map) r = min(max(row_map[r], 0), T - 1);
+      }
+    }
+    srow[threadIdx.x] = r;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int pl = i >> 6, c = i & 63;
+    const int r = srow[pl];
+    tile[pl][c] = (r >= 0 && c0 + c < C) ? src[(size_t)r * C + c0 + c] : (bf16_t)0.0f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int c = i >> 6, pl = i & 63;
+    if (c0 + c < C && p0 + pl < total) outT[(size_t)(c0 + c) * ldT + p0 + pl] = tile[pl][c];
+  }
+}
+
+// Zero each expert's pad columns [pad_off[e] + rows_e, pad_off[e+1]) of a
+// transposed buffer with M rows.
+__global__ __launch_bounds__(256) void pad_zero(bf16_t* __restrict__ buf, int M, int ldT,
+                                                const int32_t* __restrict__ offsets,
+                                                const int32_t* __restrict__ ptile) {
+  const int e = blockIdx.x;
+  const int m = blockIdx.y * 256 + threadIdx.x;
+  if (m >= M) return;
+  const int a = ptile[e] * 32 + (offsets[e + 1] - offsets[e]), z = ptile[e + 1] * 32;
+  for (int p = a; p < z; ++p) buf[(size_t)m * ldT + p] = (bf16_t)0.0f;
 }
 
 // ---------------------------------------------------------------- FP32 SIMT
@@ -501,7 +791,8 @@ FfnWs carve_ffn(const moe_cfg& c, void* base, size_t* total) {
   return r;
 }
 
-}  // namespace
+}  // namespace moe_gemm
+using namespace moe_gemm;
 
 size_t ffn_ws_bytes(const moe_cfg& c) {
   size_t total = 0;
@@ -546,9 +837,9 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
     if (big1) {
       const int nt = c.d_ff / 64;
       const int G = (mt_big * nt + 7) / 8 * 8;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<true>), dim3(G), dim3(256), 0, st,
-                         (const bf16_t*)X_perm, (const bf16_t*)W13, (bf16_t*)w.h, offsets,
-                         w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt, G);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_SWIGLU, false>), dim3(G), dim3(256), 0,
+                         st, (const bf16_t*)X_perm, nullptr, 0, (const bf16_t*)W13, (bf16_t*)w.h,
+                         offsets, w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt, G);
     } else {
       dim3 g1((N + BM - 1) / BM + c.E, c.d_ff / 64);
       hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16<true>), g1, dim3(256), 0, st,
@@ -560,8 +851,8 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
     if (big2) {
       const int nt = c.d / 128;
       const int G = (mt_big * nt + 7) / 8 * 8;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<false>), dim3(G), dim3(256), 0, st,
-                         (const bf16_t*)w.h, (const bf16_t*)W2, (bf16_t*)Y, offsets,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_PLAIN, false>), dim3(G), dim3(256), 0,
+                         st, (const bf16_t*)w.h, nullptr, 0, (const bf16_t*)W2, (bf16_t*)Y, offsets,
                          w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt, G);
     } else {
       dim3 g2((N + BM - 1) / BM + c.E, c.d / 128);
@@ -585,6 +876,123 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
                        c.d);
     PROF_END("gemm2", st);
   }
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+namespace moe_gemm {
+
+struct FfnBwdWs {
+  int32_t* tile_start;
+  int32_t* ptile;
+  bf16_t *W13T, *W2T, *AB, *dAB, *dABT, *hT, *XpT, *dYT;
+  int ldT;
+};
+
+// Row pitch of the transposed slot-major buffers: every expert's slot range
+// padded to a multiple of 32, rounded up to 64 elements.
+int bwd_ldT(const moe_cfg& c) {
+  const size_t N = (size_t)c.T * c.k;
+  return (int)align_up(N + (size_t)32 * c.E, 64);
+}
+
+FfnBwdWs carve_ffn_bwd(const moe_cfg& c, void* base, size_t* total) {
+  WsCarve wc{(char*)base, 0};
+  FfnBwdWs r;
+  const size_t N = (size_t)c.T * c.k, d = c.d, f = c.d_ff, E = c.E;
+  r.ldT = bwd_ldT(c);
+  r.tile_start = wc.take<int32_t>(E + 1);
+  r.ptile = wc.take<int32_t>(E + 1);
+  r.W13T = wc.take<bf16_t>(E * 2 * f * d);
+  r.W2T = wc.take<bf16_t>(E * f * d);
+  r.AB = wc.take<bf16_t>(N * 2 * f);
+  r.dAB = wc.take<bf16_t>(N * 2 * f);
+  r.dABT = wc.take<bf16_t>(2 * f * r.ldT);
+  r.hT = wc.take<bf16_t>(f * r.ldT);
+  r.XpT = wc.take<bf16_t>(d * r.ldT);
+  r.dYT = wc.take<bf16_t>(d * r.ldT);
+  if (total) *total = align_up(wc.off, 256);
+  return r;
+}
+
+}  // namespace moe_gemm
+using namespace moe_gemm;
+
+size_t ffn_bwd_ws_bytes(const moe_cfg& c) {
+  size_t total = 0;
+  carve_ffn_bwd(c, nullptr, &total);
+  return total;
+}
+
+extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
+                                         const int32_t* row_map, const int32_t* offsets,
+                                         const void* dY, const void* W13, const void* W2,
+                                         void* dX_perm, float* dW13, float* dW2, void* ws,
+                                         size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.act != MOE_BF16 || c.w != MOE_BF16) return MOE_EUNSUPPORTED;
+  if (c.d_ff % 128 != 0 || c.d % 256 != 0) return MOE_EUNSUPPORTED;
+  if (!offsets || !W13 || !W2 || !dW13 || !dW2) return MOE_EINVAL;
+  if (c.T > 0 && (!X || !row_map || !dY || !dX_perm)) return MOE_EINVAL;
+  if (!aligned(X, 16) || !aligned(dY, 16) || !aligned(W13, 16) || !aligned(W2, 16) ||
+      !aligned(dX_perm, 16) || !aligned(dW13, 16) || !aligned(dW2, 16) || !aligned(offsets, 4) ||
+      !aligned(row_map, 4))
+    return MOE_EINVAL;
+  if (ws_bytes < ffn_bwd_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  FfnBwdWs w = carve_ffn_bwd(c, ws, nullptr);
+  const int N = c.T * c.k, d = c.d, f = c.d_ff, E = c.E;
+  const bf16_t* Xb = (const bf16_t*)X;
+  const bf16_t* dYb = (const bf16_t*)dY;
+  PROF_BEGIN("ffn_bwd", st);
+  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, GBM, w.tile_start);
+  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, 32, w.ptile);
+  hipLaunchKernelGGL(batched_transpose, dim3(d / 64, 2 * f / 64, E), dim3(256), 0, st,
+                     (const bf16_t*)W13, w.W13T, 2 * f, d);
+  hipLaunchKernelGGL(batched_transpose, dim3(f / 64, d / 64, E), dim3(256), 0, st,
+                     (const bf16_t*)W2, w.W2T, d, f);
+  const int mt = (N + GBM - 1) / GBM + E;
+  if (N > 0) {
+    {  // [A|B] = Xp W13^T with the permute recomputed
+      const int nt = f / 64, G = (mt * nt + 7) / 8 * 8;
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_AB, true>), dim3(G), dim3(256), 0, st,
+                         Xb, row_map, c.T, (const bf16_t*)W13, w.AB, offsets, w.tile_start, E, N,
+                         d, f, 2 * f, nt, G);
+    }
+    {  // U = dY W2, then dA, dB, h
+      const int nt = f / 128, G = (mt * nt + 7) / 8 * 8;
+      hipLaunchKernelGGL(gemm_dgrad1, dim3(G), dim3(256), 0, st, dYb, w.W2T, w.AB, w.dAB, w.dABT,
+                         w.hT, w.ldT, offsets, w.tile_start, w.ptile, E, N, d, f, nt, G);
+    }
+    {  // dX_perm = [dA|dB] W13
+      const int nt = d / 128, G = (mt * nt + 7) / 8 * 8;
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_PLAIN, false>), dim3(G), dim3(256), 0,
+                         st, w.dAB, nullptr, 0, w.W13T, (bf16_t*)dX_perm, offsets, w.tile_start, E,
+                         N, 2 * f, f, d, nt, G);
+    }
+    const int pblocks = (w.ldT + 63) / 64;
+    hipLaunchKernelGGL(slot_transpose, dim3(pblocks, d / 64), dim3(256), 0, st, Xb, row_map, c.T,
+                       d, offsets, w.ptile, E, w.XpT, w.ldT);
+    hipLaunchKernelGGL(slot_transpose, dim3(pblocks, d / 64), dim3(256), 0, st, dYb, nullptr, N,
+                       d, offsets, w.ptile, E, w.dYT, w.ldT);
+    hipLaunchKernelGGL(pad_zero, dim3(E, (2 * f + 255) / 256), dim3(256), 0, st, w.dABT, 2 * f,
+                       w.ldT, offsets, w.ptile);
+    hipLaunchKernelGGL(pad_zero, dim3(E, (f + 255) / 256), dim3(256), 0, st, w.hT, f, w.ldT,
+                       offsets, w.ptile);
+  }
+  {  // dW13_e = [dA|dB]^T Xp (M = 2f, N = d); dW2_e = dY^T h (M = d, N = f)
+    const int m1 = 2 * f / GBM, n1 = d / GBN;
+    const int G1 = (E * m1 * n1 + 7) / 8 * 8;
+    hipLaunchKernelGGL(gemm_wgrad, dim3(G1), dim3(256), 0, st, w.dABT, w.XpT, w.ldT, w.ptile, E,
+                       2 * f, d, dW13, m1, n1, G1);
+    const int m2 = d / GBM, n2 = f / GBN;
+    const int G2 = (E * m2 * n2 + 7) / 8 * 8;
+    hipLaunchKernelGGL(gemm_wgrad, dim3(G2), dim3(256), 0, st, w.dYT, w.hT, w.ldT, w.ptile, E, d,
+                       f, dW2, m2, n2, G2);
+  }
+  PROF_END("ffn_bwd", st);
   MOE_LAUNCH_CHECK();
   return MOE_OK;
 }

@@ -116,3 +116,76 @@ def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None):
     r["Y"] = Y
     r["out"] = out
     return r
+
+
+# ----------------------------------------------------------------- backward
+
+def combine_bwd(cfg, dOut, Y, inv_map, w):
+    T, d, k = cfg.T, cfg.d, cfg.k
+    _need(dOut, "dOut", _DT[cfg.act], (T, d))
+    _need(Y, "Y", _DT[cfg.act], (T * k, d))
+    dY = torch.empty_like(Y)
+    dw = torch.empty(T, k, dtype=torch.float32, device=Y.device)
+    L.moe_combine_bwd(cfg, _p(dOut), _p(Y), _p(inv_map), _p(w), _p(dY), _p(dw), _stream())
+    return dY, dw
+
+
+def expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, ws=None):
+    N, d, E, f = cfg.T * cfg.k, cfg.d, cfg.E, cfg.d_ff
+    _need(X, "X", _DT[cfg.act], (cfg.T, d))
+    _need(dY, "dY", _DT[cfg.act], (N, d))
+    dev = X.device
+    dXp = torch.empty(N, d, dtype=X.dtype, device=dev)
+    dW13 = torch.empty(E, 2 * f, d, dtype=torch.float32, device=dev)
+    dW2 = torch.empty(E, d, f, dtype=torch.float32, device=dev)
+    ws = _WS.get(cfg, dev) if ws is None else ws
+    L.moe_expert_ffn_bwd(cfg, _p(X), _p(row_map), _p(offsets), _p(dY), _p(W13), _p(W2), _p(dXp),
+                         _p(dW13), _p(dW2), _p(ws), ws.numel(), _stream())
+    return dXp, dW13, dW2
+
+
+def dispatch_bwd(cfg, dXp, inv_map):
+    dX = torch.empty(cfg.T, cfg.d, dtype=torch.float32, device=dXp.device)
+    L.moe_dispatch_bwd(cfg, _p(dXp), _p(inv_map), _p(dX), _stream())
+    return dX
+
+
+def route_bwd(cfg, X, Wr, idx, w, dw, row_map, offsets, inv_map, dXp, ws=None):
+    dev = X.device
+    dX = torch.empty(cfg.T, cfg.d, dtype=torch.float32, device=dev)
+    dWr = torch.empty(cfg.E, cfg.d, dtype=torch.float32, device=dev)
+    dbr = torch.empty(cfg.E, dtype=torch.float32, device=dev)
+    ws = _WS.get(cfg, dev) if ws is None else ws
+    L.moe_route_bwd(cfg, _p(X), _p(Wr), _p(idx), _p(w), _p(dw), _p(row_map), _p(offsets),
+                    _p(inv_map), _p(dXp), _p(dX), _p(dWr), _p(dbr), _p(ws), ws.numel(), _stream())
+    return dX, dWr, dbr
+
+
+class MoEFunction(torch.autograd.Function):
+    """The layer as one differentiable op.  Saves X, the routing (indices,
+    gate weights, slot maps) and Y; the permuted tokens and the first expert
+    GEMM are recomputed in the backward.  Gradients flow to X, W_r, b_r, W13
+    and W2; none flows into the prices or through the expert selection."""
+
+    @staticmethod
+    def forward(ctx, X, Wr, br, W13, W2, cfg):
+        r = forward(cfg, X, Wr, br, W13, W2)
+        ctx.cfg = cfg
+        ctx.save_for_backward(X, Wr, W13, W2, r["idx"], r["w"], r["row_map"], r["offsets"],
+                              r["inv_map"], r["Y"])
+        return r["out"]
+
+    @staticmethod
+    def backward(ctx, dOut):
+        X, Wr, W13, W2, idx, w, row_map, offsets, inv_map, Y = ctx.saved_tensors
+        cfg = ctx.cfg
+        dOut = dOut.to(Y.dtype).contiguous()
+        dY, dw = combine_bwd(cfg, dOut, Y, inv_map, w)
+        dXp, dW13, dW2 = expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2)
+        dX, dWr, dbr = route_bwd(cfg, X, Wr, idx, w, dw, row_map, offsets, inv_map, dXp)
+        return (dX.to(X.dtype), dWr, dbr, dW13.to(W13.dtype), dW2.to(W2.dtype), None)
+
+
+def moe_layer(cfg, X, Wr, br, W13, W2):
+    """Differentiable layer forward (see MoEFunction)."""
+    return MoEFunction.apply(X, Wr, br, W13, W2, cfg)

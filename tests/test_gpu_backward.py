@@ -1,0 +1,155 @@
+"""GPU parity of the layer backward against the FP64 oracle gradient
+(oracle.grad, itself pinned by central differences), through the C ABI.
+
+Tolerances (relative Frobenius against FP64): BF16 activations, weights and
+stored intermediates (h, dA, dB, dY) give about 2^-8 per element, so
+gradients are held to 2e-2; the FP32 dot products of the combine backward
+(dw) to 1e-5 given the GPU's own Y.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import grad, routing as R
+from paper_2606_17065_amd import layer, synth
+
+from _helpers import cfg_for, device_inputs, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+# d % 256 == 0 and f % 128 == 0 (the backward GEMM tiling); ragged experts
+BWD = synth.MoEShape("bf16-bwd", T=1500, d=256, E=8, k=2, f=256, zipf=1.2, act="bf16", w="bf16")
+BWD2 = synth.MoEShape("bf16-bwd-k4", T=1100, d=512, E=16, k=4, f=384, zipf=1.3, act="bf16", w="bf16")
+
+
+def _setup(shape, config):
+    inp = synth.make_inputs(shape, config)
+    d, h = device_inputs(shape, inp)
+    cfg = cfg_for(shape)
+    fw = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"])
+    dOut = torch.from_numpy(synth.make_upstream(shape.T, shape.d, config)).to(torch.bfloat16).cuda()
+    torch.cuda.synchronize()
+    return cfg, d, h, fw, dOut
+
+
+@pytest.mark.parametrize("shape,config", [(BWD, 31), (BWD2, 32)])
+def test_backward_pieces_match_oracle(shape, config):
+    cfg, d, h, fw, dOut = _setup(shape, config)
+    dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
+    dXp, dW13, dW2 = layer.expert_ffn_bwd(cfg, d["X"], fw["row_map"], fw["offsets"], dY, d["W13"],
+                                          d["W2"])
+    dX, dWr, dbr = layer.route_bwd(cfg, d["X"], d["Wr"], fw["idx"], fw["w"], dw, fw["row_map"],
+                                   fw["offsets"], fw["inv_map"], dXp)
+    torch.cuda.synchronize()
+    sel = fw["idx"].cpu().numpy()
+    dO = dOut.float().cpu().double().numpy()
+    ref = grad.layer_backward(h["X"], h["Wr"], h["br"], h["W13"], h["W2"], sel, dO)
+    # combine backward: dw against the GPU's own Y (FP32 dot products)
+    Yg = fw["Y"].float().cpu().double().numpy()
+    inv = fw["inv_map"].cpu().numpy()
+    dw_exact = np.einsum("tkd,td->tk", Yg[inv], dO)
+    assert rel_fro(dw.cpu().numpy(), dw_exact) <= 1e-5
+    # dY = w * dOut in slot order, BF16-rounded
+    wg = fw["w"].cpu().numpy().astype(np.float64)
+    dY_exact = np.zeros_like(Yg)
+    for j in range(shape.k):
+        dY_exact[inv[:, j]] = wg[:, j:j + 1] * dO
+    assert rel_fro(dY.float().cpu().numpy(), dY_exact) <= 4e-3
+    # against the FP64 oracle
+    assert rel_fro(dw.cpu().numpy(), ref["dw"]) <= 2e-2
+    assert rel_fro(dXp.float().cpu().numpy(), ref["dXp"]) <= 2e-2
+    assert rel_fro(dW13.cpu().numpy(), ref["dW13"]) <= 2e-2
+    assert rel_fro(dW2.cpu().numpy(), ref["dW2"]) <= 2e-2
+    assert rel_fro(dX.cpu().numpy(), ref["dX"]) <= 2e-2
+    assert rel_fro(dWr.cpu().numpy(), ref["dWr"]) <= 2e-2
+    assert rel_fro(dbr.cpu().numpy(), ref["dbr"]) <= 2e-2
+
+
+def test_dispatch_backward_is_a_gather_sum():
+    cfg, d, h, fw, dOut = _setup(BWD, 33)
+    dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
+    dXp, _, _ = layer.expert_ffn_bwd(cfg, d["X"], fw["row_map"], fw["offsets"], dY, d["W13"], d["W2"])
+    dX = layer.dispatch_bwd(cfg, dXp, fw["inv_map"])
+    torch.cuda.synchronize()
+    inv = fw["inv_map"].cpu().numpy()
+    g = dXp.float().cpu().double().numpy()
+    exp = sum(g[inv[:, j]] for j in range(cfg.k))
+    assert rel_fro(dX.cpu().numpy(), exp) <= 1e-6
+
+
+def test_autograd_function_matches_oracle():
+    shape = BWD
+    inp = synth.make_inputs(shape, 34)
+    d, h = device_inputs(shape, inp)
+    cfg = cfg_for(shape)
+    X = d["X"].clone().requires_grad_(True)
+    Wr = d["Wr"].clone().requires_grad_(True)
+    br = d["br"].clone().requires_grad_(True)
+    W13 = d["W13"].clone().requires_grad_(True)
+    W2 = d["W2"].clone().requires_grad_(True)
+    out = layer.moe_layer(cfg, X, Wr, br, W13, W2)
+    dOut = torch.from_numpy(synth.make_upstream(shape.T, shape.d, 34)).to(torch.bfloat16).cuda()
+    out.backward(dOut)
+    torch.cuda.synchronize()
+    r = layer.route(cfg, d["X"], d["Wr"], d["br"])
+    sel = r["idx"].cpu().numpy()
+    ref = grad.layer_backward(h["X"], h["Wr"], h["br"], h["W13"], h["W2"], sel,
+                              dOut.float().cpu().double().numpy())
+    for name, t, key in [("X", X, "dX"), ("Wr", Wr, "dWr"), ("br", br, "dbr"), ("W13", W13, "dW13"),
+                         ("W2", W2, "dW2")]:
+        err = rel_fro(t.grad.float().cpu().numpy(), ref[key])
+        assert err <= 2e-2, (name, err)
+
+
+def test_backward_is_deterministic():
+    cfg, d, h, fw, dOut = _setup(BWD2, 35)
+    res = []
+    for _ in range(2):
+        dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
+        dXp, dW13, dW2 = layer.expert_ffn_bwd(cfg, d["X"], fw["row_map"], fw["offsets"], dY,
+                                              d["W13"], d["W2"])
+        dX, dWr, dbr = layer.route_bwd(cfg, d["X"], d["Wr"], fw["idx"], fw["w"], dw, fw["row_map"],
+                                       fw["offsets"], fw["inv_map"], dXp)
+        res.append([x.clone() for x in (dY, dw, dXp, dW13, dW2, dX, dWr, dbr)])
+    torch.cuda.synchronize()
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
+
+
+def test_backward_fwd_bwd_config_sampled():
+    """Workload 4 (T=32768, d=2048, E=128, top-8, f=1024): weight gradients of
+    two experts and dX of 24 tokens against FP64 computed from those slots."""
+    shape = synth.SHAPES[4]
+    inp = synth.make_inputs(shape, 4)
+    d, h = device_inputs(shape, inp, host_weights=False)
+    del inp
+    cfg = cfg_for(shape)
+    fw = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"])
+    dOut = torch.from_numpy(synth.make_upstream(shape.T, shape.d, 4)).to(torch.bfloat16).cuda()
+    dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
+    dXp, dW13, dW2 = layer.expert_ffn_bwd(cfg, d["X"], fw["row_map"], fw["offsets"], dY, d["W13"],
+                                          d["W2"])
+    torch.cuda.synchronize()
+    off = fw["offsets"].cpu().numpy()
+    row_map = fw["row_map"].cpu().numpy()
+    Xh = h["X"]
+    dYh = dY.float().cpu().double().numpy()
+    import scipy.special
+    for e in (0, int(np.argmax(np.diff(off)))):
+        a, b = int(off[e]), int(off[e + 1])
+        x = Xh[row_map[a:b]]
+        W13e = d["W13"][e].float().cpu().double().numpy()
+        W2e = d["W2"][e].float().cpu().double().numpy()
+        f = shape.f
+        A = x @ W13e[:f].T
+        B = x @ W13e[f:].T
+        g = scipy.special.expit(A)
+        hh = A * g * B
+        U = dYh[a:b] @ W2e
+        dA = U * B * (g + A * g * (1 - g))
+        dB = U * A * g
+        assert rel_fro(dW2[e].cpu().numpy(), dYh[a:b].T @ hh) <= 2e-2
+        assert rel_fro(dW13[e, :f].cpu().numpy(), dA.T @ x) <= 2e-2
+        assert rel_fro(dW13[e, f:].cpu().numpy(), dB.T @ x) <= 2e-2
+        dxp = dA @ W13e[:f] + dB @ W13e[f:]
+        assert rel_fro(dXp[a:b].float().cpu().numpy(), dxp) <= 2e-2
