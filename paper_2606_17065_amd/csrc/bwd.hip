@@ -46,10 +46,12 @@ __global__ __launch_bounds__(256) void combine_bwd_kernel(const TA* __restrict__
   }
 }
 
-// dX_t = sum_j dX_perm[slot(t,j)] + sum_j ds_tj W_r[e_j] (FP32 out).  The
-// second sum is the router backward into the tokens; ds is formed here from
-// w and dw.  One wavefront per token.
-template <typename TA>
+// dX_t = sum_j dX_perm[slot(t,j)] (+ sum_j ds_tj W_r[e_j] when ROUTER) in
+// FP32.  With ROUTER the second sum is the router backward into the tokens;
+// ds is formed here from w and dw (and written to ds_out).  Without ROUTER
+// idx, w, dw, Wr and ds_out are not touched (they may be null).  One
+// wavefront per token.
+template <typename TA, bool ROUTER>
 __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
     const TA* __restrict__ dXp, int T, int d, int k, int E, const int32_t* __restrict__ inv_map,
     const int32_t* __restrict__ idx, const float* __restrict__ w, const float* __restrict__ dw,
@@ -60,20 +62,29 @@ __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
   const int N = T * k;
   int slots[MOE_MAX_K], ex[MOE_MAX_K];
   float ds[MOE_MAX_K];
-  float sw = 0.0f;
-#pragma unroll
-  for (int j = 0; j < MOE_MAX_K; ++j)
-    if (j < k) sw = sw + w[(size_t)t * k + j] * dw[(size_t)t * k + j];
 #pragma unroll
   for (int j = 0; j < MOE_MAX_K; ++j) {
     slots[j] = j < k ? clampi(inv_map[(size_t)t * k + j], 0, N - 1) : 0;
-    ex[j] = j < k ? clampi(idx[(size_t)t * k + j], 0, E - 1) : 0;
-    ds[j] = j < k ? w[(size_t)t * k + j] * (dw[(size_t)t * k + j] - sw) : 0.0f;
+    ex[j] = 0;
+    ds[j] = 0.0f;
   }
-  if (ds_out && lane < k) {
+  if (ROUTER) {
+    float sw = 0.0f;
 #pragma unroll
     for (int j = 0; j < MOE_MAX_K; ++j)
-      if (j == lane) ds_out[(size_t)t * k + j] = ds[j];
+      if (j < k) sw = sw + w[(size_t)t * k + j] * dw[(size_t)t * k + j];
+#pragma unroll
+    for (int j = 0; j < MOE_MAX_K; ++j) {
+      if (j < k) {
+        ex[j] = clampi(idx[(size_t)t * k + j], 0, E - 1);
+        ds[j] = w[(size_t)t * k + j] * (dw[(size_t)t * k + j] - sw);
+      }
+    }
+    if (lane < k) {
+#pragma unroll
+      for (int j = 0; j < MOE_MAX_K; ++j)
+        if (j == lane) ds_out[(size_t)t * k + j] = ds[j];
+    }
   }
   for (int c0 = lane * 4; c0 < d; c0 += 64 * 4) {
     float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -84,7 +95,7 @@ __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
         for (int i = 0; i < 4; ++i) acc[i] = acc[i] + ActIO<TA>::ld(dXp, (size_t)slots[j] * d + c0 + i);
       }
     }
-    if (Wr) {
+    if (ROUTER) {
 #pragma unroll
       for (int j = 0; j < MOE_MAX_K; ++j) {
         if (j < k) {
@@ -189,12 +200,12 @@ extern "C" moe_status moe_dispatch_bwd(const moe_cfg* cfg, const void* dX_perm,
   hipStream_t st = (hipStream_t)stream;
   PROF_BEGIN("dispatch_bwd", st);
   if (c.act == MOE_F32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float>), dim3((c.T + 3) / 4), dim3(256),
-                       0, st, (const float*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr, nullptr,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float, false>), dim3((c.T + 3) / 4),
+                       dim3(256), 0, st, (const float*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr, nullptr,
                        nullptr, nullptr, dX, nullptr);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t>), dim3((c.T + 3) / 4), dim3(256),
-                       0, st, (const bf16_t*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t, false>), dim3((c.T + 3) / 4),
+                       dim3(256), 0, st, (const bf16_t*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr,
                        nullptr, nullptr, nullptr, dX, nullptr);
   PROF_END("dispatch_bwd", st);
   MOE_LAUNCH_CHECK();
@@ -226,11 +237,11 @@ extern "C" moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const flo
     hipLaunchKernelGGL(slot_source, dim3((N + 255) / 256), dim3(256), 0, st, inv_map, N,
                        w.slot_src);
     if (c.act == MOE_F32)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float>), dim3((c.T + 3) / 4),
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float, true>), dim3((c.T + 3) / 4),
                          dim3(256), 0, st, (const float*)dX_perm, c.T, c.d, c.k, c.E, inv_map,
                          topk_idx, topk_w, dtopk_w, Wr, dX, w.ds);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t>), dim3((c.T + 3) / 4),
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t, true>), dim3((c.T + 3) / 4),
                          dim3(256), 0, st, (const bf16_t*)dX_perm, c.T, c.d, c.k, c.E, inv_map,
                          topk_idx, topk_w, dtopk_w, Wr, dX, w.ds);
   }
