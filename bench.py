@@ -1,19 +1,26 @@
 #!/usr/bin/env python3
 """Routed tokens/s of one mixture-of-experts layer on one MI355X.
 
-Workload (default): T=16384 tokens, d_model=1024, E=64 experts, top-8,
-SwiGLU d_ff=2048, capacity factor 1.25, Zipf(1.2) router bias, BF16 tokens
-and expert weights, FP32 router and prices; seeded synthetic inputs already
-resident in HBM.  One step = router logits + clearing-price loop + top-k +
-capacity check + dispatch + both grouped expert GEMMs + combine.
+Timed workload (the value of the JSON line): T=16384 tokens, d_model=1024,
+E=64 experts, top-8, SwiGLU d_ff=2048, capacity factor 1.25, Zipf(1.2)
+router bias, BF16 tokens and expert weights, FP32 router and prices; seeded
+synthetic inputs already resident in HBM.  One step = router logits +
+clearing-price loop + top-k + capacity check + dispatch + both grouped
+expert GEMMs + combine.
 
-Prints ONE JSON line (rank 0) with the throughput, the roofline of the
-dominant kernel (timed live with HIP events on the launch stream) and the
-CPU oracle timed on a bounded sample of the same workload.
+Also measured (extra fields): forward+backward at T=32768, d=2048, E=128,
+top-8, d_ff=1024 (Zipf 1.3), the per-stage kernel times (HIP events on the
+launch stream), the roofline of the dominant kernel, and the CPU oracle on
+the same forward batch.
+
+Prints ONE JSON line.  `--profile-only fwd|copy` runs a few steps without
+output for hardware-counter runs (copy = a plain device copy of 1 GiB used
+to calibrate the byte counters).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +33,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm1_bf16_scale.json")
+GEMM_SRC = os.path.join(ROOT, "paper_2606_17065_amd", "csrc", "gemm.hip")
 
 
 def parse():
@@ -33,12 +42,62 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, help="workload number (1..5)")
-    ap.add_argument("--cpu-tokens", type=int, default=4096,
-                    help="tokens in the oracle's timed sample (0 = skip)")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with counter-derived HBM bytes per launch of the dominant kernel")
+    ap.add_argument("--config", type=int, default=2, help="forward workload number (1, 2, 4)")
+    ap.add_argument("--bwd-config", type=int, default=4, help="fwd+bwd workload (0 = skip)")
+    ap.add_argument("--cpu-tokens", type=int, default=-1,
+                    help="tokens in the oracle's timed sample (-1 = the whole batch, 0 = skip)")
+    ap.add_argument("--profile-only", choices=["fwd", "copy"], default=None)
     return ap.parse_args()
+
+
+def gemm_src_hash() -> str:
+    return hashlib.sha256(open(GEMM_SRC, "rb").read()).hexdigest()[:16]
+
+
+def load_inputs(shape, config, dev, torch):
+    from paper_2606_17065_amd import synth
+    act = torch.float32 if shape.act == "f32" else torch.bfloat16
+    inp = synth.make_inputs(shape, config)
+    d = dict(X=torch.from_numpy(inp["X"]).to(act).to(dev),
+             Wr=torch.from_numpy(inp["Wr"]).to(dev), br=torch.from_numpy(inp["br"]).to(dev),
+             W13=torch.from_numpy(inp["W13"]).to(act).to(dev),
+             W2=torch.from_numpy(inp["W2"]).to(act).to(dev))
+    return inp, d
+
+
+def make_cfg(shape, L):
+    return L.make_cfg(shape.T, shape.d, shape.E, shape.k, shape.f, shape.capacity, shape.max_iters,
+                      L.MOE_F32 if shape.act == "f32" else L.MOE_BF16,
+                      L.MOE_F32 if shape.w == "f32" else L.MOE_BF16, L.MOE_PRICE_ACP)
+
+
+def timed(fn, steps, warmup, torch, L):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    L.moe_prof_reset()
+    L.moe_prof_enable(True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    L.moe_prof_enable(False)
+    return ev0.elapsed_time(ev1), wall
+
+
+def stage_times(L, names):
+    out = {}
+    for name in names:
+        tot, n = L.moe_prof_get(name)
+        if n:
+            out[name] = {"ms": tot / n, "launches": n}
+    return out
 
 
 def main():
@@ -58,72 +117,72 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+
+    if args.profile_only == "copy":
+        a = torch.empty(1 << 29, dtype=torch.int16, device=dev).fill_(1)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("copied 1 GiB x3")
+        return
+
     shape = synth.SHAPES[args.config]
-    if shape.w == "fp8":
-        print("FP8 experts are not built yet", file=sys.stderr)
-        sys.exit(2)
-    act = torch.float32 if shape.act == "f32" else torch.bfloat16
-    inp = synth.make_inputs(shape, args.config)
-    X = torch.from_numpy(inp["X"]).to(act).to(dev)
-    Wr = torch.from_numpy(inp["Wr"]).to(dev)
-    br = torch.from_numpy(inp["br"]).to(dev)
-    W13 = torch.from_numpy(inp["W13"]).to(act).to(dev)
-    W2 = torch.from_numpy(inp["W2"]).to(act).to(dev)
-    cfg = L.make_cfg(shape.T, shape.d, shape.E, shape.k, shape.f, shape.capacity, shape.max_iters,
-                     L.MOE_F32 if shape.act == "f32" else L.MOE_BF16,
-                     L.MOE_F32 if shape.w == "f32" else L.MOE_BF16, L.MOE_PRICE_ACP)
+    inp, D = load_inputs(shape, args.config, dev, torch)
+    cfg = make_cfg(shape, L)
 
-    def step():
-        return layer.forward(cfg, X, Wr, br, W13, W2)
+    def fwd():
+        return layer.forward(cfg, D["X"], D["Wr"], D["br"], D["W13"], D["W2"])
 
-    for _ in range(args.warmup):
-        out = step()
+    if args.profile_only == "fwd":
+        for _ in range(max(args.steps, 1)):
+            fwd()
+        torch.cuda.synchronize()
+        print("forward steps done")
+        return
+
+    gpu_ms, wall = timed(fwd, args.steps, args.warmup, torch, L)
+    out = fwd()
     torch.cuda.synchronize()
     info = out["info"].cpu().numpy()
-
-    L.moe_prof_reset()
-    L.moe_prof_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        out = step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    L.moe_prof_enable(False)
-    gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = gpu_ms / args.steps
     value = shape.T * args.steps / (gpu_ms / 1e3)
 
     N, d, f, E, T = shape.N, shape.d, shape.f, shape.E, shape.T
     b = 4 if shape.act == "f32" else 2
-    stages = {}
-    for name in ("router_logits", "price_loop", "dispatch", "gemm1_swiglu", "gemm2", "combine"):
-        tot, n = L.moe_prof_get(name)
-        stages[name] = {"ms": tot / max(n, 1), "launches": n}
-    # algorithmic work per launch
+    stages = stage_times(L, ("router_logits", "price_loop", "dispatch", "gemm1_swiglu", "gemm2",
+                             "combine"))
     gemm1_flop = 4.0 * N * d * f
     gemm2_flop = 2.0 * N * d * f
-    stages["gemm1_swiglu"].update(flop=gemm1_flop, tflops=gemm1_flop / (stages["gemm1_swiglu"]["ms"] * 1e9))
+    stages["gemm1_swiglu"].update(flop=gemm1_flop,
+                                  tflops=gemm1_flop / (stages["gemm1_swiglu"]["ms"] * 1e9))
     stages["gemm2"].update(flop=gemm2_flop, tflops=gemm2_flop / (stages["gemm2"]["ms"] * 1e9))
     disp_bytes = T * d * b + N * d * b + 4.0 * (T * shape.k * 3 + E + 1)
     comb_bytes = N * d * b + T * d * b + 8.0 * N
     stages["dispatch"].update(bytes=disp_bytes, gbs=disp_bytes / (stages["dispatch"]["ms"] * 1e6))
     stages["combine"].update(bytes=comb_bytes, gbs=comb_bytes / (stages["combine"]["ms"] * 1e6))
-    dom = max(("gemm1_swiglu", "gemm2"), key=lambda k: stages[k]["ms"])
+    route_bytes = T * d * b + 4.0 * d * E + 8.0 * T * E
+    stages["router_logits"].update(bytes=route_bytes,
+                                   gbs=route_bytes / (stages["router_logits"]["ms"] * 1e6))
+    dom = "gemm1_swiglu"
     ach = stages[dom]["tflops"]
     traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get(dom)
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("gemm_src_sha256_16") == gemm_src_hash() and tr.get("workload") == shape.name:
+            traffic = tr.get("hbm_bytes_per_launch")
     roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": BF16_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS, "traffic": traffic}
+            "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS, "traffic": traffic,
+            "algorithmic_flop_per_launch": gemm1_flop}
+
+    fb = None
+    if args.bwd_config:
+        fb = fwd_bwd(args.bwd_config, args, dev, torch, L, layer, synth)
 
     cpu = None
-    if args.cpu_tokens > 0:
-        cpu = cpu_baseline(shape, inp, args.cpu_tokens)
+    if args.cpu_tokens != 0:
+        T_s = T if args.cpu_tokens < 0 else min(args.cpu_tokens, T)
+        cpu = cpu_baseline(shape, inp, T_s)
 
     rec = {
         "metric": "routed tokens/s per MoE layer (forward)",
@@ -137,9 +196,39 @@ def main():
                    "parallelism": "single-gpu"},
         "price_iters": int(info[0]), "converged": bool(info[1]),
         "slots_per_s": value * shape.k, "wall_s": wall,
-        "roofline": roof, "stages": stages, "cpu_baseline": cpu,
+        "roofline": roof, "stages": stages, "fwd_bwd": fb, "cpu_baseline": cpu,
     }
     print(json.dumps(rec))
+
+
+def fwd_bwd(config, args, dev, torch, L, layer, synth):
+    """Forward + backward through the autograd Function (upstream ~N(0,1))."""
+    shape = synth.SHAPES[config]
+    inp, D = load_inputs(shape, config, dev, torch)
+    del inp
+    cfg = make_cfg(shape, L)
+    params = {k: D[k].clone().requires_grad_(True) for k in ("X", "Wr", "br", "W13", "W2")}
+    dOut = torch.from_numpy(synth.make_upstream(shape.T, shape.d, config)).to(torch.bfloat16).to(dev)
+
+    def step():
+        for p in params.values():
+            p.grad = None
+        out = layer.moe_layer(cfg, params["X"], params["Wr"], params["br"], params["W13"],
+                              params["W2"])
+        out.backward(dOut)
+
+    steps = max(2, args.steps // 2)
+    gpu_ms, wall = timed(step, steps, max(1, args.warmup // 2), torch, L)
+    ms = gpu_ms / steps
+    st = stage_times(L, ("router_logits", "price_loop", "dispatch", "gemm1_swiglu", "gemm2",
+                         "combine", "combine_bwd", "ffn_bwd", "route_bwd"))
+    N, d, f = shape.N, shape.d, shape.f
+    if "ffn_bwd" in st:
+        st["ffn_bwd"].update(flop=16.0 * N * d * f,
+                             tflops=16.0 * N * d * f / (st["ffn_bwd"]["ms"] * 1e9))
+    return {"workload": f"moe-{shape.name}", "T": shape.T, "d_model": d, "E": shape.E,
+            "top_k": shape.k, "d_ff": f, "steps": steps, "ms_per_step": ms,
+            "tokens_per_s": shape.T / (ms / 1e3), "stages": st}
 
 
 def cpu_baseline(shape, inp, T_s):
@@ -169,9 +258,10 @@ def cpu_baseline(shape, inp, T_s):
     ffn.layer_forward(Xb, r["sel"], r["w"], W13, W2)
     dt = time.perf_counter() - t0
     return {"value": T_s / dt, "unit": "tokens/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {T_s} tokens of the timed batch, same weights, capacity "
-                      f"{sub.capacity}: full layer forward in FP64 NumPy (logits, price loop, "
-                      f"top-k, dispatch, experts, combine)",
+            "sample": f"{'the whole batch' if T_s == shape.T else f'first {T_s} tokens'} "
+                      f"({T_s} tokens, capacity {sub.capacity}) of the timed workload, same "
+                      f"weights: full layer forward in FP64 NumPy (logits, price loop, top-k, "
+                      f"dispatch, experts, combine)",
             "seconds": dt}
 
 
