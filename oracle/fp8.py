@@ -18,6 +18,7 @@ A block's dequantised value is decode(q) * scale; a matrix product over a
 from __future__ import annotations
 
 import numpy as np
+import scipy.special
 
 F32 = np.float32
 FP8_MAX = 448.0
@@ -92,3 +93,62 @@ def dequantize_blocks(codes: np.ndarray, scales: np.ndarray, br: int, bc: int) -
     R, Cc = codes.shape
     sc = np.repeat(np.repeat(np.asarray(scales, np.float64), br, axis=0)[:R], bc, axis=1)
     return v * sc
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Nearest BF16 value (8 significant bits, ties to even) of float64
+    values in BF16's normal range; float64 result."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    _, ex = np.frexp(np.where(a > 0, a, 1.0))
+    quantum = np.exp2(ex - 1 - 7.0)
+    r = np.rint(a / quantum) * quantum
+    return np.where(a > 0, np.sign(x) * r, 0.0 * x)
+
+
+def slots_forward_fp8(X, row_map, offsets, W13q, W13s, W2q, W2s):
+    """FP8 expert path over the slots (reading; the paper defines none).
+
+    X holds the stored token values (float64 of the BF16 activations).
+    Tokens are quantised per 1 x 128 block of a row and gathered into
+    slot order; weights come quantised per 128 x 128 block (codes and
+    scales as quantize_blocks returns them, one expert per leading index).
+    Per expert: [A|B] = Xd W13d^T with Xd, W13d the dequantised values
+    decode(q) * scale -- exact in FP64, so this product equals the sum over
+    128-wide K blocks of (sum qa qb) * sa * sb; h = silu(A) * B is stored
+    as BF16 and quantised per 1 x 128 block; Y = hd W2d^T.
+
+    Returns dict of Xq, Xs (token codes / scales, [T,d] / [T,d/128]), h
+    (BF16 values, [N,f]), hq, hs, Y [N,d] (FP64)."""
+    X = np.asarray(X, np.float32)
+    Xq, Xs = quantize_blocks(X, 1, 128)
+    Xd = dequantize_blocks(Xq, Xs, 1, 128)[row_map]
+    E = offsets.shape[0] - 1
+    f = W13q.shape[1] // 2
+    N, d = Xd.shape
+    h = np.zeros((N, f))
+    for e in range(E):
+        a, b = int(offsets[e]), int(offsets[e + 1])
+        if a == b:
+            continue
+        W = dequantize_blocks(W13q[e], W13s[e], 128, 128)
+        A = Xd[a:b] @ W[:f].T
+        B = Xd[a:b] @ W[f:].T
+        h[a:b] = round_bf16(A * scipy.special.expit(A) * B)
+    hq, hs = quantize_blocks(h.astype(np.float32), 1, 128)
+    hd = dequantize_blocks(hq, hs, 1, 128)
+    Y = np.zeros((N, d))
+    for e in range(E):
+        a, b = int(offsets[e]), int(offsets[e + 1])
+        if a == b:
+            continue
+        Y[a:b] = hd[a:b] @ dequantize_blocks(W2q[e], W2s[e], 128, 128).T
+    return dict(Xq=Xq, Xs=Xs, h=h, hq=hq, hs=hs, Y=Y)
+
+
+def quantize_experts(W, br=128, bc=128):
+    """Per-expert block quantisation of W [E, R, C]: (codes [E,R,C] uint8,
+    scales [E, ceil(R/br), C/bc] float32)."""
+    W = np.asarray(W, np.float32)
+    qs = [quantize_blocks(W[e], br, bc) for e in range(W.shape[0])]
+    return np.stack([q for q, _ in qs]), np.stack([s for _, s in qs])

@@ -3,6 +3,7 @@ closed forms, special cases and finite differences."""
 import math
 
 import numpy as np
+import scipy.special
 import pytest
 import torch
 import torch.nn.functional as Fnn
@@ -175,6 +176,73 @@ def test_fp8_block_quantisation_bounds():
     # the block maximum maps to +-448 codes
     amax_pos = np.abs(x[:, :128]).argmax(axis=1)
     assert np.all(np.abs(fp8.decode(q[np.arange(130), amax_pos])[np.arange(130) != 5]) == 448.0)
+
+
+def test_round_bf16_is_nearest_even_and_matches_torch_on_float32_inputs():
+    rng = np.random.default_rng(2)
+    x = (rng.standard_normal(50000) * np.exp(rng.uniform(-30, 30, 50000))).astype(F32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).double().numpy()
+    np.testing.assert_array_equal(fp8.round_bf16(x.astype(np.float64)), ref)
+    # ties between 1 and 1 + 2^-7 go to the even significand
+    t = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), 0.0])
+    np.testing.assert_array_equal(fp8.round_bf16(t), [1.0, 1 + 2 * 2.0 ** -7, -1.0, 0.0])
+
+
+def _fp8_layer_case(T=96, d=256, E=4, k=2, f=256, seed=3, grid=False):
+    rng = np.random.default_rng(seed)
+    if grid:
+        # every value on the e4m3 grid and every block holding a 448, so all
+        # scales are 1 and quantisation is exact
+        vals = fp8.decode(np.arange(0x20, 0x48, dtype=np.uint8))  # 2^-4 .. 3.75
+        X = rng.choice(vals, (T, d)) * rng.choice([-1.0, 1.0], (T, d))
+        X[:, ::128] = 448.0
+        W13 = rng.choice(vals, (E, 2 * f, d)) * rng.choice([-1.0, 1.0], (E, 2 * f, d))
+        W13[:, ::128, ::128] = 448.0
+        W2 = rng.choice(vals, (E, d, f))
+        W2[:, ::128, ::128] = 448.0
+    else:
+        X = rng.standard_normal((T, d))
+        W13 = 0.05 * rng.standard_normal((E, 2 * f, d))
+        W2 = 0.05 * rng.standard_normal((E, d, f))
+    X, W13, W2 = (a.astype(F32) for a in (X, W13, W2))
+    sel = np.stack([rng.permutation(E)[:k] for _ in range(T)])
+    offsets, row_map, inv_map = ffn.dispatch_maps(sel, E)
+    W13q, W13s = fp8.quantize_experts(W13)
+    W2q, W2s = fp8.quantize_experts(W2)
+    return X, W13, W2, offsets, row_map, W13q, W13s, W2q, W2s
+
+
+def test_fp8_layer_is_exact_on_the_grid():
+    X, W13, W2, offsets, row_map, W13q, W13s, W2q, W2s = _fp8_layer_case(grid=True)
+    assert np.all(W13s == 1.0) and np.all(W2s == 1.0)
+    r = fp8.slots_forward_fp8(X, row_map, offsets, W13q, W13s, W2q, W2s)
+    assert np.all(r["Xs"] == 1.0)
+    Xp = X.astype(np.float64)[row_map]
+    f = W13.shape[1] // 2
+    for e in range(W13.shape[0]):
+        a, b = offsets[e], offsets[e + 1]
+        A = Xp[a:b] @ W13[e, :f].astype(np.float64).T
+        B = Xp[a:b] @ W13[e, f:].astype(np.float64).T
+        h = fp8.round_bf16(A * scipy.special.expit(A) * B)
+        np.testing.assert_array_equal(r["h"][a:b], h)
+
+
+def test_fp8_layer_power_of_two_weight_scaling_is_exact():
+    X, W13, W2, offsets, row_map, W13q, W13s, W2q, W2s = _fp8_layer_case(seed=4)
+    r1 = fp8.slots_forward_fp8(X, row_map, offsets, W13q, W13s, W2q, W2s)
+    W2q8, W2s8 = fp8.quantize_experts(W2 * np.float32(8.0))
+    np.testing.assert_array_equal(W2q8, W2q)
+    np.testing.assert_array_equal(W2s8, W2s * 8)
+    r8 = fp8.slots_forward_fp8(X, row_map, offsets, W13q, W13s, W2q8, W2s8)
+    np.testing.assert_array_equal(r8["Y"], 8.0 * r1["Y"])
+
+
+def test_fp8_layer_close_to_the_fp64_layer():
+    X, W13, W2, offsets, row_map, W13q, W13s, W2q, W2s = _fp8_layer_case(seed=5)
+    r = fp8.slots_forward_fp8(X, row_map, offsets, W13q, W13s, W2q, W2s)
+    _, _, Y64 = ffn.slots_forward(X, row_map, offsets, W13, W2)
+    rel = np.linalg.norm(r["Y"] - Y64) / np.linalg.norm(Y64)
+    assert 1e-4 < rel <= 8e-2, rel
 
 
 # ---------------------------------------------------------------- price MLP
