@@ -126,6 +126,105 @@ moe_status moe_route(const moe_cfg* cfg, const void* X, const float* Wr, const f
                      int32_t* load, int32_t* info, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * moe_route_logits -- moe_route for caller-supplied logits: the same
+ *   sigma_s, price update (cfg.price_mode), top-k, weights, capacity repair
+ *   and info[], starting from logits [T,E] f32 (read only) instead of
+ *   computing them.  cfg.d, cfg.d_ff, cfg.act and cfg.w are validated as for
+ *   moe_route but not used.  Other arguments as in moe_route.
+ */
+moe_status moe_route_logits(const moe_cfg* cfg, const float* logits, float* price,
+                            int32_t* topk_idx, float* topk_w, int32_t* load, int32_t* info,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * moe_route_certify -- duality certificate of a routing under prices p:
+ *   cert[0] = primal  sum_t sum_j s[t, topk_idx[t,j]]
+ *   cert[1] = dual    D(p) = C sum_e p_e + sum_t (sum of the k largest
+ *                     s_te - p_e over e; ranking by the FP32 key)
+ *   cert[2] = (dual - primal) / |dual|   (|dual| = 0 is taken as 1)
+ *   FP64, fixed-order sums.  For any feasible routing, primal <= optimum <=
+ *   dual; when topk_idx is the top-k under p the gap equals
+ *   sum_e p_e (C - load_e).  logits [T,E] f32; price [E] f32; topk_idx
+ *   [T,k] i32; cert [3] f64 out (8-byte aligned).  Uses ws (any buffer of
+ *   moe_workspace_bytes).
+ */
+moe_status moe_route_certify(const moe_cfg* cfg, const float* logits, const float* price,
+                             const int32_t* topk_idx, double* cert, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/*
+ * Learned starting prices.  Eight statistics of a batch of logits per
+ * expert feed a small network shared by all experts whose output,
+ * p_hat_e = sigma * softplus(z_e), predicts the prices the clearing-price
+ * update reaches; it is used as a warm start (MOE_PRICE_WARM: p0 =
+ * warm_gamma * p_hat) or alone (MOE_PRICE_GIVEN), with moe_route_certify
+ * judging the result.
+ *
+ * moe_logit_stats -- features [E,8] f32 out of logits [T,E] f32.  With mu,
+ *   sigma the mean and population std of all T*E logits (FP64, fixed
+ *   order), load0 the plain top-k loads at p = 0, kappa1_t / kappa2_t the
+ *   k-th / (k+1)-th largest logit of token t, margins
+ *   m0_te = fl32(s_te - (e in top-k of t ? kappa2_t : kappa1_t)), and
+ *   q(v) = the (C+1)-th largest of a column v (its minimum when T <= C):
+ *     f0 = (mean_t s_te - mu)/sigma     f1 = std_t s_te / sigma
+ *     f2 = (max_t s_te - mu)/sigma      f3 = (q(s_.e) - mu)/sigma
+ *     f4 = load0_e / C                  f5 = mean_t m0_te / sigma
+ *     f6 = q(m0_.e) / sigma             f7 = std_t m0_te / sigma
+ *   sigma [1] f32 out (may be NULL).  Requires T >= 1 (MOE_EINVAL) and
+ *   k < E (MOE_EUNSUPPORTED).  Logits must be finite.
+ */
+moe_status moe_logit_stats(const moe_cfg* cfg, const float* logits, float* feats, float* sigma,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Price network parameters: one f32 vector of n_params values laid out as
+ *   W1 [256,8], b1 [256], W2 [256,256], b2 [256], w3 [256], b3 [1];
+ *   u1 = F W1^T + b1, a1 = gelu(u1), u2 = a1 W2^T + b2, a2 = gelu(u2),
+ *   z = a2 w3 + b3, p_hat = sigma * softplus(z),
+ *   gelu(u) = u/2 (1 + erf(u / sqrt 2)).
+ * moe_price_mlp_sizes (host outs, each may be NULL): n_params, the floats
+ *   of the activation buffer and the backward workspace bytes for `rows`.
+ */
+moe_status moe_price_mlp_sizes(int rows, int32_t* n_params /* host out */,
+                               size_t* acts_floats /* host out */,
+                               size_t* bwd_ws_bytes /* host out */);
+
+/*
+ * moe_price_mlp_forward -- p_hat [rows] f32 out for features [rows,8] f32.
+ *   sigma: device f32 scalar, or NULL for 1.  acts [acts_floats] f32 out:
+ *   u1, a1, u2, a2 ([rows,256] each) and z [rows], kept for the backward.
+ */
+moe_status moe_price_mlp_forward(int rows, const float* feats, const float* params,
+                                 const float* sigma, float* price_hat, float* acts, void* stream);
+
+/*
+ * moe_price_mlp_backward -- dparams [n_params] f32 out = the gradient of a
+ *   loss whose derivative with respect to p_hat is dprice [rows], through
+ *   the forward whose activations are in acts.  Row sums are taken in
+ *   fixed 256-row chunks folded in order.  ws: bwd_ws_bytes.
+ */
+moe_status moe_price_mlp_backward(int rows, const float* feats, const float* params,
+                                  const float* sigma, const float* acts, const float* dprice,
+                                  float* dparams, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * moe_price_mse -- loss [1] = mean_r (price_hat_r - y_r)^2 with
+ *   y_r = target_r / sigma[r / group] (sigma may be NULL: y = target), and
+ *   dprice [rows] = 2 (price_hat_r - y_r) / rows (may be NULL).
+ */
+moe_status moe_price_mse(int rows, int group, const float* price_hat, const float* target,
+                         const float* sigma, float* dprice, float* loss, void* stream);
+
+/*
+ * moe_adam_step -- Adam with bias correction, in place, f32:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   params -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ *   step >= 1 counts updates; 0 <= b1, b2 < 1.
+ */
+moe_status moe_adam_step(int n, float* params, const float* grads, float* m, float* v, float lr,
+                         float beta1, float beta2, float eps, int step, void* stream);
+
+/*
  * moe_dispatch -- histogram / prefix-scan permute of the tokens into slots.
  *   offsets[e] = first slot of expert e (exclusive scan of the loads),
  *   offsets[E] = N; row_map[slot] = token of the slot; inv_map[t, j] = slot

@@ -59,6 +59,16 @@ SIGNATURES = {
     "moe_expert_ffn_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_dispatch_bwd": [_CFG, _P, _P, _P, _P],
     "moe_route_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_route_logits": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_route_certify": [_CFG, _P, _P, _P, _P, _P, _S, _P],
+    "moe_logit_stats": [_CFG, _P, _P, _P, _P, _S, _P],
+    "moe_price_mlp_sizes": [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
+                            ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
+    "moe_price_mlp_forward": [ctypes.c_int, _P, _P, _P, _P, _P, _P],
+    "moe_price_mlp_backward": [ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_price_mse": [ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P],
+    "moe_adam_step": [ctypes.c_int, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float,
+                      ctypes.c_float, ctypes.c_float, ctypes.c_int, _P],
     "moe_prof_enable": [ctypes.c_int],
     "moe_prof_reset": [],
     "moe_prof_get": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)],
@@ -144,6 +154,52 @@ def moe_route_bwd(cfg, X, Wr, topk_idx, topk_w, dtopk_w, row_map, offsets, inv_m
     _check(lib().moe_route_bwd(ctypes.byref(cfg), X, Wr, topk_idx, topk_w, dtopk_w, row_map,
                                offsets, inv_map, dX_perm, dX, dWr, dbr, ws, ws_bytes, stream),
            "moe_route_bwd")
+
+
+def moe_route_logits(cfg, logits, price, topk_idx, topk_w, load, info, ws, ws_bytes, stream):
+    _check(lib().moe_route_logits(ctypes.byref(cfg), logits, price, topk_idx, topk_w, load, info,
+                                  ws, ws_bytes, stream), "moe_route_logits")
+
+
+def moe_route_certify(cfg, logits, price, topk_idx, cert, ws, ws_bytes, stream):
+    _check(lib().moe_route_certify(ctypes.byref(cfg), logits, price, topk_idx, cert, ws, ws_bytes,
+                                   stream), "moe_route_certify")
+
+
+def moe_logit_stats(cfg, logits, feats, sigma, ws, ws_bytes, stream):
+    _check(lib().moe_logit_stats(ctypes.byref(cfg), logits, feats, sigma, ws, ws_bytes, stream),
+           "moe_logit_stats")
+
+
+def moe_price_mlp_sizes(rows: int):
+    """(n_params, acts_floats, bwd_ws_bytes) for `rows` feature rows."""
+    n = ctypes.c_int32(0)
+    a = ctypes.c_size_t(0)
+    w = ctypes.c_size_t(0)
+    _check(lib().moe_price_mlp_sizes(int(rows), ctypes.byref(n), ctypes.byref(a), ctypes.byref(w)),
+           "moe_price_mlp_sizes")
+    return int(n.value), int(a.value), int(w.value)
+
+
+def moe_price_mlp_forward(rows, feats, params, sigma, price_hat, acts, stream):
+    _check(lib().moe_price_mlp_forward(int(rows), feats, params, sigma, price_hat, acts, stream),
+           "moe_price_mlp_forward")
+
+
+def moe_price_mlp_backward(rows, feats, params, sigma, acts, dprice, dparams, ws, ws_bytes,
+                           stream):
+    _check(lib().moe_price_mlp_backward(int(rows), feats, params, sigma, acts, dprice, dparams, ws,
+                                        ws_bytes, stream), "moe_price_mlp_backward")
+
+
+def moe_price_mse(rows, group, price_hat, target, sigma, dprice, loss, stream):
+    _check(lib().moe_price_mse(int(rows), int(group), price_hat, target, sigma, dprice, loss,
+                               stream), "moe_price_mse")
+
+
+def moe_adam_step(n, params, grads, m, v, lr, beta1, beta2, eps, step, stream):
+    _check(lib().moe_adam_step(int(n), params, grads, m, v, float(lr), float(beta1), float(beta2),
+                               float(eps), int(step), stream), "moe_adam_step")
 
 
 def moe_prof_enable(on: bool) -> None:

@@ -34,6 +34,8 @@ SOURCES = [
     ("dispatch.hip", []),
     ("gemm.hip", []),
     ("bwd.hip", []),
+    ("price.hip", []),
+    ("mlp.hip", []),
     ("api.cpp", []),
     ("prof.cpp", []),
 ]

@@ -11,6 +11,8 @@ size_t dispatch_ws_bytes(const moe_cfg& c);
 size_t ffn_ws_bytes(const moe_cfg& c);
 size_t ffn_bwd_ws_bytes(const moe_cfg& c);
 size_t route_bwd_ws_bytes(const moe_cfg& c);
+size_t stats_ws_bytes(const moe_cfg& c);
+size_t cert_ws_bytes(const moe_cfg& c);
 
 // Host-side argument checks shared by several entry points.
 moe_status check_cfg_shape(const moe_cfg* c);

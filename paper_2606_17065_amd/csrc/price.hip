@@ -1,0 +1,449 @@
+// Batch statistics of router logits for the learned price (eight features
+// per expert), the duality certificate of a routing, and the squared-error
+// loss of predicted prices.
+//
+// moe_logit_stats data flow (one stream):
+//   ls_rows      per token: k-th and (k+1)-th best score, and the expert
+//                holding rank k (defines the plain top-k set at p = 0)
+//   ls_cols      64-token x 64-expert tiles: margins m0, transposed sortable
+//                keys of s and m0, per-tile FP64 column partials
+//   ls_expert    per expert: fold the partials in tile order, (C+1)-th
+//                largest s and m0 by radix select
+//   ls_features  global mean / std (fixed order over experts), features
+#include <math.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int LS_TILE = 64;
+constexpr int NSTAT = 6;  // sum s, sum s^2, max s, sum m0, sum m0^2, load0
+
+template <int L>
+__device__ __forceinline__ void top_insert(uint32_t (&K)[L], int (&X)[L], uint32_t key, int e) {
+  // sorted descending; strict comparison keeps the lower expert first
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    const bool gt = key > K[j];
+    const uint32_t hi = gt ? key : K[j], lo = gt ? K[j] : key;
+    const int eh = gt ? e : X[j], el = gt ? X[j] : e;
+    K[j] = hi;
+    X[j] = eh;
+    key = lo;
+    e = el;
+  }
+}
+
+// One thread per token: the best k+1 experts at zero prices.
+template <int L>
+__global__ __launch_bounds__(256) void ls_rows(const float* __restrict__ s, int T, int E, int k,
+                                               uint32_t* __restrict__ kkey,
+                                               int32_t* __restrict__ kexp,
+                                               float* __restrict__ kap) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= T) return;
+  uint32_t K[L];
+  int X[L];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    K[j] = 0u;
+    X[j] = E;
+  }
+  const float* row = s + (size_t)t * E;
+  for (int e = 0; e < E; ++e) top_insert<L>(K, X, f32_key(row[e]), e);
+  uint32_t k1 = K[0], k2 = K[0];
+  int e1 = X[0];
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    if (j == k - 1) {
+      k1 = K[j];
+      e1 = X[j];
+    }
+    if (j == k) k2 = K[j];
+  }
+  kkey[t] = k1;
+  kexp[t] = e1;
+  kap[2 * t] = key_f32(k1);
+  kap[2 * t + 1] = key_f32(k2);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block (token tile, 64-expert group), 256 threads = 4 waves; lane = token
+// within the tile, wave w handles experts w, w+4, ...  FP64 partials per
+// (tile, expert) are wave reductions in a fixed butterfly order.
+__global__ __launch_bounds__(256) void ls_cols(const float* __restrict__ s, int T, int E,
+                                               const uint32_t* __restrict__ kkey,
+                                               const int32_t* __restrict__ kexp,
+                                               const float* __restrict__ kap,
+                                               uint32_t* __restrict__ sT, uint32_t* __restrict__ mT,
+                                               double* __restrict__ part) {
+  __shared__ float tile[LS_TILE][LS_TILE + 1];
+  const int t0 = blockIdx.x * LS_TILE, e0 = blockIdx.y * LS_TILE, tid = threadIdx.x;
+  for (int i = tid; i < LS_TILE * LS_TILE; i += 256) {
+    const int tl = i >> 6, el = i & 63;
+    const int t = t0 + tl, e = e0 + el;
+    tile[tl][el] = (t < T && e < E) ? s[(size_t)t * E + e] : 0.0f;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  const int t = t0 + lane;
+  const bool valid = t < T;
+  const uint32_t kk = valid ? kkey[t] : 0u;
+  const int ke = valid ? kexp[t] : 0;
+  const float kap1 = valid ? kap[2 * t] : 0.0f, kap2 = valid ? kap[2 * t + 1] : 0.0f;
+  for (int el = wv; el < LS_TILE; el += 4) {
+    const int e = e0 + el;
+    if (e >= E) break;
+    const float v = tile[lane][el];
+    const uint32_t key = f32_key(v);
+    const bool held = key > kk || (key == kk && e <= ke);
+    const float m = v - (held ? kap2 : kap1);
+    if (valid) {
+      sT[(size_t)e * T + t] = key;
+      mT[(size_t)e * T + t] = f32_key(m);
+    }
+    const double dv = valid ? (double)v : 0.0, dm = valid ? (double)m : 0.0;
+    const double r0 = wave_sum(dv);
+    const double r1 = wave_sum(dv * dv);
+    const double r2 = wave_max(valid ? dv : -INFINITY);
+    const double r3 = wave_sum(dm);
+    const double r4 = wave_sum(dm * dm);
+    const double r5 = wave_sum((valid && held) ? 1.0 : 0.0);
+    if (lane == 0) {
+      double* p = part + ((size_t)blockIdx.x * E + e) * NSTAT;
+      p[0] = r0;
+      p[1] = r1;
+      p[2] = r2;
+      p[3] = r3;
+      p[4] = r4;
+      p[5] = r5;
+    }
+  }
+}
+
+// r-th largest key (1-based, r <= n) of col[0..n) by four 8-bit radix
+// passes; 1024 threads.
+__device__ uint32_t block_rth_key(const uint32_t* __restrict__ col, int n, int r, int* hist,
+                                  int* sh) {
+  const int tid = threadIdx.x;
+  uint32_t prefix = 0u, mask = 0u;
+  int need = r;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) {
+      const uint32_t key = col[i];
+      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int acc = 0, dg = 0;
+      for (int b = 255; b >= 0; --b) {
+        if (acc + hist[b] >= need) {
+          dg = b;
+          break;
+        }
+        acc += hist[b];
+      }
+      sh[0] = dg;
+      sh[1] = need - acc;
+    }
+    __syncthreads();
+    prefix |= (uint32_t)sh[0] << shift;
+    mask |= 255u << shift;
+    need = sh[1];
+    __syncthreads();
+  }
+  return prefix;
+}
+
+// One block per expert: fold the tile partials in tile order and select
+// the (C+1)-th largest s and m0 of the expert's column.
+__global__ __launch_bounds__(1024) void ls_expert(const uint32_t* __restrict__ sT,
+                                                  const uint32_t* __restrict__ mT,
+                                                  const double* __restrict__ part, int ntile,
+                                                  int T, int E, int C, double* __restrict__ col,
+                                                  float* __restrict__ q) {
+  __shared__ int hist[256];
+  __shared__ int sh[2];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  if (tid < NSTAT) {
+    double a = tid == 2 ? -INFINITY : 0.0;
+    for (int b = 0; b < ntile; ++b) {
+      const double v = part[((size_t)b * E + e) * NSTAT + tid];
+      a = tid == 2 ? fmax(a, v) : a + v;
+    }
+    col[e * NSTAT + tid] = a;
+  }
+  const int r = C + 1 < T ? C + 1 : T;
+  const uint32_t ks = block_rth_key(sT + (size_t)e * T, T, r, hist, sh);
+  const uint32_t km = block_rth_key(mT + (size_t)e * T, T, r, hist, sh);
+  if (tid == 0) {
+    q[2 * e] = key_f32(ks);
+    q[2 * e + 1] = key_f32(km);
+  }
+}
+
+// One block: global mean / std over all T*E logits (experts summed in
+// index order), then the eight features of every expert.
+__global__ __launch_bounds__(1024) void ls_features(const double* __restrict__ col,
+                                                    const float* __restrict__ q, int T, int E,
+                                                    int C, float* __restrict__ feats,
+                                                    float* __restrict__ sigma_out) {
+  __shared__ double g[2];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int e = 0; e < E; ++e) {
+      s1 += col[e * NSTAT + 0];
+      s2 += col[e * NSTAT + 1];
+    }
+    const double n = (double)T * (double)E;
+    const double mu = s1 / n;
+    double var = s2 / n - mu * mu;
+    var = var > 0.0 ? var : 0.0;
+    double sg = sqrt(var);
+    if (!(sg > 0.0)) sg = 1.0;
+    g[0] = mu;
+    g[1] = sg;
+    if (sigma_out) sigma_out[0] = (float)sg;
+  }
+  __syncthreads();
+  const double mu = g[0], sg = g[1], Tn = (double)T;
+  for (int e = tid; e < E; e += blockDim.x) {
+    const double* c = col + e * NSTAT;
+    const double ms = c[0] / Tn, mm = c[3] / Tn;
+    double vs = c[1] / Tn - ms * ms, vm = c[4] / Tn - mm * mm;
+    vs = vs > 0.0 ? vs : 0.0;
+    vm = vm > 0.0 ? vm : 0.0;
+    float* f = feats + (size_t)e * 8;
+    f[0] = (float)((ms - mu) / sg);
+    f[1] = (float)(sqrt(vs) / sg);
+    f[2] = (float)((c[2] - mu) / sg);
+    f[3] = (float)(((double)q[2 * e] - mu) / sg);
+    f[4] = (float)(c[5] / (double)C);
+    f[5] = (float)(mm / sg);
+    f[6] = (float)((double)q[2 * e + 1] / sg);
+    f[7] = (float)(sqrt(vm) / sg);
+  }
+}
+
+struct StatsWs {
+  uint32_t *kkey, *sT, *mT;
+  int32_t* kexp;
+  float *kap, *q;
+  double *part, *col;
+};
+
+StatsWs carve_stats(const moe_cfg& c, void* base, size_t* total) {
+  WsCarve wc{(char*)base, 0};
+  StatsWs w;
+  const size_t T = (size_t)c.T, E = (size_t)c.E;
+  const size_t ntile = (T + LS_TILE - 1) / LS_TILE;
+  w.kkey = wc.take<uint32_t>(T);
+  w.kexp = wc.take<int32_t>(T);
+  w.kap = wc.take<float>(2 * T);
+  w.sT = wc.take<uint32_t>(T * E);
+  w.mT = wc.take<uint32_t>(T * E);
+  w.part = wc.take<double>(ntile * E * NSTAT);
+  w.col = wc.take<double>(E * NSTAT);
+  w.q = wc.take<float>(2 * E);
+  if (total) *total = align_up(wc.off, 256);
+  return w;
+}
+
+// ------------------------------------------------------------ certificate
+// Per token: primal term sum_j s[t, idx_j] and the dual term
+// topk_sum(s_t - p) (FP64 values of the FP32 ranking); 256-token block
+// partials, folded in block order by cert_final.
+
+template <int L>
+__global__ __launch_bounds__(256) void cert_tokens(const float* __restrict__ s,
+                                                   const float* __restrict__ p,
+                                                   const int32_t* __restrict__ idx, int T, int E,
+                                                   int k, double* __restrict__ part) {
+  __shared__ double sp[256], sd[256];
+  const int tid = threadIdx.x, t = blockIdx.x * 256 + tid;
+  double prim = 0.0, dual = 0.0;
+  if (t < T) {
+    uint32_t K[L];
+    int X[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      K[j] = 0u;
+      X[j] = 0;
+    }
+    const float* row = s + (size_t)t * E;
+    for (int e = 0; e < E; ++e) top_insert<L>(K, X, f32_key(row[e] - p[e]), e);
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+      if (j < k) dual += (double)row[X[j]] - (double)p[X[j]];
+    for (int j = 0; j < k; ++j) {
+      const int e = idx[(size_t)t * k + j];
+      prim += (e >= 0 && e < E) ? (double)row[e] : 0.0;
+    }
+  }
+  sp[tid] = prim;
+  sd[tid] = dual;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (tid < h) {
+      sp[tid] += sp[tid + h];
+      sd[tid] += sd[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[2 * blockIdx.x] = sp[0];
+    part[2 * blockIdx.x + 1] = sd[0];
+  }
+}
+
+__global__ void cert_final(const double* __restrict__ part, int nb, const float* __restrict__ p,
+                           int E, int C, double* __restrict__ cert) {
+  if (threadIdx.x != 0) return;
+  double prim = 0.0, dual = 0.0, ps = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    prim += part[2 * b];
+    dual += part[2 * b + 1];
+  }
+  for (int e = 0; e < E; ++e) ps += (double)p[e];
+  dual += (double)C * ps;
+  cert[0] = prim;
+  cert[1] = dual;
+  const double den = fabs(dual) > 0.0 ? fabs(dual) : 1.0;
+  cert[2] = (dual - prim) / den;
+}
+
+// ------------------------------------------------------------------- mse
+// loss = mean_r (phat_r - y_r)^2 with y_r = target_r / sigma[r / group];
+// dphat_r = 2 (phat_r - y_r) / rows.  One block, fixed-order reduction.
+__global__ __launch_bounds__(1024) void mse_kernel(int rows, int group,
+                                                   const float* __restrict__ phat,
+                                                   const float* __restrict__ target,
+                                                   const float* __restrict__ sigma,
+                                                   float* __restrict__ dphat,
+                                                   float* __restrict__ loss) {
+  __shared__ double red[1024];
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int r = tid; r < rows; r += 1024) {
+    const float y = sigma ? target[r] / sigma[r / group] : target[r];
+    const float d = phat[r] - y;
+    acc += (double)d * (double)d;
+    if (dphat) dphat[r] = 2.0f * d / (float)rows;
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int h = 512; h >= 1; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0 && loss) loss[0] = (float)(red[0] / (double)rows);
+}
+
+}  // namespace
+
+size_t stats_ws_bytes(const moe_cfg& c) {
+  size_t total = 0;
+  carve_stats(c, nullptr, &total);
+  return total;
+}
+
+size_t cert_ws_bytes(const moe_cfg& c) {
+  return align_up(sizeof(double) * 2 * (((size_t)c.T + 255) / 256 + 1), 256);
+}
+
+extern "C" moe_status moe_logit_stats(const moe_cfg* cfg, const float* logits, float* feats,
+                                      float* sigma, void* ws, size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.T < 1 || !logits || !feats) return MOE_EINVAL;
+  if (c.k >= c.E) return MOE_EUNSUPPORTED;
+  if (!aligned(logits, 4) || !aligned(feats, 4) || !aligned(sigma, 4)) return MOE_EINVAL;
+  if (!ws || ws_bytes < stats_ws_bytes(c)) return MOE_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  StatsWs w = carve_stats(c, ws, nullptr);
+  const int L = c.k + 1;
+  const dim3 gr((c.T + 255) / 256);
+  if (L <= 3)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(ls_rows<3>), gr, dim3(256), 0, st, logits, c.T, c.E, c.k,
+                       w.kkey, w.kexp, w.kap);
+  else if (L <= 5)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(ls_rows<5>), gr, dim3(256), 0, st, logits, c.T, c.E, c.k,
+                       w.kkey, w.kexp, w.kap);
+  else if (L <= 9)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(ls_rows<9>), gr, dim3(256), 0, st, logits, c.T, c.E, c.k,
+                       w.kkey, w.kexp, w.kap);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(ls_rows<17>), gr, dim3(256), 0, st, logits, c.T, c.E, c.k,
+                       w.kkey, w.kexp, w.kap);
+  const int ntile = (c.T + LS_TILE - 1) / LS_TILE;
+  hipLaunchKernelGGL(ls_cols, dim3(ntile, (c.E + LS_TILE - 1) / LS_TILE), dim3(256), 0, st,
+                     logits, c.T, c.E, w.kkey, w.kexp, w.kap, w.sT, w.mT, w.part);
+  hipLaunchKernelGGL(ls_expert, dim3(c.E), dim3(1024), 0, st, w.sT, w.mT, w.part, ntile, c.T,
+                     c.E, c.capacity, w.col, w.q);
+  hipLaunchKernelGGL(ls_features, dim3(1), dim3(1024), 0, st, w.col, w.q, c.T, c.E, c.capacity,
+                     feats, sigma);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_route_certify(const moe_cfg* cfg, const float* logits,
+                                        const float* price, const int32_t* topk_idx,
+                                        double* cert, void* ws, size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (!price || !cert || (c.T > 0 && (!logits || !topk_idx))) return MOE_EINVAL;
+  if (!aligned(logits, 4) || !aligned(price, 4) || !aligned(topk_idx, 4) || !aligned(cert, 8))
+    return MOE_EINVAL;
+  if (!ws || ws_bytes < cert_ws_bytes(c)) return MOE_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  double* part = (double*)ws;
+  const int nb = (c.T + 255) / 256;
+  if (nb > 0) {
+    const int L = c.k;
+    if (L <= 2)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(cert_tokens<2>), dim3(nb), dim3(256), 0, st, logits,
+                         price, topk_idx, c.T, c.E, c.k, part);
+    else if (L <= 4)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(cert_tokens<4>), dim3(nb), dim3(256), 0, st, logits,
+                         price, topk_idx, c.T, c.E, c.k, part);
+    else if (L <= 8)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(cert_tokens<8>), dim3(nb), dim3(256), 0, st, logits,
+                         price, topk_idx, c.T, c.E, c.k, part);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(cert_tokens<16>), dim3(nb), dim3(256), 0, st, logits,
+                         price, topk_idx, c.T, c.E, c.k, part);
+  }
+  hipLaunchKernelGGL(cert_final, dim3(1), dim3(64), 0, st, part, nb, price, c.E, c.capacity,
+                     cert);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_price_mse(int rows, int group, const float* price_hat,
+                                    const float* target, const float* sigma, float* dprice,
+                                    float* loss, void* stream) {
+  if (rows < 1 || group < 1 || !price_hat || !target) return MOE_EINVAL;
+  if (!aligned(price_hat, 4) || !aligned(target, 4) || !aligned(sigma, 4) ||
+      !aligned(dprice, 4) || !aligned(loss, 4))
+    return MOE_EINVAL;
+  hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, rows, group,
+                     price_hat, target, sigma, dprice, loss);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}

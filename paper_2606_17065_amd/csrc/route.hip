@@ -35,6 +35,26 @@ __global__ void route_init(int32_t* state, int E, float* price, int mode, float 
   }
 }
 
+// ------------------------------------------------- caller-given logits
+// sT[E,T] from s[T,E] through a 64x64 LDS tile (moe_route_logits).
+
+__global__ __launch_bounds__(256) void logits_transpose(const float* __restrict__ s, int T, int E,
+                                                        float* __restrict__ sT) {
+  __shared__ float tile[64][65];
+  const int t0 = blockIdx.x * 64, e0 = blockIdx.y * 64, tid = threadIdx.x;
+  for (int i = tid; i < 64 * 64; i += 256) {
+    const int tl = i >> 6, el = i & 63;
+    const int t = t0 + tl, e = e0 + el;
+    tile[tl][el] = (t < T && e < E) ? s[(size_t)t * E + e] : 0.0f;
+  }
+  __syncthreads();
+  for (int i = tid; i < 64 * 64; i += 256) {
+    const int el = i >> 6, tl = i & 63;
+    const int t = t0 + tl, e = e0 + el;
+    if (t < T && e < E) sT[(size_t)e * T + t] = tile[tl][el];
+  }
+}
+
 // ------------------------------------------------------------ router GEMM
 // 64 tokens x 64 experts per block, 256 threads, 4x4 outputs per thread,
 // FP32 fused multiply-add accumulation over d in chunks of 32.
@@ -1020,6 +1040,26 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
                      ws.prop, ws.missing);
 }
 
+moe_status route_from_scores(const moe_cfg& c, const RouteWs& w, const float* logits,
+                             float* price, int32_t* topk_idx, float* topk_w, int32_t* load,
+                             int32_t* info, hipStream_t st);
+
+moe_status route_check(const moe_cfg* cfg, const float* logits, float* price, int32_t* topk_idx,
+                       float* topk_w, int32_t* load, int32_t* info, void* ws, size_t ws_bytes) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.price_mode < MOE_PRICE_NONE || c.price_mode > MOE_PRICE_WARM) return MOE_EINVAL;
+  if (c.max_iters < 0) return MOE_EINVAL;
+  if (!price || !load || !info) return MOE_EINVAL;
+  if (c.T > 0 && (!logits || !topk_idx || !topk_w)) return MOE_EINVAL;
+  if (!aligned(logits, 4) || !aligned(price, 4) || !aligned(topk_idx, 4) ||
+      !aligned(topk_w, 4) || !aligned(load, 4) || !aligned(info, 4))
+    return MOE_EINVAL;
+  if (ws_bytes < route_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  return MOE_OK;
+}
+
 }  // namespace
 
 size_t route_ws_bytes(const moe_cfg& c) {
@@ -1032,18 +1072,11 @@ extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* 
                                 const float* br, float* logits, float* price, int32_t* topk_idx,
                                 float* topk_w, int32_t* load, int32_t* info, void* ws,
                                 size_t ws_bytes, void* stream) {
-  moe_status stc = check_cfg_shape(cfg);
+  moe_status stc = route_check(cfg, logits, price, topk_idx, topk_w, load, info, ws, ws_bytes);
   if (stc != MOE_OK) return stc;
   const moe_cfg& c = *cfg;
-  if (c.price_mode < MOE_PRICE_NONE || c.price_mode > MOE_PRICE_WARM) return MOE_EINVAL;
-  if (c.max_iters < 0) return MOE_EINVAL;
-  if (!price || !load || !info) return MOE_EINVAL;
-  if (c.T > 0 && (!X || !Wr || !br || !logits || !topk_idx || !topk_w)) return MOE_EINVAL;
-  if (!aligned(X, 16) || !aligned(Wr, 4) || !aligned(br, 4) || !aligned(logits, 4) ||
-      !aligned(price, 4) || !aligned(topk_idx, 4) || !aligned(topk_w, 4) || !aligned(load, 4) ||
-      !aligned(info, 4))
-    return MOE_EINVAL;
-  if (ws_bytes < route_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  if (c.T > 0 && (!X || !Wr || !br)) return MOE_EINVAL;
+  if (!aligned(X, 16) || !aligned(Wr, 4) || !aligned(br, 4)) return MOE_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   RouteWs w = carve_route(c, ws, nullptr);
   hipLaunchKernelGGL(route_init, dim3(1), dim3(256), 0, st, w.state, c.E, price,
@@ -1068,6 +1101,15 @@ extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* 
                        st, (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
   }
   PROF_END("router_logits", st);
+  return route_from_scores(c, w, logits, price, topk_idx, topk_w, load, info, st);
+}
+
+namespace {
+
+// Everything after the logits: sigma_s, the price loop, weights, repair.
+moe_status route_from_scores(const moe_cfg& c, const RouteWs& w, const float* logits,
+                             float* price, int32_t* topk_idx, float* topk_w, int32_t* load,
+                             int32_t* info, hipStream_t st) {
   const int nb = (c.T + SIG_BLOCK - 1) / SIG_BLOCK;
   hipLaunchKernelGGL(score_partials, dim3(nb), dim3(SIG_BLOCK), 0, st, w.sT, c.T, c.E, w.part);
   hipLaunchKernelGGL(score_sigma, dim3(1), dim3(SIG_BLOCK), 0, st, w.part, nb,
@@ -1088,4 +1130,26 @@ extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* 
   hipLaunchKernelGGL(route_finalize, dim3(1), dim3(64), 0, st, w.state, info, load, c.E, 0);
   MOE_LAUNCH_CHECK();
   return MOE_OK;
+}
+
+}  // namespace
+
+extern "C" moe_status moe_route_logits(const moe_cfg* cfg, const float* logits, float* price,
+                                       int32_t* topk_idx, float* topk_w, int32_t* load,
+                                       int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  moe_status stc = route_check(cfg, logits, price, topk_idx, topk_w, load, info, ws, ws_bytes);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  hipStream_t st = (hipStream_t)stream;
+  RouteWs w = carve_route(c, ws, nullptr);
+  hipLaunchKernelGGL(route_init, dim3(1), dim3(256), 0, st, w.state, c.E, price,
+                     c.price_mode, c.warm_gamma);
+  if (c.T == 0) {
+    hipLaunchKernelGGL(route_finalize, dim3(1), dim3(256), 0, st, w.state, info, load, c.E, 1);
+    MOE_LAUNCH_CHECK();
+    return MOE_OK;
+  }
+  hipLaunchKernelGGL(logits_transpose, dim3((c.T + 63) / 64, (c.E + 63) / 64), dim3(256), 0, st,
+                     logits, c.T, c.E, w.sT);
+  return route_from_scores(c, w, logits, price, topk_idx, topk_w, load, info, st);
 }

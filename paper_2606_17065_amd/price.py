@@ -1,0 +1,232 @@
+"""Learned starting prices: batch logit statistics, the price network, its
+training, and routing that starts from (or replaces) the clearing-price
+update with the exact update as fallback and judge.
+
+Every computation runs in libmoe's kernels; this module allocates device
+tensors, passes pointers and streams, and makes the one host-side decision
+of the judge (fall back to the exact update or not), which needs the
+certificate's value on the host.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import torch
+
+from . import _lib as L
+from .layer import _WS, _need, _p, _stream
+
+GAP_TOL = 1e-3  # relative duality gap the judge accepts
+
+
+def route_logits(cfg, logits, price=None, ws=None):
+    """moe_route from given logits [T,E] f32; returns the routing dict."""
+    T, E, k = cfg.T, cfg.E, cfg.k
+    _need(logits, "logits", torch.float32, (T, E))
+    dev = logits.device
+    if price is None:
+        price = torch.zeros(E, dtype=torch.float32, device=dev)
+    else:
+        _need(price, "price", torch.float32, (E,))
+    out = dict(price=price, idx=torch.empty(T, k, dtype=torch.int32, device=dev),
+               w=torch.empty(T, k, dtype=torch.float32, device=dev),
+               load=torch.empty(E, dtype=torch.int32, device=dev),
+               info=torch.zeros(L.INFO_LEN, dtype=torch.int32, device=dev))
+    ws = _WS.get(cfg, dev) if ws is None else ws
+    L.moe_route_logits(cfg, _p(logits), _p(price), _p(out["idx"]), _p(out["w"]), _p(out["load"]),
+                       _p(out["info"]), _p(ws), ws.numel(), _stream())
+    return out
+
+
+def certify(cfg, logits, price, idx, ws=None):
+    """[primal, dual, gap_rel] (f64 device tensor) of a routing under prices."""
+    _need(logits, "logits", torch.float32, (cfg.T, cfg.E))
+    _need(idx, "topk_idx", torch.int32, (cfg.T, cfg.k))
+    cert = torch.empty(3, dtype=torch.float64, device=logits.device)
+    ws = _WS.get(cfg, logits.device) if ws is None else ws
+    L.moe_route_certify(cfg, _p(logits), _p(price), _p(idx), _p(cert), _p(ws), ws.numel(),
+                        _stream())
+    return cert
+
+
+def logit_stats(cfg, logits, ws=None):
+    """(features [E,8] f32, sigma [1] f32) of a batch of logits."""
+    _need(logits, "logits", torch.float32, (cfg.T, cfg.E))
+    dev = logits.device
+    feats = torch.empty(cfg.E, 8, dtype=torch.float32, device=dev)
+    sigma = torch.empty(1, dtype=torch.float32, device=dev)
+    ws = _WS.get(cfg, dev) if ws is None else ws
+    L.moe_logit_stats(cfg, _p(logits), _p(feats), _p(sigma), _p(ws), ws.numel(), _stream())
+    return feats, sigma
+
+
+def n_params() -> int:
+    return L.moe_price_mlp_sizes(0)[0]
+
+
+def mlp_forward(params, feats, sigma=None):
+    """(p_hat [rows], acts) for features [rows,8]; sigma None = sigma units."""
+    rows = feats.shape[0]
+    _need(feats, "feats", torch.float32, (rows, 8))
+    _need(params, "params", torch.float32, (n_params(),))
+    _, nacts, _ = L.moe_price_mlp_sizes(rows)
+    acts = torch.empty(max(nacts, 1), dtype=torch.float32, device=feats.device)
+    phat = torch.empty(rows, dtype=torch.float32, device=feats.device)
+    L.moe_price_mlp_forward(rows, _p(feats), _p(params), _p(sigma), _p(phat), _p(acts), _stream())
+    return phat, acts
+
+
+def mlp_backward(params, feats, acts, dprice, sigma=None, ws=None):
+    rows = feats.shape[0]
+    _, _, nws = L.moe_price_mlp_sizes(rows)
+    if ws is None or ws.numel() < nws:
+        ws = torch.empty(max(nws, 256), dtype=torch.uint8, device=feats.device)
+    dparams = torch.empty_like(params)
+    L.moe_price_mlp_backward(rows, _p(feats), _p(params), _p(sigma), _p(acts), _p(dprice),
+                             _p(dparams), _p(ws), ws.numel(), _stream())
+    return dparams
+
+
+def mse(phat, target, sigma=None, group=None):
+    """(loss [1], dprice [rows]) of p_hat against target / sigma[r // group]."""
+    rows = phat.shape[0]
+    group = rows if group is None else group
+    loss = torch.empty(1, dtype=torch.float32, device=phat.device)
+    dprice = torch.empty(rows, dtype=torch.float32, device=phat.device)
+    L.moe_price_mse(rows, group, _p(phat), _p(target), _p(sigma), _p(dprice), _p(loss), _stream())
+    return loss, dprice
+
+
+class Adam:
+    """Adam state over one parameter vector; step() runs moe_adam_step."""
+
+    def __init__(self, params, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+        self.params, self.lr, self.betas, self.eps = params, lr, betas, eps
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.t = 0
+
+    def step(self, grads):
+        self.t += 1
+        L.moe_adam_step(self.params.numel(), _p(self.params), _p(grads), _p(self.m), _p(self.v),
+                        self.lr, self.betas[0], self.betas[1], self.eps, self.t, _stream())
+
+
+@dataclasses.dataclass
+class PriceDataset:
+    """Rows of (features, target price, sigma) for B batches of E experts;
+    row r belongs to batch r // E."""
+
+    feats: torch.Tensor  # [B*E, 8]
+    target: torch.Tensor  # [B*E] clearing prices p*
+    sigma: torch.Tensor  # [B]
+    iters: torch.Tensor  # [B] int32: price updates the exact update needed
+    E: int
+
+
+def build_dataset(batches, E, k, max_iters=50):
+    """batches: iterable of (logits [T,E] f32 device tensor, C).  Features
+    and sigma from moe_logit_stats, targets from the exact clearing-price
+    update (moe_route_logits, MOE_PRICE_ACP, starting at p = 0)."""
+    feats, target, sigma, iters = [], [], [], []
+    for s, C in batches:
+        cfg = L.make_cfg(s.shape[0], 8, E, k, 1, C, max_iters, L.MOE_F32, L.MOE_F32,
+                         L.MOE_PRICE_ACP)
+        f, sg = logit_stats(cfg, s)
+        r = route_logits(cfg, s)
+        feats.append(f)
+        sigma.append(sg)
+        target.append(r["price"])
+        iters.append(r["info"][L.INFO_ITERS:L.INFO_ITERS + 1])
+    return PriceDataset(torch.cat(feats), torch.cat(target), torch.cat(sigma),
+                        torch.cat(iters), E)
+
+
+def init_params(seed: int, device) -> torch.Tensor:
+    """He-normal weights, zero biases (the network's starting point)."""
+    g = torch.Generator().manual_seed(seed)
+    H, NF = 256, 8
+    parts = [torch.randn(H * NF, generator=g, dtype=torch.float64) * (2.0 / NF) ** 0.5,
+             torch.zeros(H, dtype=torch.float64),
+             torch.randn(H * H, generator=g, dtype=torch.float64) * (2.0 / H) ** 0.5,
+             torch.zeros(H, dtype=torch.float64),
+             torch.randn(H, generator=g, dtype=torch.float64) * (1.0 / H) ** 0.5,
+             torch.zeros(1, dtype=torch.float64)]
+    return torch.cat(parts).to(torch.float32).to(device)
+
+
+def train(ds: PriceDataset, steps=2000, batches_per_step=32, lr=1e-3, seed=0, params=None,
+          log_every=0):
+    """Adam on the mean squared error of softplus(z) against p*/sigma over
+    minibatches of whole batches (consecutive in a fixed seeded order of
+    the dataset).  Returns (params, list of (step, loss))."""
+    dev = ds.feats.device
+    B, E = ds.sigma.numel(), ds.E
+    params = init_params(seed, dev) if params is None else params
+    opt = Adam(params, lr=lr)
+    perm = torch.randperm(B, generator=torch.Generator().manual_seed(seed + 1))
+    rows_idx = (perm[:, None] * E + torch.arange(E)[None, :]).reshape(-1).to(dev)
+    feats = ds.feats.index_select(0, rows_idx).contiguous()
+    target = ds.target.index_select(0, rows_idx).contiguous()
+    sigma = ds.sigma.index_select(0, perm.to(dev)).contiguous()
+    mb = min(batches_per_step, B)
+    rows = mb * E
+    _, _, nws = L.moe_price_mlp_sizes(rows)
+    ws = torch.empty(max(nws, 256), dtype=torch.uint8, device=dev)
+    hist = []
+    for step in range(steps):
+        b0 = (step * mb) % (B - mb + 1) if B > mb else 0
+        F = feats[b0 * E:(b0 + mb) * E]
+        y = target[b0 * E:(b0 + mb) * E]
+        sg = sigma[b0:b0 + mb]
+        phat, acts = mlp_forward(params, F)
+        loss, dprice = mse(phat, y, sg, group=E)
+        grads = mlp_backward(params, F, acts, dprice, ws=ws)
+        opt.step(grads)
+        if log_every and (step % log_every == 0 or step == steps - 1):
+            hist.append((step, float(loss.item())))
+    return params, hist
+
+
+def predict(cfg, logits, params):
+    """p_hat [E] for one batch of logits: statistics, then the network."""
+    feats, sigma = logit_stats(cfg, logits)
+    phat, _ = mlp_forward(params, feats, sigma)
+    return phat
+
+
+def learned_route(cfg, logits, params, mode="warm", gamma=0.9):
+    """Route one batch with learned prices.
+
+    warm:    p0 = gamma * p_hat, then the exact clearing-price update.
+    replace: route under p_hat alone (no update; the capacity repair runs
+             if an expert overflows); the violation V = overflow / N is
+             reported; the judge accepts the result when V = 0 and the
+             certificate's relative gap is <= GAP_TOL, else the batch is
+             routed again by the exact update from p = 0.
+    Returns the routing dict plus p_hat, and for replace: V, gap, fallback."""
+    phat = predict(cfg, logits, params)
+    if mode == "warm":
+        c = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act,
+                       cfg.w, L.MOE_PRICE_WARM, gamma)
+        r = route_logits(c, logits, phat.clone())
+        r["p_hat"] = phat
+        return r
+    if mode != "replace":
+        raise ValueError(f"unknown mode {mode!r}")
+    c = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act,
+                   cfg.w, L.MOE_PRICE_GIVEN)
+    r = route_logits(c, logits, phat.clone())
+    info = r["info"].cpu()
+    overflow = int(info[L.INFO_OVERFLOW])
+    V = overflow / float(cfg.T * cfg.k)
+    gap = float("nan")
+    if overflow == 0:
+        gap = float(certify(c, logits, r["price"], r["idx"])[2].item())
+    accept = overflow == 0 and gap <= GAP_TOL
+    if not accept:
+        c0 = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity, cfg.max_iters,
+                        cfg.act, cfg.w, L.MOE_PRICE_ACP)
+        r = route_logits(c0, logits)
+    r.update(p_hat=phat, V=V, gap=gap, fallback=not accept)
+    return r

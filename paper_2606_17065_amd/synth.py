@@ -117,3 +117,34 @@ def tiny_logits(T: int, E: int, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     b = zipf_bias(rng, E, 1.0)
     return (rng.standard_normal((T, E), dtype=np.float32) + b[None, :]).astype(np.float32)
+
+
+def price_batch_logits(i: int, E: int = 256, d: int = 2048, k: int = 8,
+                       t_min: int = 4096, t_max: int = 65536, Wr: np.ndarray | None = None):
+    """Training batch ``i`` of the learned-price workload: router logits
+    drawn without tokens, s = Z L^T + b with L = chol(W_r W_r^T) (rows of
+    X W_r^T for X ~ N(0, 1) have exactly this law), Z ~ N(0, 1) [T, E].
+
+    T is log-uniform over the integers [t_min, t_max]; the Zipf exponent is
+    U[1.0, 1.5] per batch.  ``Wr`` defaults to the learned-price workload's
+    router weights (workload 5, rep 0).  Returns (logits [T,E] float32, C)."""
+    if Wr is None:
+        Wr = router_weights(5, E, d)
+    L = np.linalg.cholesky(Wr.astype(np.float64) @ Wr.astype(np.float64).T).astype(np.float32)
+    rng = np.random.Generator(np.random.PCG64(5_000_000 + i))
+    T = int(math.floor(math.exp(rng.uniform(math.log(t_min), math.log(t_max + 1)))))
+    T = min(max(T, t_min), t_max)
+    s_z = float(rng.uniform(1.0, 1.5))
+    b = zipf_bias(rng, E, s_z)
+    z = rng.standard_normal((T, E), dtype=np.float32)
+    s = (z @ L.T + b[None, :]).astype(np.float32)
+    return s, capacity(T, k, E)
+
+
+def router_weights(config: int, E: int, d: int, rep: int = 0) -> np.ndarray:
+    """The W_r that make_inputs(config, rep) draws (same stream position)."""
+    rng = rng_for(config, rep)
+    shape = SHAPES[config]
+    rng.standard_normal((shape.T, shape.d), dtype=np.float32)  # X
+    assert shape.d == d and shape.E == E
+    return (0.02 * rng.standard_normal((E, d), dtype=np.float32)).astype(np.float32)

@@ -1,0 +1,222 @@
+"""GPU parity of the learned-price path (logit statistics, price network,
+its loss, backward and Adam, routing from given logits, the certificate)
+against the CPU oracle, through the C ABI.
+
+Tolerances (FP32 kernels against FP64 definitions):
+  features      |gpu - ref| <= 2e-6 * max(1, |ref|): FP64 sums rounded to
+                FP32 once; the GPU's margins are FP32-rounded differences,
+                the oracle's exact, which moves a quantile by <= 1 ulp
+  network       p_hat and the loss: rel <= 1e-5 (FP32 dot products of
+                length <= 256); gradients: rel. Frobenius <= 2e-5 per block
+  Adam          rtol 1e-6 after three steps
+  certificate   primal and dual: rel <= 1e-12 (FP64 sums of the same FP32
+                values in another order)
+Routing from given logits (any price mode, learned prices included) must be
+bit-identical to the FP32 replica given the same logits and p_hat.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as M
+from oracle import routing as R
+from paper_2606_17065_amd import _lib as L
+from paper_2606_17065_amd import price as P
+from paper_2606_17065_amd import synth
+
+from _helpers import assert_route_matches, rel_fro, replica_route
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+def _cfg(T, E, k, C=None, mode=L.MOE_PRICE_ACP, gamma=0.9, max_iters=50):
+    C = synth.capacity(T, k, E) if C is None else C
+    return L.make_cfg(T, 8, E, k, 1, C, max_iters, L.MOE_F32, L.MOE_F32, mode, gamma)
+
+
+def _logits(T, E, seed, s_z=1.2):
+    s = synth.make_logits(T, E, s_z, seed)
+    return s, torch.from_numpy(s).cuda()
+
+
+# (T, E, k, capacity or None, seed): ragged tiles, E not a multiple of 64,
+# k = 1 and k = E - 1, T <= C (quantile = column minimum), a wide batch
+STATS_CASES = [(1000, 64, 8, None, 51), (333, 40, 3, None, 52), (50, 5, 4, None, 53),
+               (777, 100, 1, None, 54), (4100, 256, 8, None, 55), (200, 17, 16, 200, 56),
+               (65, 3, 2, 70, 57)]
+
+
+@pytest.mark.parametrize("T,E,k,C,seed", STATS_CASES)
+def test_logit_stats_match_oracle(T, E, k, C, seed):
+    s, sd = _logits(T, E, seed)
+    cfg = _cfg(T, E, k, C)
+    feats, sigma = P.logit_stats(cfg, sd)
+    torch.cuda.synchronize()
+    ref = M.features(s, k, cfg.capacity)
+    got = feats.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 2e-6, (err.max(), np.unravel_index(err.argmax(), err.shape))
+    # the plain top-k loads behind f4 are integers and must agree exactly
+    np.testing.assert_array_equal(np.rint(got[:, 4] * cfg.capacity),
+                                  np.rint(ref[:, 4] * cfg.capacity))
+    assert abs(float(sigma.item()) - s.astype(np.float64).std()) <= 1e-6 * s.std()
+
+
+def test_logit_stats_rejects_bad_shapes():
+    s, sd = _logits(10, 4, 1)
+    with pytest.raises(L.MoEError) as e:
+        P.logit_stats(_cfg(10, 4, 4, 10), sd)  # k == E: no (k+1)-th score
+    assert e.value.status == L.MOE_EUNSUPPORTED
+    cfg = _cfg(0, 4, 2, 0)
+    with pytest.raises(L.MoEError) as e:
+        L.moe_logit_stats(cfg, 0, sd.data_ptr(), 0, sd.data_ptr(), 1 << 20, 0)
+    assert e.value.status == L.MOE_EINVAL
+
+
+def _feature_rows(R_, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((R_, 8)).astype(F32)
+
+
+def test_mlp_forward_matches_oracle():
+    theta = M.init_params(3)
+    F = _feature_rows(300, 4)
+    params = torch.from_numpy(theta).cuda()
+    sigma = torch.tensor([1.7], dtype=torch.float32, device="cuda")
+    phat, acts = P.mlp_forward(params, torch.from_numpy(F).cuda(), sigma)
+    torch.cuda.synchronize()
+    z, _ = M.forward(theta.astype(np.float64), F.astype(np.float64))
+    ref = np.float64(F32(1.7)) * M.softplus(z)
+    got = phat.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    nz = acts[4 * 256 * 300:].cpu().numpy()
+    assert np.abs(nz - z).max() <= 1e-5 * max(1.0, np.abs(z).max())
+
+
+@pytest.mark.parametrize("rows", [1, 300, 1100])
+def test_mlp_loss_and_gradient_match_oracle(rows):
+    theta = M.init_params(5 + rows)
+    F = _feature_rows(rows, 6 + rows)
+    y = np.abs(np.random.Generator(np.random.PCG64(rows)).standard_normal(rows)).astype(F32)
+    params = torch.from_numpy(theta).cuda()
+    Fd = torch.from_numpy(F).cuda()
+    phat, acts = P.mlp_forward(params, Fd)
+    loss, dprice = P.mse(phat, torch.from_numpy(y).cuda())
+    grads = P.mlp_backward(params, Fd, acts, dprice)
+    torch.cuda.synchronize()
+    ref_loss, ref_g = M.loss_and_grad(theta.astype(np.float64), F.astype(np.float64), y)
+    assert abs(float(loss.item()) - ref_loss) <= 1e-5 * abs(ref_loss)
+    g = grads.cpu().numpy()
+    o = 0
+    for name, shp in M.SIZES:
+        n = int(np.prod(shp))
+        assert rel_fro(g[o:o + n], ref_g[o:o + n]) <= 2e-5, name
+        o += n
+
+
+def test_mse_groups_divide_by_their_sigma():
+    E, B = 7, 5
+    rng = np.random.Generator(np.random.PCG64(9))
+    ph = rng.standard_normal(E * B).astype(F32)
+    tg = rng.uniform(0, 3, E * B).astype(F32)
+    sg = rng.uniform(0.5, 2, B).astype(F32)
+    loss, dp = P.mse(torch.from_numpy(ph).cuda(), torch.from_numpy(tg).cuda(),
+                     torch.from_numpy(sg).cuda(), group=E)
+    torch.cuda.synchronize()
+    y = tg.astype(np.float64) / np.repeat(sg.astype(np.float64), E)
+    r = ph - y
+    assert abs(float(loss.item()) - np.mean(r * r)) <= 1e-6 * np.mean(r * r)
+    np.testing.assert_allclose(dp.cpu().numpy(), 2 * r / (E * B), rtol=1e-5, atol=1e-8)
+
+
+def test_adam_matches_oracle():
+    n = M.N_PARAMS
+    rng = np.random.Generator(np.random.PCG64(11))
+    theta = M.init_params(12)
+    p = torch.from_numpy(theta.copy()).cuda()
+    opt = P.Adam(p, lr=1e-2)
+    th, m, v = theta.astype(np.float64), np.zeros(n), np.zeros(n)
+    for step in range(1, 4):
+        g = (rng.standard_normal(n) * 10.0 ** rng.uniform(-4, 0, n)).astype(F32)
+        opt.step(torch.from_numpy(g).cuda())
+        th, m, v = M.adam_step(th, g.astype(np.float64), m, v, step, 1e-2)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(p.cpu().numpy(), th, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("mode", [L.MOE_PRICE_ACP, L.MOE_PRICE_NONE])
+def test_route_logits_bit_exact(mode):
+    s, sd = _logits(3001, 48, 61)
+    cfg = _cfg(3001, 48, 6, mode=mode)
+    r = P.route_logits(cfg, sd)
+    torch.cuda.synchronize()
+    ref = replica_route(cfg, s)
+    if mode == L.MOE_PRICE_ACP:
+        assert ref["iters"] > 0
+    assert_route_matches(cfg, r, ref)
+
+
+def test_route_logits_empty_batch():
+    cfg = _cfg(0, 8, 2, 0)
+    r = P.route_logits(cfg, torch.empty(0, 8, device="cuda"))
+    torch.cuda.synchronize()
+    assert int(r["info"][L.INFO_STATUS]) == 0 and int(r["load"].sum()) == 0
+
+
+def test_certificate_matches_oracle():
+    s, sd = _logits(2500, 32, 71)
+    cfg = _cfg(2500, 32, 4)
+    r = P.route_logits(cfg, sd)
+    cert = P.certify(cfg, sd, r["price"], r["idx"]).cpu().numpy()
+    p = r["price"].cpu().numpy()
+    sel = r["idx"].cpu().numpy()
+    prim = R.primal_objective(s, sel)
+    dual = R.dual_objective(s, p, cfg.k, cfg.capacity)
+    assert abs(cert[0] - prim) <= 1e-12 * abs(prim)
+    assert abs(cert[1] - dual) <= 1e-12 * abs(dual)
+    assert abs(cert[2] - (dual - prim) / abs(dual)) <= 1e-12
+    if not int(r["info"][L.INFO_REPAIRED]):
+        load = r["load"].cpu().numpy()
+        ident = float(np.sum(p.astype(np.float64) * (cfg.capacity - load)))
+        assert abs((cert[1] - cert[0]) - ident) <= 1e-9 * abs(dual)
+    assert cert[2] <= 1e-3  # the update's own epsilon-optimality
+
+
+def _small_dataset(n, E, k, seed0):
+    out = []
+    for i in range(n):
+        T = 600 + (i * 397) % 2500
+        s = synth.make_logits(T, E, 1.0 + 0.5 * ((i * 7) % 11) / 10.0, seed0 + i)
+        out.append((torch.from_numpy(s).cuda(), synth.capacity(T, k, E)))
+    return out
+
+
+def test_learned_prices_train_and_route_bit_exact():
+    E, k = 64, 8
+    ds = P.build_dataset(_small_dataset(24, E, k, 900), E, k)
+    params, hist = P.train(ds, steps=300, batches_per_step=8, lr=1e-3, seed=3, log_every=50)
+    torch.cuda.synchronize()
+    assert hist[-1][1] < 0.5 * hist[0][1], hist
+    T = 2048
+    s = synth.make_logits(T, E, 1.25, 12345)
+    sd = torch.from_numpy(s).cuda()
+    cfg = _cfg(T, E, k)
+    # warm start: bit-exact against the replica started from gamma * p_hat
+    rw = P.learned_route(cfg, sd, params, mode="warm")
+    torch.cuda.synchronize()
+    phat = rw["p_hat"].cpu().numpy()
+    cw = _cfg(T, E, k, mode=L.MOE_PRICE_WARM)
+    assert_route_matches(cw, rw, replica_route(cw, s, phat))
+    cold = replica_route(_cfg(T, E, k), s)
+    # replace: either accepted with no violation and a small gap, or the
+    # exact update from zero prices
+    rr = P.learned_route(cfg, sd, params, mode="replace")
+    torch.cuda.synchronize()
+    if rr["fallback"]:
+        assert_route_matches(cfg, rr, cold)
+    else:
+        assert rr["V"] == 0.0 and rr["gap"] <= P.GAP_TOL
+        cg = _cfg(T, E, k, mode=L.MOE_PRICE_GIVEN)
+        assert_route_matches(cg, rr, replica_route(cg, s, phat))
