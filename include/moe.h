@@ -231,10 +231,14 @@ moe_status moe_adam_step(int n, float* params, const float* grads, float* m, flo
  *   of (t, topk_idx[t, j]); X_perm[slot] = X[row_map[slot]].
  *   X [T,d] act; topk_idx [T,k] i32; offsets [E+1] i32 out;
  *   row_map [N] i32 out; inv_map [T,k] i32 out; X_perm [N,d] act out.
+ *   FP8 experts (cfg.w == MOE_FP8E4M3, d % 128 == 0): every token row is
+ *   quantised per 1 x 128 block as moe_quantize_fp8 does and X_perm [N,d]
+ *   u8 receives the codes, X_perm_scale [N, d/128] f32 the scales (NULL
+ *   otherwise).
  */
 moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int32_t* topk_idx,
                         int32_t* offsets, int32_t* row_map, int32_t* inv_map, void* X_perm,
-                        void* ws, size_t ws_bytes, void* stream);
+                        float* X_perm_scale, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * moe_expert_ffn -- grouped SwiGLU experts over uneven per-expert row counts.
@@ -244,13 +248,36 @@ moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int32_t* topk_i
  *     stored in cfg.act between the two products.
  *   W13 [E, 2f, d] cfg.w (rows 0..f-1 = W1_e, rows f..2f-1 = W3_e);
  *   W2 [E, d, f] cfg.w; X_perm [N,d] act; Y [N,d] act out.
- *   W13_scale / W2_scale: per-128x128-block FP32 scales when cfg.w is
- *   MOE_FP8E4M3, else ignored (may be NULL).
+ *   Supported: act = w = MOE_F32; act = w = MOE_BF16 (d % 128 == 0,
+ *   f % 64 == 0); act = MOE_BF16 with w = MOE_FP8E4M3 (d % 128 == 0,
+ *   f % 128 == 0).
+ *   FP8 experts: X_perm [N,d] u8 codes with X_perm_scale [N, d/128] (as
+ *   moe_dispatch writes them); W13 / W2 u8 codes with W13_scale
+ *   [E, 2f/128, d/128] and W2_scale [E, d/128, f/128] (128 x 128 blocks, as
+ *   moe_quantize_fp8 writes them).  Every product accumulates each 128-wide
+ *   K block on its own and adds it to the FP32 result times sa * sb; h is
+ *   rounded to BF16 and re-quantised per 1 x 128 block before the second
+ *   product; Y is BF16.  The scale pointers are ignored (may be NULL) for
+ *   the other dtypes.
  */
-moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm, const int32_t* offsets,
-                          const void* W13, const float* W13_scale, const void* W2,
-                          const float* W2_scale, void* Y, void* ws, size_t ws_bytes,
-                          void* stream);
+moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm, const float* X_perm_scale,
+                          const int32_t* offsets, const void* W13, const float* W13_scale,
+                          const void* W2, const float* W2_scale, void* Y, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/*
+ * moe_quantize_fp8 -- OCP FP8 e4m3 block quantisation of src [rows, cols]
+ *   (src_dtype MOE_F32 or MOE_BF16; cols % 128 == 0) in blocks of
+ *   block_rows x 128 (block_rows 1 or 128; a ragged last row block is
+ *   allowed).  Per block: amax = max |x| (FP32); if amax == 0 the scale is
+ *   1 and every code 0, else inv = fl32(448 / amax), code = e4m3 of
+ *   fl32(x * inv) rounded to nearest even and saturated to +-448, scale =
+ *   fl32(amax / 448).  codes [rows, cols] u8 out (8-byte aligned); scales
+ *   [ceil(rows / block_rows), cols / 128] f32 out.  Expert weights [E, R, C]
+ *   quantise as rows = E * R when R % 128 == 0.
+ */
+moe_status moe_quantize_fp8(int rows, int cols, int block_rows, int src_dtype, const void* src,
+                            uint8_t* codes, float* scales, void* stream);
 
 /*
  * moe_combine -- out[t] = sum_j topk_w[t,j] * Y[inv_map[t,j]], accumulated
@@ -324,7 +351,8 @@ moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const float* Wr,
  * by a HIP event pair on its stream.  moe_prof_get waits for the recorded
  * events and returns the summed elapsed time and the launch count of one
  * kernel name: "router_logits", "price_loop", "dispatch", "gemm1_swiglu",
- * "gemm2", "combine", "combine_bwd", "ffn_bwd", "dispatch_bwd", "route_bwd".
+ * "gemm2", "quant_h" (FP8 experts), "combine", "combine_bwd", "ffn_bwd",
+ * "dispatch_bwd", "route_bwd".
  * moe_prof_reset forgets every record.
  */
 moe_status moe_prof_enable(int on);

@@ -52,8 +52,9 @@ _CFG = ctypes.POINTER(MoeCfg)
 SIGNATURES = {
     "moe_workspace_bytes": [_CFG, ctypes.POINTER(ctypes.c_size_t)],
     "moe_route": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
-    "moe_dispatch": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
-    "moe_expert_ffn": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_dispatch": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_expert_ffn": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_quantize_fp8": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P],
     "moe_combine": [_CFG, _P, _P, _P, _P, _P],
     "moe_combine_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P],
     "moe_expert_ffn_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
@@ -120,14 +121,21 @@ def moe_route(cfg, X, Wr, br, logits, price, topk_idx, topk_w, load, info, ws, w
                            info, ws, ws_bytes, stream), "moe_route")
 
 
-def moe_dispatch(cfg, X, topk_idx, offsets, row_map, inv_map, X_perm, ws, ws_bytes, stream):
+def moe_dispatch(cfg, X, topk_idx, offsets, row_map, inv_map, X_perm, X_perm_scale, ws, ws_bytes,
+                 stream):
     _check(lib().moe_dispatch(ctypes.byref(cfg), X, topk_idx, offsets, row_map, inv_map, X_perm,
-                              ws, ws_bytes, stream), "moe_dispatch")
+                              X_perm_scale, ws, ws_bytes, stream), "moe_dispatch")
 
 
-def moe_expert_ffn(cfg, X_perm, offsets, W13, W13_scale, W2, W2_scale, Y, ws, ws_bytes, stream):
-    _check(lib().moe_expert_ffn(ctypes.byref(cfg), X_perm, offsets, W13, W13_scale, W2, W2_scale,
-                                Y, ws, ws_bytes, stream), "moe_expert_ffn")
+def moe_expert_ffn(cfg, X_perm, X_perm_scale, offsets, W13, W13_scale, W2, W2_scale, Y, ws,
+                   ws_bytes, stream):
+    _check(lib().moe_expert_ffn(ctypes.byref(cfg), X_perm, X_perm_scale, offsets, W13, W13_scale,
+                                W2, W2_scale, Y, ws, ws_bytes, stream), "moe_expert_ffn")
+
+
+def moe_quantize_fp8(rows, cols, block_rows, src_dtype, src, codes, scales, stream):
+    _check(lib().moe_quantize_fp8(int(rows), int(cols), int(block_rows), int(src_dtype), src, codes,
+                                  scales, stream), "moe_quantize_fp8")
 
 
 def moe_combine(cfg, Y, inv_map, topk_w, out, stream):

@@ -44,6 +44,36 @@ __device__ __forceinline__ float key_f32(uint32_t k) {
 __device__ __forceinline__ float bf2f(bf16_t x) { return (float)x; }
 __device__ __forceinline__ bf16_t f2bf(float x) { return (bf16_t)x; }
 
+// OCP FP8 e4m3 code of an FP32 value: round to nearest, ties to the even
+// mantissa, saturate to +-448 (no infinities; the sign of zero is kept).
+// Subnormals (|v| < 2^-6) have the quantum 2^-9; normals 2^(e-3).
+__device__ __forceinline__ uint32_t fp8_encode(float v) {
+  const uint32_t u = __float_as_uint(v);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const float a = __uint_as_float(u & 0x7FFFFFFFu);
+  uint32_t code;
+  if (!(a < 448.0f)) {
+    code = 0x7Eu;  // 448 and everything that rounds or saturates to it
+  } else if (a < 0.015625f) {
+    code = (uint32_t)rintf(a * 512.0f);  // 0..8; 8 is the code of 2^-6
+  } else {
+    const int e = (int)((__float_as_uint(a) >> 23) & 0xFFu) - 127;  // -6..8
+    const float p = __uint_as_float((uint32_t)(130 - e) << 23);     // 2^(3-e)
+    uint32_t m = (uint32_t)rintf(a * p);                              // 8..16
+    int ee = e;
+    if (m == 16u) {
+      m = 8u;
+      ee += 1;
+    }
+    code = ((uint32_t)(ee + 7) << 3) | (m - 8u);
+    code = code > 0x7Eu ? 0x7Eu : code;
+  }
+  return code | sign;
+}
+
+typedef uint8_t fp8_t;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 template <typename T> struct ActIO;
 template <> struct ActIO<float> {
   __device__ static __forceinline__ float ld(const float* p, size_t i) { return p[i]; }

@@ -132,6 +132,63 @@ __global__ __launch_bounds__(256) void dispatch_gather(const u32x4* __restrict__
   }
 }
 
+// FP8 variant of the gather: each token row is quantised once per 1 x 128
+// block (amax over the block, inv = 448 / amax, codes of x * inv, scale =
+// amax / 448; an all-zero block has scale 1 and zero codes) and the codes
+// and scales are written to all k slots of the token.  One wavefront per
+// token; 16 lanes of 8 elements cover one block.
+template <typename TA>
+__global__ __launch_bounds__(256) void dispatch_gather_fp8(const TA* __restrict__ X, int T, int d,
+                                                           int k,
+                                                           const int32_t* __restrict__ inv_map,
+                                                           fp8_t* __restrict__ Xq,
+                                                           float* __restrict__ Xs) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= T) return;
+  int slots[MOE_MAX_K];
+#pragma unroll
+  for (int j = 0; j < MOE_MAX_K; ++j)
+    slots[j] = j < k ? clampi(inv_map[(size_t)t * k + j], 0, T * k - 1) : 0;
+  const int nblk = d / 128;
+  for (int c0 = 0; c0 < d; c0 += 512) {
+    const int col = c0 + lane * 8;
+    const bool act = col < d;
+    float v[8];
+    if (act) {
+      const TA* src = X + (size_t)t * d + col;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = ActIO<TA>::ld(src, i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = 0.0f;
+    }
+    float am = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) am = fmaxf(am, fabsf(v[i]));
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) am = fmaxf(am, __shfl_xor(am, o, 64));
+    const bool nz = am > 0.0f;
+    const float inv = nz ? 448.0f / am : 1.0f;
+    const float scale = nz ? am / 448.0f : 1.0f;
+    u32x2 q;
+    q[0] = q[1] = 0u;
+    if (nz) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) q[i >> 2] |= fp8_encode(v[i] * inv) << (8 * (i & 3));
+    }
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < MOE_MAX_K; ++j) {
+        if (j < k) {
+          *(u32x2*)(Xq + (size_t)slots[j] * d + col) = q;
+          if ((lane & 15) == 0) Xs[(size_t)slots[j] * nblk + col / 128] = scale;
+        }
+      }
+    }
+  }
+}
+
 // out[t] = sum_j w[t,j] * Y[inv_map[t,j]], FP32 in j order; one wavefront
 // per token, 8 elements per lane per step.
 template <typename TA>
@@ -189,12 +246,17 @@ size_t dispatch_ws_bytes(const moe_cfg& c) {
 
 extern "C" moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int32_t* topk_idx,
                                    int32_t* offsets, int32_t* row_map, int32_t* inv_map,
-                                   void* X_perm, void* ws, size_t ws_bytes, void* stream) {
+                                   void* X_perm, float* X_perm_scale, void* ws, size_t ws_bytes,
+                                   void* stream) {
   moe_status stc = check_cfg_shape(cfg);
   if (stc != MOE_OK) return stc;
   const moe_cfg& c = *cfg;
+  const bool fp8 = c.w == MOE_FP8E4M3;
   if (!offsets) return MOE_EINVAL;
   if (c.T > 0 && (!X || !topk_idx || !row_map || !inv_map || !X_perm)) return MOE_EINVAL;
+  if (fp8 && c.d % 128 != 0) return MOE_EUNSUPPORTED;
+  if (fp8 && c.T > 0 && !X_perm_scale) return MOE_EINVAL;
+  if (!aligned(X_perm_scale, 4)) return MOE_EINVAL;
   if (!aligned(X, 16) || !aligned(X_perm, 16) || !aligned(topk_idx, 4) || !aligned(offsets, 4) ||
       !aligned(row_map, 4) || !aligned(inv_map, 4))
     return MOE_EINVAL;
@@ -210,9 +272,19 @@ extern "C" moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int3
   if (c.T > 0) {
     hipLaunchKernelGGL(dispatch_scatter, dim3(nb), dim3(TB), 0, st, topk_idx, c.T, c.E, c.k, w.cnt,
                        row_map, inv_map);
-    const int row_vec = c.d * act_bytes(c.act) / 16;
-    hipLaunchKernelGGL(dispatch_gather, dim3((c.T + 3) / 4), dim3(256), 0, st, (const u32x4*)X, c.T,
-                       row_vec, c.k, inv_map, (u32x4*)X_perm);
+    if (!fp8) {
+      const int row_vec = c.d * act_bytes(c.act) / 16;
+      hipLaunchKernelGGL(dispatch_gather, dim3((c.T + 3) / 4), dim3(256), 0, st, (const u32x4*)X,
+                         c.T, row_vec, c.k, inv_map, (u32x4*)X_perm);
+    } else if (c.act == MOE_BF16) {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_gather_fp8<bf16_t>), dim3((c.T + 3) / 4),
+                         dim3(256), 0, st, (const bf16_t*)X, c.T, c.d, c.k, inv_map,
+                         (fp8_t*)X_perm, X_perm_scale);
+    } else {
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_gather_fp8<float>), dim3((c.T + 3) / 4),
+                         dim3(256), 0, st, (const float*)X, c.T, c.d, c.k, inv_map,
+                         (fp8_t*)X_perm, X_perm_scale);
+    }
   }
   PROF_END("dispatch", st);
   MOE_LAUNCH_CHECK();

@@ -454,6 +454,283 @@ MOE_INST_BIG(EPI_PLAIN, false)
 MOE_INST_BIG(EPI_AB, true)
 #undef MOE_INST_BIG
 
+// ------------------------------------------------------------------ FP8
+// Per-block FP8 e4m3 quantisation (block amax, inv = 448 / amax, codes of
+// x * inv, scale = amax / 448; an all-zero block has scale 1 and codes 0).
+
+// 1 x 128 blocks: one wavefront per row, 16 lanes of 8 values per block.
+template <typename TA>
+__global__ __launch_bounds__(256) void fp8_quant_rows(const TA* __restrict__ X, int R, int C,
+                                                      fp8_t* __restrict__ Q,
+                                                      float* __restrict__ S) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= R) return;
+  const int nblk = C / 128;
+  for (int c0 = 0; c0 < C; c0 += 512) {
+    const int col = c0 + lane * 8;
+    const bool act = col < C;
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = act ? ActIO<TA>::ld(X + (size_t)r * C + col, i) : 0.0f;
+    float am = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) am = fmaxf(am, fabsf(v[i]));
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) am = fmaxf(am, __shfl_xor(am, o, 64));
+    const bool nz = am > 0.0f;
+    const float inv = nz ? 448.0f / am : 1.0f;
+    u32x2 q;
+    q[0] = q[1] = 0u;
+    if (nz) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) q[i >> 2] |= fp8_encode(v[i] * inv) << (8 * (i & 3));
+    }
+    if (act) {
+      *(u32x2*)(Q + (size_t)r * C + col) = q;
+      if ((lane & 15) == 0) S[(size_t)r * nblk + col / 128] = nz ? am / 448.0f : 1.0f;
+    }
+  }
+}
+
+// 128 x 128 blocks (ragged last row block): one 256-thread block per tile.
+template <typename TA>
+__global__ __launch_bounds__(256) void fp8_quant_tiles(const TA* __restrict__ X, int R, int C,
+                                                       fp8_t* __restrict__ Q,
+                                                       float* __restrict__ S) {
+  __shared__ float red[256];
+  const int tid = threadIdx.x;
+  const int cb = blockIdx.x, rb = blockIdx.y;
+  const int r0 = rb * 128, nr = min(128, R - r0);
+  const int col = cb * 128 + (tid & 15) * 8;
+  float am = 0.0f;
+  for (int rr = tid >> 4; rr < nr; rr += 16)
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      am = fmaxf(am, fabsf(ActIO<TA>::ld(X + (size_t)(r0 + rr) * C + col, i)));
+  red[tid] = am;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (tid < h) red[tid] = fmaxf(red[tid], red[tid + h]);
+    __syncthreads();
+  }
+  am = red[0];
+  const bool nz = am > 0.0f;
+  const float inv = nz ? 448.0f / am : 1.0f;
+  for (int rr = tid >> 4; rr < nr; rr += 16) {
+    u32x2 q;
+    q[0] = q[1] = 0u;
+    if (nz) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        q[i >> 2] |= fp8_encode(ActIO<TA>::ld(X + (size_t)(r0 + rr) * C + col, i) * inv)
+                     << (8 * (i & 3));
+    }
+    *(u32x2*)(Q + (size_t)(r0 + rr) * C + col) = q;
+  }
+  if (tid == 0) S[(size_t)rb * (C / 128) + cb] = nz ? am / 448.0f : 1.0f;
+}
+
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// FP8 grouped GEMM with per-block scales: A codes [N,K] with scales
+// [N, K/128] (1 x 128 blocks), B codes [E, Brows, K] with scales
+// [E, Brows/128, K/128] (128 x 128 blocks).  Same tiles, tile order, DMA
+// staging and LDS layout as gemm_bf16_big, with 64 FP8 values of K per
+// 64-byte stage row: one v_mfma_f32_32x32x64_f8f6f4 per 32x32 tile and
+// stage.  Each 128-wide K block is accumulated on its own (two stages) and
+// then promoted into the FP32 result: acc += partial * (sa * sb).
+// A lane holds one token row of each 32x32 tile, so sa is one value per
+// row tile and sb one value per column tile.
+template <int EPI>
+__global__ __launch_bounds__(256, 1) void gemm_fp8_big(
+    const fp8_t* __restrict__ A, const float* __restrict__ As, const fp8_t* __restrict__ B,
+    const float* __restrict__ Bs, bf16_t* __restrict__ C, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ tile_start, int E, int N, int K, int f, int Ncols, int n_tiles,
+    int grid_total) {
+  typedef __attribute__((address_space(3))) void lds_void;
+  constexpr bool PAIRED = EPI == EPI_SWIGLU;
+  __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
+  const int b = blockIdx.x;
+  const int per = grid_total >> 3;
+  const int Lt = (b & 7) * per + (b >> 3);
+  int e, row0, rows, nt;
+  if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = __builtin_amdgcn_readfirstlane(wv & 1);
+  const int n0 = nt * (PAIRED ? 64 : 128);
+  const int Brows_e = PAIRED ? 2 * f : Ncols;
+  const int nkb = K / 128;
+  const fp8_t* Be = B + (size_t)e * Brows_e * K;
+  const fp8_t* asrc[A_INS];
+  const fp8_t* bsrc[B_INS];
+#pragma unroll
+  for (int i = 0; i < A_INS; ++i) {
+    const int R = wv * (GBM / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    asrc[i] = A + (size_t)(row0 + min(R, rows - 1)) * K + c * 16;
+  }
+#pragma unroll
+  for (int i = 0; i < B_INS; ++i) {
+    const int R = wv * (GBN / 4) + i * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(R);
+    const int wrow = PAIRED ? (R < 64 ? n0 + R : f + n0 + (R - 64)) : n0 + R;
+    bsrc[i] = Be + (size_t)wrow * K + c * 16;
+  }
+  int aoff[4], asw[4], boff[2], bsw[2];
+  frag_offsets(wm, PAIRED ? wn * 32 : wn * 64, PAIRED ? 64 + wn * 32 : wn * 64 + 32, lane, aoff,
+               asw, boff, bsw);
+  // scale rows: token rows of the lane in each row tile, weight row blocks
+  // of the wavefront's two column tiles
+  const float* sa_row[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    sa_row[i] = As + (size_t)(row0 + min(wm * 128 + i * 32 + (lane & 31), rows - 1)) * nkb;
+  const int wr0 = PAIRED ? n0 + wn * 32 : n0 + wn * 64;
+  const int wr1 = PAIRED ? f + n0 + wn * 32 : n0 + wn * 64 + 32;
+  const float* sb_row0 = Bs + ((size_t)e * (Brows_e / 128) + wr0 / 128) * nkb;
+  const float* sb_row1 = Bs + ((size_t)e * (Brows_e / 128) + wr1 / 128) * nkb;
+
+  f32x16 acc[4][2], part[4][2];
+  zero_acc(acc);
+  zero_acc(part);
+  const int nk = K / 64;
+  constexpr int VMS = A_INS + B_INS;
+  const int fh = lane >> 5;
+#define F8_ISSUE(kstep)                                                                        \
+  {                                                                                            \
+    char* st_ = lds + ((kstep) % NSTAGE) * STAGE_BYTES;                                        \
+    const int k0_ = (kstep) * 64;                                                              \
+    _Pragma("unroll") for (int i = 0; i < A_INS; ++i) __builtin_amdgcn_global_load_lds(        \
+        asrc[i] + k0_, (lds_void*)(st_ + (wv * (GBM / 4) + i * 16) * 64), 16, 0, 0);           \
+    _Pragma("unroll") for (int i = 0; i < B_INS; ++i) __builtin_amdgcn_global_load_lds(        \
+        bsrc[i] + k0_, (lds_void*)(st_ + STAGE_A + (wv * (GBN / 4) + i * 16) * 64), 16, 0, 0); \
+  }
+#define F8_READ(AF, BF, stp)                                                                  \
+  {                                                                                           \
+    const char* st_ = lds + ((stp) % NSTAGE) * STAGE_BYTES;                                   \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                           \
+      const u32x4 lo_ = *(const u32x4*)(st_ + aoff[i] + ((fh ^ asw[i]) << 4));                \
+      const u32x4 hi_ = *(const u32x4*)(st_ + aoff[i] + (((2 + fh) ^ asw[i]) << 4));          \
+      AF[i] = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                     \
+                      (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};                    \
+    }                                                                                         \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                           \
+      const u32x4 lo_ = *(const u32x4*)(st_ + boff[j] + ((fh ^ bsw[j]) << 4));                \
+      const u32x4 hi_ = *(const u32x4*)(st_ + boff[j] + (((2 + fh) ^ bsw[j]) << 4));          \
+      BF[j] = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                     \
+                      (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};                    \
+    }                                                                                         \
+  }
+#define F8_MFMA(AF, BF)                                                                       \
+  _Pragma("unroll") for (int i = 0; i < 4; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) \
+      part[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(BF[j], AF[i], part[i][j], \
+                                                                    0, 0, 0, 0, 0, 0);
+  i32x8 a0[4], b0[2], a1[4], b1[2];
+  float sa[4], sb[2];
+  F8_ISSUE(0);
+  if (nk > 1) F8_ISSUE(1);
+  if (nk > 2) F8_ISSUE(2);
+  if (nk > 2) {
+    WAIT_VM_LGKM0(2 * VMS);
+  } else if (nk > 1) {
+    WAIT_VM_LGKM0(VMS);
+  } else {
+    WAIT_VM_LGKM0(0);
+  }
+  stage_barrier();
+  F8_READ(a0, b0, 0);
+  for (int kt = 0; kt < nk; kt += 2) {
+    // K block kt/2: stages kt (in a0/b0) and kt+1
+    const int kb = kt >> 1;
+    // stage kt+1 landed (stage kt+2 may still be in flight)
+    if (kt + 2 < nk) {
+      WAIT_VM_LGKM0(VMS);
+    } else {
+      WAIT_VM_LGKM0(0);
+    }
+    stage_barrier();
+    // the scale loads go out before the next DMA issue, so the next
+    // vmcnt(VMS) wait covers them without waiting for that issue
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sa[i] = sa_row[i][kb];
+    sb[0] = sb_row0[kb];
+    sb[1] = sb_row1[kb];
+    if (kt + 3 < nk) F8_ISSUE(kt + 3);
+    F8_READ(a1, b1, kt + 1);
+    F8_MFMA(a0, b0);
+    // stage kt+2 landed (kt+3 may be in flight); everyone is done with kt+1
+    if (kt + 2 < nk) {
+      if (kt + 3 < nk) {
+        WAIT_VM_LGKM0(VMS);
+      } else {
+        WAIT_VM_LGKM0(0);
+      }
+      stage_barrier();
+      if (kt + 4 < nk) F8_ISSUE(kt + 4);
+      F8_READ(a0, b0, kt + 2);
+    }
+    F8_MFMA(a1, b1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float sc = sa[i] * sb[j];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          acc[i][j][q] = fmaf(part[i][j][q], sc, acc[i][j][q]);
+          part[i][j][q] = 0.0f;
+        }
+      }
+  }
+#undef F8_ISSUE
+#undef F8_READ
+#undef F8_MFMA
+  WAIT_VM_LGKM0(0);
+  stage_barrier();
+
+  constexpr int CS = EPI == EPI_SWIGLU ? 64 : 128;
+  constexpr int CLD = CS + 8;
+  bf16_t* Cs = (bf16_t*)lds;
+  const int fr = lane & 31, cbase = (lane >> 5) * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rl = wm * 128 + i * 32 + fr;
+#pragma unroll
+    for (int j = 0; j < (EPI == EPI_SWIGLU ? 1 : 2); ++j) {
+      const int col0 = EPI == EPI_SWIGLU ? wn * 32 : wn * 64 + j * 32;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        bf16x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float x = acc[i][j][g * 4 + q];
+          if (EPI == EPI_SWIGLU) v[q] = (bf16_t)(silu(x) * acc[i][1][g * 4 + q]);
+          else v[q] = (bf16_t)x;
+        }
+        *(bf16x4*)(Cs + rl * CLD + col0 + g * 8 + cbase) = v;
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int CPR = CS / 8;
+  for (int c = tid; c < GBM * CPR; c += 256) {
+    const int rr = c / CPR, cc = (c - rr * CPR) * 8;
+    if (rr >= rows) continue;
+    *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + (size_t)nt * CS + cc) =
+        *(const u32x4*)(Cs + rr * CLD + cc);
+  }
+}
+
+#define MOE_INST_F8(EPI)                                                                     \
+  template __global__ void gemm_fp8_big<EPI>(                                                \
+      const fp8_t* __restrict__, const float* __restrict__, const fp8_t* __restrict__,       \
+      const float* __restrict__, bf16_t* __restrict__, const int32_t* __restrict__,          \
+      const int32_t* __restrict__, int, int, int, int, int, int, int);
+MOE_INST_F8(EPI_SWIGLU)
+MOE_INST_F8(EPI_PLAIN)
+#undef MOE_INST_F8
+
 // ------------------------------------------------------------- backward
 // Recompute-based backward of the expert FFN for the rows of each expert
 // (dY = w * dOut in slot order, supplied by the combine backward):
@@ -778,6 +1055,8 @@ struct FfnWs {
   int32_t* tile_start;
   int32_t* tile_start_big;
   void* h;
+  fp8_t* hq;   // FP8 path: codes of h [N, f]
+  float* hs;   // FP8 path: scales of h [N, f/128]
 };
 
 FfnWs carve_ffn(const moe_cfg& c, void* base, size_t* total) {
@@ -787,6 +1066,12 @@ FfnWs carve_ffn(const moe_cfg& c, void* base, size_t* total) {
   r.tile_start_big = wc.take<int32_t>((size_t)c.E + 1);
   const size_t N = (size_t)c.T * c.k;
   r.h = wc.take<char>(N * (size_t)c.d_ff * act_bytes(c.act));
+  r.hq = nullptr;
+  r.hs = nullptr;
+  if (c.w == MOE_FP8E4M3) {
+    r.hq = wc.take<fp8_t>(N * (size_t)c.d_ff);
+    r.hs = wc.take<float>(N * (size_t)(c.d_ff / 128));
+  }
   if (total) *total = align_up(wc.off, 256);
   return r;
 }
@@ -801,30 +1086,55 @@ size_t ffn_ws_bytes(const moe_cfg& c) {
 }
 
 extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
-                                     const int32_t* offsets, const void* W13,
-                                     const float* W13_scale, const void* W2,
+                                     const float* X_perm_scale, const int32_t* offsets,
+                                     const void* W13, const float* W13_scale, const void* W2,
                                      const float* W2_scale, void* Y, void* ws, size_t ws_bytes,
                                      void* stream) {
-  (void)W13_scale;
-  (void)W2_scale;
   moe_status stc = check_cfg_shape(cfg);
   if (stc != MOE_OK) return stc;
   const moe_cfg& c = *cfg;
   if (!offsets || !W13 || !W2) return MOE_EINVAL;
   if (c.T > 0 && (!X_perm || !Y)) return MOE_EINVAL;
   if (!aligned(X_perm, 16) || !aligned(W13, 16) || !aligned(W2, 16) || !aligned(Y, 16) ||
-      !aligned(offsets, 4))
+      !aligned(offsets, 4) || !aligned(X_perm_scale, 4) || !aligned(W13_scale, 4) ||
+      !aligned(W2_scale, 4))
     return MOE_EINVAL;
   const bool f32path = c.act == MOE_F32 && c.w == MOE_F32;
   const bool bf16path = c.act == MOE_BF16 && c.w == MOE_BF16;
-  if (!f32path && !bf16path) return MOE_EUNSUPPORTED;
+  const bool fp8path = c.act == MOE_BF16 && c.w == MOE_FP8E4M3;
+  if (!f32path && !bf16path && !fp8path) return MOE_EUNSUPPORTED;
   if (bf16path && (c.d_ff % 64 != 0 || c.d % 128 != 0)) return MOE_EUNSUPPORTED;
+  if (fp8path && (c.d_ff % 128 != 0 || c.d % 128 != 0)) return MOE_EUNSUPPORTED;
+  if (fp8path && (!W13_scale || !W2_scale || (c.T > 0 && !X_perm_scale))) return MOE_EINVAL;
   if (ws_bytes < ffn_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
   if (c.T == 0) return MOE_OK;
   hipStream_t st = (hipStream_t)stream;
   FfnWs w = carve_ffn(c, ws, nullptr);
   const int N = c.T * c.k;
-  if (bf16path) {
+  if (fp8path) {
+    hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
+    const int mt_big = (N + GBM - 1) / GBM + c.E;
+    const int nt1 = c.d_ff / 64;
+    const int G1 = (mt_big * nt1 + 7) / 8 * 8;
+    PROF_BEGIN("gemm1_swiglu", st);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_SWIGLU>), dim3(G1), dim3(256), 0, st,
+                       (const fp8_t*)X_perm, X_perm_scale, (const fp8_t*)W13, W13_scale,
+                       (bf16_t*)w.h, offsets, w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt1,
+                       G1);
+    PROF_END("gemm1_swiglu", st);
+    PROF_BEGIN("quant_h", st);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_rows<bf16_t>), dim3((N + 3) / 4), dim3(256), 0,
+                       st, (const bf16_t*)w.h, N, c.d_ff, w.hq, w.hs);
+    PROF_END("quant_h", st);
+    const int nt2 = c.d / 128;
+    const int G2 = (mt_big * nt2 + 7) / 8 * 8;
+    PROF_BEGIN("gemm2", st);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_PLAIN>), dim3(G2), dim3(256), 0, st,
+                       (const fp8_t*)w.hq, (const float*)w.hs, (const fp8_t*)W2, W2_scale,
+                       (bf16_t*)Y, offsets, w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt2,
+                       G2);
+    PROF_END("gemm2", st);
+  } else if (bf16path) {
     // 256-row tiles where the shape allows them, 128-row tiles otherwise
     const bool big1 = c.d_ff % 64 == 0 && c.d % GBK == 0;
     const bool big2 = c.d % 128 == 0 && c.d_ff % GBK == 0;
@@ -993,6 +1303,38 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
                        f, dW2, m2, n2, G2);
   }
   PROF_END("ffn_bwd", st);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_quantize_fp8(int rows, int cols, int block_rows, int src_dtype,
+                                       const void* src, uint8_t* codes, float* scales,
+                                       void* stream) {
+  if (rows < 0 || cols < 0 || cols % 128 != 0) return MOE_EINVAL;
+  if (block_rows != 1 && block_rows != 128) return MOE_EINVAL;
+  if (src_dtype != MOE_F32 && src_dtype != MOE_BF16) return MOE_EINVAL;
+  if ((int64_t)rows * cols >= ((int64_t)1 << 40)) return MOE_EUNSUPPORTED;
+  if (block_rows == 128 && (rows + 127) / 128 > 65535) return MOE_EUNSUPPORTED;
+  if (rows == 0 || cols == 0) return MOE_OK;
+  if (!src || !codes || !scales) return MOE_EINVAL;
+  if (!aligned(src, 16) || !aligned(codes, 8) || !aligned(scales, 4)) return MOE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (block_rows == 1) {
+    if (src_dtype == MOE_BF16)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_rows<bf16_t>), dim3((rows + 3) / 4), dim3(256),
+                         0, st, (const bf16_t*)src, rows, cols, codes, scales);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_rows<float>), dim3((rows + 3) / 4), dim3(256),
+                         0, st, (const float*)src, rows, cols, codes, scales);
+  } else {
+    const dim3 g(cols / 128, (rows + 127) / 128);
+    if (src_dtype == MOE_BF16)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_tiles<bf16_t>), g, dim3(256), 0, st,
+                         (const bf16_t*)src, rows, cols, codes, scales);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_tiles<float>), g, dim3(256), 0, st,
+                         (const float*)src, rows, cols, codes, scales);
+  }
   MOE_LAUNCH_CHECK();
   return MOE_OK;
 }

@@ -1001,7 +1001,7 @@ RouteWs carve_route(const moe_cfg& c, void* base, size_t* total) {
   r.sT = wc.take<float>(T * E);
   r.mT = wc.take<uint32_t>(T * E);
   r.state = wc.take<int32_t>(ST_LEN);
-  r.cnt = wc.take<int32_t>(((T + 127) / 128 + 1) * E);
+  r.cnt = wc.take<int32_t>(((T + 63) / 64 + 1) * E);  // one row per rank block
   r.part = wc.take<double>(2 * (nb > 0 ? nb : 1));
   r.held = wc.take<uint32_t>(T * W);
   r.tried = wc.take<uint32_t>(T * W);
@@ -1016,7 +1016,9 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
                                float* price, int32_t* idx, float* w, int32_t* load,
                                int max_iters, hipStream_t st) {
   const int T = c.T, E = c.E, k = c.k, C = c.capacity;
-  constexpr int TG = L <= 9 ? 4 : 2;
+  // one 64-token group per block: T/64 blocks keep every CU busy at
+  // T = 16384 (four groups per block left three quarters of the chip idle)
+  constexpr int TG = 1;
   const int nblk = (T + 64 * TG - 1) / (64 * TG);
   const int per = (E + RANK_WAVES - 1) / RANK_WAVES;
   for (int it = 0; it <= max_iters; ++it) {

@@ -69,31 +69,68 @@ def route(cfg, X, Wr, br, price=None, ws=None):
 
 
 def dispatch(cfg, X, idx, ws=None):
+    """Slot maps and permuted tokens; with FP8 experts X_perm holds e4m3
+    codes (uint8) and X_perm_scale the per-1x128-block scales."""
     T, d, E, k = cfg.T, cfg.d, cfg.E, cfg.k
     _need(X, "X", _DT[cfg.act], (T, d))
     _need(idx, "topk_idx", torch.int32, (T, k))
     dev = X.device
+    fp8 = cfg.w == L.MOE_FP8E4M3
     out = dict(offsets=torch.empty(E + 1, dtype=torch.int32, device=dev),
                row_map=torch.empty(T * k, dtype=torch.int32, device=dev),
                inv_map=torch.empty(T, k, dtype=torch.int32, device=dev),
-               X_perm=torch.empty(T * k, d, dtype=X.dtype, device=dev))
+               X_perm=torch.empty(T * k, d, dtype=torch.uint8 if fp8 else X.dtype, device=dev),
+               X_perm_scale=(torch.empty(T * k, d // 128, dtype=torch.float32, device=dev)
+                             if fp8 else None))
     ws = _WS.get(cfg, dev) if ws is None else ws
     L.moe_dispatch(cfg, _p(X), _p(idx), _p(out["offsets"]), _p(out["row_map"]),
-                   _p(out["inv_map"]), _p(out["X_perm"]), _p(ws), ws.numel(), _stream())
+                   _p(out["inv_map"]), _p(out["X_perm"]), _p(out["X_perm_scale"]), _p(ws),
+                   ws.numel(), _stream())
     return out
 
 
-def expert_ffn(cfg, X_perm, offsets, W13, W2, W13_scale=None, W2_scale=None, ws=None):
+def expert_ffn(cfg, X_perm, offsets, W13, W2, W13_scale=None, W2_scale=None, ws=None,
+               X_perm_scale=None):
     N, d, E, f = cfg.T * cfg.k, cfg.d, cfg.E, cfg.d_ff
-    _need(X_perm, "X_perm", _DT[cfg.act], (N, d))
+    fp8 = cfg.w == L.MOE_FP8E4M3
+    _need(X_perm, "X_perm", torch.uint8 if fp8 else _DT[cfg.act], (N, d))
     _need(offsets, "offsets", torch.int32, (E + 1,))
     _need(W13, "W13", _DT[cfg.w], (E, 2 * f, d))
     _need(W2, "W2", _DT[cfg.w], (E, d, f))
-    Y = torch.empty(N, d, dtype=X_perm.dtype, device=X_perm.device)
+    if fp8:
+        _need(X_perm_scale, "X_perm_scale", torch.float32, (N, d // 128))
+        _need(W13_scale, "W13_scale", torch.float32, (E, 2 * f // 128, d // 128))
+        _need(W2_scale, "W2_scale", torch.float32, (E, d // 128, f // 128))
+    Y = torch.empty(N, d, dtype=_DT[cfg.act], device=X_perm.device)
     ws = _WS.get(cfg, X_perm.device) if ws is None else ws
-    L.moe_expert_ffn(cfg, _p(X_perm), _p(offsets), _p(W13), _p(W13_scale), _p(W2), _p(W2_scale),
-                     _p(Y), _p(ws), ws.numel(), _stream())
+    L.moe_expert_ffn(cfg, _p(X_perm), _p(X_perm_scale), _p(offsets), _p(W13), _p(W13_scale),
+                     _p(W2), _p(W2_scale), _p(Y), _p(ws), ws.numel(), _stream())
     return Y
+
+
+def quantize_fp8(x, block_rows):
+    """(codes uint8, scales f32) of a [rows, cols] f32/bf16 matrix (or a
+    stack of expert matrices, quantised as rows = E * R) in block_rows x 128
+    blocks."""
+    if x.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("quantize_fp8 takes float32 or bfloat16")
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("quantize_fp8 takes a contiguous device tensor")
+    cols = x.shape[-1]
+    rows = x.numel() // max(cols, 1)
+    lead = tuple(x.shape[:-1])
+    codes = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    if block_rows == 1:
+        sshape = lead + (cols // 128,)
+    else:
+        R = x.shape[-2]
+        if x.dim() > 2 and R % block_rows != 0:
+            raise ValueError("expert matrices need a multiple of 128 rows")
+        sshape = tuple(x.shape[:-2]) + ((R + block_rows - 1) // block_rows, cols // 128)
+    scales = torch.empty(sshape, dtype=torch.float32, device=x.device)
+    L.moe_quantize_fp8(rows, cols, block_rows, L.MOE_BF16 if x.dtype == torch.bfloat16 else L.MOE_F32,
+                       _p(x), _p(codes), _p(scales), _stream())
+    return codes, scales
 
 
 def combine(cfg, Y, inv_map, w):
@@ -110,7 +147,8 @@ def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None):
     """The whole layer forward; returns every intermediate."""
     r = route(cfg, X, Wr, br, price)
     dsp = dispatch(cfg, X, r["idx"])
-    Y = expert_ffn(cfg, dsp["X_perm"], dsp["offsets"], W13, W2, W13_scale, W2_scale)
+    Y = expert_ffn(cfg, dsp["X_perm"], dsp["offsets"], W13, W2, W13_scale, W2_scale,
+                   X_perm_scale=dsp["X_perm_scale"])
     out = combine(cfg, Y, dsp["inv_map"], r["w"])
     r.update(dsp)
     r["Y"] = Y

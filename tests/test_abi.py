@@ -84,12 +84,26 @@ def test_entry_points_reject_bad_arguments_on_the_host():
         L.moe_route(bad, fake, fake, fake, fake, fake, fake, fake, fake, fake, fake, 1 << 30, None)
     assert e.value.status == L.MOE_EINVAL
     with pytest.raises(L.MoEError) as e:
-        L.moe_dispatch(cfg, fake, fake, fake, fake, fake, fake, fake, 0, None)
+        L.moe_dispatch(cfg, fake, fake, fake, fake, fake, fake, None, fake, 0, None)
     assert e.value.status == L.MOE_EWORKSPACE
     with pytest.raises(L.MoEError) as e:
-        L.moe_expert_ffn(_cfg(act=L.MOE_F32, w=L.MOE_BF16), fake, fake, fake, None, fake, None, fake,
-                         fake, 1 << 30, None)
+        L.moe_expert_ffn(_cfg(act=L.MOE_F32, w=L.MOE_BF16), fake, None, fake, fake, None, fake,
+                         None, fake, fake, 1 << 30, None)
     assert e.value.status == L.MOE_EUNSUPPORTED
+    with pytest.raises(L.MoEError) as e:  # FP8 experts need the weight scales
+        L.moe_expert_ffn(_cfg(act=L.MOE_BF16, w=L.MOE_FP8E4M3), fake, fake, fake, fake, None, fake,
+                         None, fake, fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:  # FP8 dispatch needs the scale output
+        L.moe_dispatch(_cfg(w=L.MOE_FP8E4M3), fake, fake, fake, fake, fake, fake, None, fake,
+                       1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:
+        L.moe_quantize_fp8(4, 100, 1, L.MOE_BF16, fake, fake, fake, None)  # cols % 128
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:
+        L.moe_quantize_fp8(4, 128, 2, L.MOE_BF16, fake, fake, fake, None)  # block rows
+    assert e.value.status == L.MOE_EINVAL
     with pytest.raises(L.MoEError) as e:
         L.moe_combine(cfg, None, fake, fake, fake, None)
     assert e.value.status == L.MOE_EINVAL

@@ -1,0 +1,142 @@
+"""GPU parity of the FP8 (OCP e4m3, per-block scales) expert path against
+the CPU oracle, through the C ABI.
+
+Bars:
+  quantisation (tokens 1 x 128 in the dispatch, weights 128 x 128, h):
+      codes and scales bit-identical to the oracle's quantiser run on the
+      same FP32 / BF16 values;
+  expert outputs Y and layer output: rel. Frobenius <= 1e-2 against the
+      FP8-emulating FP64 oracle (its h is rounded to BF16 and re-quantised
+      like the GPU's; a BF16 rounding of h on either side can move an FP8
+      code by one step), and <= 8e-2 against the FP64 layer on the same
+      BF16 tokens and unquantised weights.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ffn, fp8
+from oracle import routing as R
+from paper_2606_17065_amd import _lib as L
+from paper_2606_17065_amd import layer, synth
+
+from _helpers import cfg_for, device_inputs, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+def _bf16(x):
+    return torch.from_numpy(np.asarray(x, F32)).to(torch.bfloat16)
+
+
+def _mixed_rows(R_, C, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.standard_normal((R_, C)) * np.exp(rng.uniform(-6, 6, (R_, 1)))
+    x[3, :128] = 0.0  # an all-zero block
+    x[4, 128:256] = -0.0
+    x[5, :] *= 1e-3
+    x[6, 5] = 1e4
+    return x.astype(F32)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_quantize_rows_bit_exact(dtype):
+    x = _mixed_rows(333, 384, 1)
+    xd = torch.from_numpy(x).to(dtype).cuda()
+    q, s = layer.quantize_fp8(xd, 1)
+    torch.cuda.synchronize()
+    xv = xd.float().cpu().numpy()
+    rq, rs = fp8.quantize_blocks(xv, 1, 128)
+    np.testing.assert_array_equal(q.cpu().numpy(), rq)
+    np.testing.assert_array_equal(s.cpu().numpy().view(np.uint32), rs.view(np.uint32))
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_quantize_expert_tiles_bit_exact(dtype):
+    rng = np.random.Generator(np.random.PCG64(2))
+    W = (0.02 * rng.standard_normal((3, 384, 256))).astype(F32)
+    W[1, :128, 128:] = 0.0
+    W[2] *= 50.0
+    Wd = torch.from_numpy(W).to(dtype).cuda()
+    q, s = layer.quantize_fp8(Wd, 128)
+    torch.cuda.synchronize()
+    rq, rs = fp8.quantize_experts(Wd.float().cpu().numpy())
+    np.testing.assert_array_equal(q.cpu().numpy(), rq)
+    np.testing.assert_array_equal(s.cpu().numpy().view(np.uint32), rs.view(np.uint32))
+
+
+def test_quantize_ragged_row_tiles():
+    rng = np.random.Generator(np.random.PCG64(3))
+    x = rng.standard_normal((300, 256)).astype(F32)
+    q, s = layer.quantize_fp8(torch.from_numpy(x).cuda(), 128)
+    torch.cuda.synchronize()
+    rq, rs = fp8.quantize_blocks(x, 128, 128)
+    assert tuple(s.shape) == (3, 2)
+    np.testing.assert_array_equal(q.cpu().numpy(), rq)
+    np.testing.assert_array_equal(s.cpu().numpy(), rs)
+
+
+FP8_SMALL = synth.MoEShape("fp8-small", T=700, d=256, E=8, k=2, f=256, zipf=1.2, act="bf16",
+                           w="fp8")
+FP8_WIDE = synth.MoEShape("fp8-wide", T=1300, d=512, E=8, k=2, f=384, zipf=1.2, act="bf16",
+                          w="fp8")
+
+
+def _fp8_case(shape, config):
+    inp = synth.make_inputs(shape, config)
+    d, h = device_inputs(dataclass_bf16(shape), inp)
+    cfg = cfg_for(shape)
+    W13d = torch.from_numpy(inp["W13"]).to(torch.bfloat16).cuda()
+    W2d = torch.from_numpy(inp["W2"]).to(torch.bfloat16).cuda()
+    q13, s13 = layer.quantize_fp8(W13d, 128)
+    q2, s2 = layer.quantize_fp8(W2d, 128)
+    return cfg, inp, d, h, W13d, W2d, q13, s13, q2, s2
+
+
+def dataclass_bf16(shape):
+    import dataclasses
+    return dataclasses.replace(shape, w="bf16")
+
+
+@pytest.mark.parametrize("shape,config", [(FP8_SMALL, 31), (FP8_WIDE, 32)])
+def test_fp8_layer_matches_emulating_oracle(shape, config):
+    cfg, inp, d, h, W13d, W2d, q13, s13, q2, s2 = _fp8_case(shape, config)
+    r = layer.forward(cfg, d["X"], d["Wr"], d["br"], q13, q2, W13_scale=s13, W2_scale=s2)
+    torch.cuda.synchronize()
+    assert int(r["info"][L.INFO_STATUS]) == 0
+    sel = r["idx"].cpu().numpy()
+    offsets, row_map, inv_map = ffn.dispatch_maps(sel, shape.E)
+    np.testing.assert_array_equal(r["offsets"].cpu().numpy(), offsets)
+    np.testing.assert_array_equal(r["row_map"].cpu().numpy(), row_map)
+    # the oracle quantises the same BF16 weights itself
+    W13v = W13d.float().cpu().numpy()
+    W2v = W2d.float().cpu().numpy()
+    oq13, os13 = fp8.quantize_experts(W13v)
+    oq2, os2 = fp8.quantize_experts(W2v)
+    np.testing.assert_array_equal(q13.cpu().numpy(), oq13)
+    np.testing.assert_array_equal(s2.cpu().numpy(), os2)
+    ref = fp8.slots_forward_fp8(h["X"], row_map, offsets, oq13, os13, oq2, os2)
+    # token codes and scales in slot order: bit-exact
+    np.testing.assert_array_equal(r["X_perm"].cpu().numpy(), ref["Xq"][row_map])
+    np.testing.assert_array_equal(r["X_perm_scale"].cpu().numpy(), ref["Xs"][row_map])
+    Y = r["Y"].float().cpu().numpy()
+    assert rel_fro(Y, ref["Y"]) <= 1e-2
+    w = r["w"].cpu().numpy()
+    out_ref = ffn.combine(ref["Y"], inv_map, w)
+    assert rel_fro(r["out"].float().cpu().numpy(), out_ref) <= 1e-2
+    # against the unquantised FP64 layer on the same BF16 tokens and weights
+    _, _, Y64 = ffn.slots_forward(h["X"], row_map, offsets, W13v, W2v)
+    assert rel_fro(Y, Y64) <= 8e-2
+
+
+def test_fp8_ffn_rejects_unaligned_widths():
+    shape = synth.MoEShape("fp8-bad", T=64, d=192, E=4, k=2, f=256, zipf=1.0, act="bf16", w="fp8")
+    cfg = cfg_for(shape)
+    x = torch.zeros(128, 192, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.MoEError) as e:
+        L.moe_expert_ffn(cfg, x.data_ptr(), x.data_ptr(), x.data_ptr(), x.data_ptr(),
+                         x.data_ptr(), x.data_ptr(), x.data_ptr(), x.data_ptr(), x.data_ptr(),
+                         1 << 30, 0)
+    assert e.value.status == L.MOE_EUNSUPPORTED
