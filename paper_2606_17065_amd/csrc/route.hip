@@ -234,13 +234,14 @@ __global__ __launch_bounds__(SIG_BLOCK) void score_partials(const float* __restr
   const int t = blockIdx.x * SIG_BLOCK + tid;
   double r1 = 0.0, r2 = 0.0;
   if (t < T) {
-    // loads batched 16 at a time; the additions keep expert order
-    for (int e0 = 0; e0 < E; e0 += 16) {
-      float xv[16];
+    // loads batched 64 at a time (one latency for E <= 64); the additions
+    // keep expert order
+    for (int e0 = 0; e0 < E; e0 += 64) {
+      float xv[64];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) xv[i] = e0 + i < E ? sT[(size_t)(e0 + i) * T + t] : 0.0f;
+      for (int i = 0; i < 64; ++i) xv[i] = e0 + i < E ? sT[(size_t)(e0 + i) * T + t] : 0.0f;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
+      for (int i = 0; i < 64; ++i) {
         if (e0 + i < E) {
           const double v = (double)xv[i];
           r1 = r1 + v;
@@ -363,12 +364,16 @@ __device__ __forceinline__ void insert_kv(uint32_t (&K)[L], int (&X)[L], uint32_
   }
 }
 
+// Token group of sub-group tg: gbase + tg * gstride (64 tokens each);
+// the block's per-expert counts go to row crow of cnt.  With a state
+// pointer the pass is skipped once the price loop is done.
 template <int L, int NV, int TG>
-__global__ __launch_bounds__(64 * RANK_WAVES * TG) void acp_rank(
-    const float* __restrict__ sT, const float* __restrict__ price, int T, int E, int k,
-    const int32_t* __restrict__ state, uint32_t* __restrict__ mT, int32_t* __restrict__ idx,
-    int32_t* __restrict__ cnt) {
-  if (state[ST_DONE]) return;
+__device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
+                                          const float* __restrict__ price, int T, int E, int k,
+                                          const int32_t* __restrict__ state,
+                                          uint32_t* __restrict__ mT, int32_t* __restrict__ idx,
+                                          int32_t* __restrict__ cnt, int gbase, int gstride,
+                                          int crow) {
   __shared__ int hist[MOE_MAX_E];
   __shared__ float ps[MOE_MAX_E];
   __shared__ uint32_t partk[TG][RANK_WAVES][L][64];
@@ -379,19 +384,27 @@ __global__ __launch_bounds__(64 * RANK_WAVES * TG) void acp_rank(
   constexpr int NT = 64 * RANK_WAVES * TG;
   const int tid = threadIdx.x, lane = tid & 63, wv = (tid >> 6) & (RANK_WAVES - 1);
   const int tg = tid / (64 * RANK_WAVES);
-  for (int e = tid; e < E; e += NT) {
-    hist[e] = 0;
-    ps[e] = price[e];
-  }
-  __syncthreads();
-  const int t = (blockIdx.x * TG + tg) * 64 + lane;
+  const int t = (gbase + tg * gstride) * 64 + lane;
   const bool valid = t < T;
   const int tl = valid ? t : T - 1;  // out-of-range lanes read a valid row, write nothing
   const int per = (E + RANK_WAVES - 1) / RANK_WAVES;
   const int e_lo = wv * per;
   const int ne = max(0, min(E, e_lo + per) - e_lo);
   const bool cached = ne <= NV;
+  // the logits, the prices and the done flag are independent loads: issue
+  // them together so their latencies overlap
   float sv[NV];
+  if (cached) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sv[i] = sT[(size_t)(e_lo + min(i, max(ne - 1, 0))) * T + tl];
+  }
+  const int done = state ? state[ST_DONE] : 0;
+  if (done) return;  // uniform: every thread read the same flag
+  for (int e = tid; e < E; e += NT) {
+    hist[e] = 0;
+    ps[e] = price[e];
+  }
+  __syncthreads();
   uint32_t K[L];
   int X[L];
 #pragma unroll
@@ -400,8 +413,6 @@ __global__ __launch_bounds__(64 * RANK_WAVES * TG) void acp_rank(
     X[j] = 0;
   }
   if (cached) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) sv[i] = sT[(size_t)(e_lo + min(i, max(ne - 1, 0))) * T + tl];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const uint32_t key = i < ne ? f32_key(sv[i] - ps[e_lo + min(i, max(ne - 1, 0))]) : 0u;
@@ -488,7 +499,15 @@ __global__ __launch_bounds__(64 * RANK_WAVES * TG) void acp_rank(
       }
     }
   }
-  for (int e = tid; e < E; e += NT) cnt[(size_t)blockIdx.x * E + e] = hist[e];
+  for (int e = tid; e < E; e += NT) cnt[(size_t)crow * E + e] = hist[e];
+}
+
+template <int L, int NV, int TG>
+__global__ __launch_bounds__(64 * RANK_WAVES * TG) void acp_rank(
+    const float* __restrict__ sT, const float* __restrict__ price, int T, int E, int k,
+    const int32_t* __restrict__ state, uint32_t* __restrict__ mT, int32_t* __restrict__ idx,
+    int32_t* __restrict__ cnt) {
+  rank_pass<L, NV, TG>(sT, price, T, E, k, state, mT, idx, cnt, blockIdx.x * TG, 1, blockIdx.x);
 }
 
 // Gate weights of the final routing: softmax of the raw logits over each
@@ -658,66 +677,17 @@ __device__ void block_pick_digit(const uint32_t* hist, int rr, int* red, int* pi
   __syncthreads();
 }
 
-__global__ __launch_bounds__(SEL_THREADS) void acp_select(
-    const uint32_t* __restrict__ mT, float* __restrict__ price, int T, int E, int C, int it,
-    int max_iters, int nblk, const int32_t* __restrict__ cnt, int32_t* __restrict__ state,
-    int32_t* __restrict__ load_out) {
-  if (state[ST_DONE]) return;
-  __shared__ SelScratch sc;
-  __shared__ int red[32];
-  __shared__ int ld[MOE_MAX_E];
+// The price update of one overloaded expert e (all SEL_THREADS threads):
+// q = (C+1)-th largest margin key of the column by a three-pass 11/11/10-bit
+// radix select over the keys at or above a floor just below the current
+// price (restarting over all keys if fewer than C+1 lie above it), then
+// p_e = max(p_e, nextafter(q, +inf) + eps).  kk holds the column when
+// cached (T <= SEL_THREADS * SEL_KPT).
+__device__ __forceinline__ void select_update(const uint32_t* __restrict__ col,
+                                              uint32_t (&kk)[SEL_KPT], bool cached, int T,
+                                              int C, int e, float* __restrict__ price,
+                                              float eps, SelScratch& sc, int* red) {
   const int tid = threadIdx.x;
-  // loads of this iteration: column sums of the per-block count matrix
-  for (int e = tid; e < E; e += SEL_THREADS) ld[e] = 0;
-  __syncthreads();
-  {
-    const int lanes_per_e = max(1, SEL_THREADS / E);
-    for (int e0 = 0; e0 < E; e0 += SEL_THREADS) {
-      const int e = e0 + tid % min(E, SEL_THREADS);
-      const int r0 = tid / min(E, SEL_THREADS);
-      if (e < E && r0 < lanes_per_e) {
-        int sum = 0;
-        for (int r = r0; r < nblk; r += lanes_per_e) sum += cnt[(size_t)r * E + e];
-        atomicAdd(&ld[e], sum);
-      }
-    }
-  }
-  __syncthreads();
-  int over = 0, excess = 0;
-  for (int e = tid; e < E; e += SEL_THREADS) {
-    int x = ld[e] - C;
-    if (x > 0) {
-      over = 1;
-      excess += x;
-    }
-  }
-  const int n_over = block_sum(over, red);
-  const int e = blockIdx.x;
-  if (n_over == 0 || it >= max_iters) {
-    if (e == 0) {
-      const int tot_excess = block_sum(excess, red);
-      for (int i = tid; i < E; i += SEL_THREADS) load_out[i] = ld[i];
-      if (tid == 0) {
-        state[ST_ITERS] = it;
-        state[ST_CONVERGED] = n_over == 0;
-        state[ST_OVERFLOW] = tot_excess;
-        state[ST_NEED_REPAIR] = n_over != 0;
-        state[ST_DONE] = 1;
-      }
-    }
-    return;
-  }
-  if (ld[e] <= C) return;
-  const uint32_t* col = mT + (size_t)e * T;
-  const bool cached = T <= SEL_THREADS * SEL_KPT;
-  uint32_t kk[SEL_KPT];
-  if (cached) {
-#pragma unroll
-    for (int i = 0; i < SEL_KPT; ++i) {
-      const int j = i * SEL_THREADS + tid;
-      kk[i] = j < T ? col[j] : 0u;
-    }
-  }
   const uint32_t pkey = f32_key(price[e]);
   uint32_t floor_key = pkey > 4096u ? pkey - 4096u : 0u;
   uint32_t prefix = 0, mask = 0;
@@ -760,12 +730,86 @@ __global__ __launch_bounds__(SEL_THREADS) void acp_select(
     mask |= dm << sh;
   }
   if (tid == 0) {
-    const float eps = __int_as_float(state[ST_EPS]);
     const float qf = key_f32(prefix);
     const float cand = nextafterf(qf, INFINITY) + eps;
     const float old = price[e];
     price[e] = cand > old ? cand : old;
   }
+}
+
+__global__ __launch_bounds__(SEL_THREADS) void acp_select(
+    const uint32_t* __restrict__ mT, float* __restrict__ price, int T, int E, int C, int it,
+    int max_iters, int nblk, const int32_t* __restrict__ cnt, int32_t* __restrict__ state,
+    int32_t* __restrict__ load_out) {
+  __shared__ SelScratch sc;
+  __shared__ int red[32];
+  __shared__ int ld[MOE_MAX_E];
+  const int tid = threadIdx.x;
+  const int done = state[ST_DONE];
+  for (int e = tid; e < E; e += SEL_THREADS) ld[e] = 0;
+  if (done) return;  // uniform
+  // this block's margin column, requested before the load count is known
+  // (the latencies overlap; blocks of experts within capacity discard it)
+  const uint32_t* col = mT + (size_t)blockIdx.x * T;
+  const bool cached = T <= SEL_THREADS * SEL_KPT;
+  uint32_t kk[SEL_KPT];
+  if (cached) {
+#pragma unroll
+    for (int i = 0; i < SEL_KPT; ++i) {
+      const int j = i * SEL_THREADS + tid;
+      kk[i] = j < T ? col[j] : 0u;
+    }
+  }
+  __syncthreads();
+  // loads of this iteration: column sums of the per-block count matrix,
+  // eight independent loads in flight per thread
+  {
+    const int lanes_per_e = max(1, SEL_THREADS / E);
+    for (int e0 = 0; e0 < E; e0 += SEL_THREADS) {
+      const int e = e0 + tid % min(E, SEL_THREADS);
+      const int r0 = tid / min(E, SEL_THREADS);
+      if (e < E && r0 < lanes_per_e) {
+        int sum = 0;
+        int r = r0;
+        for (; r + 7 * lanes_per_e < nblk; r += 8 * lanes_per_e) {
+          int v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = cnt[(size_t)(r + u * lanes_per_e) * E + e];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sum += v[u];
+        }
+        for (; r < nblk; r += lanes_per_e) sum += cnt[(size_t)r * E + e];
+        atomicAdd(&ld[e], sum);
+      }
+    }
+  }
+  __syncthreads();
+  int over = 0, excess = 0;
+  for (int e = tid; e < E; e += SEL_THREADS) {
+    int x = ld[e] - C;
+    if (x > 0) {
+      over = 1;
+      excess += x;
+    }
+  }
+  const int n_over = block_sum(over, red);
+  const int e = blockIdx.x;
+  if (n_over == 0 || it >= max_iters) {
+    if (e == 0) {
+      const int tot_excess = block_sum(excess, red);
+      for (int i = tid; i < E; i += SEL_THREADS) load_out[i] = ld[i];
+      if (tid == 0) {
+        state[ST_ITERS] = it;
+        state[ST_CONVERGED] = n_over == 0;
+        state[ST_OVERFLOW] = tot_excess;
+        state[ST_NEED_REPAIR] = n_over != 0;
+        state[ST_DONE] = 1;
+      }
+    }
+    return;
+  }
+  if (ld[e] <= C) return;
+  select_update(col, kk, cached, T, C, e, price, __int_as_float(state[ST_EPS]), sc, red);
 }
 
 // ----------------------------------------------------- capacity repair
@@ -1021,6 +1065,8 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
   constexpr int TG = 1;
   const int nblk = (T + 64 * TG - 1) / (64 * TG);
   const int per = (E + RANK_WAVES - 1) / RANK_WAVES;
+  // one ranking and one update kernel per iteration, each exiting at once
+  // after the loop has stopped
   for (int it = 0; it <= max_iters; ++it) {
     const dim3 rb(64 * RANK_WAVES * TG);
     if (per <= 4)
