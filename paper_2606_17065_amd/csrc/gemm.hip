@@ -454,6 +454,169 @@ MOE_INST_BIG(EPI_PLAIN, false)
 MOE_INST_BIG(EPI_AB, true)
 #undef MOE_INST_BIG
 
+// ------------------------------------------------- BF16, 256 x 256 tiles
+// Forward expert GEMMs: block tile 256 tokens x 256 weight rows, K = 64 per
+// stage (128-byte LDS rows, one full cache line per row and stage), two
+// stages of 64 KB, one block per CU with 8 wavefronts (2 rows x 4 columns,
+// each 128 x 64 as 4 x 2 tiles of v_mfma_f32_32x32x16_bf16), so two
+// wavefronts per SIMD as in the 256 x 128 kernel but half the L2 bytes per
+// flop and one barrier per 32 MFMAs.  Chunk swizzle over the eight 16-byte
+// chunks of a row: physical = logical ^ (row & 7).  SwiGLU: weight rows
+// 0..127 are W1 rows n0.., 128..255 the matching W3 rows; wavefront wn owns
+// outputs wn*32 .. wn*32+31 (gate tile and up tile).
+constexpr int XBN = 256, XBK = 64;
+constexpr int XSTAGE_A = GBM * 128, XSTAGE_B = XBN * 128;
+constexpr int XSTAGE = XSTAGE_A + XSTAGE_B;
+constexpr int XEPI = GBM * (256 + 8) * 2;
+constexpr int XLDS = 2 * XSTAGE > XEPI ? 2 * XSTAGE : XEPI;
+constexpr int XW = 8;  // wavefronts per block: 2 (rows) x 4 (columns), each 128 x 64
+constexpr int XA_INS = GBM * 128 / 1024 / XW, XB_INS = XBN * 128 / 1024 / XW;
+
+template <int EPI>
+__global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
+    const bf16_t* __restrict__ A, const bf16_t* __restrict__ B, bf16_t* __restrict__ C,
+    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start, int E, int N,
+    int K, int f, int Ncols, int n_tiles, int grid_total) {
+  typedef __attribute__((address_space(3))) void lds_void;
+  constexpr bool PAIRED = EPI == EPI_SWIGLU;
+  __shared__ __attribute__((aligned(1024))) char lds[XLDS];
+  const int b = blockIdx.x;
+  const int per = grid_total >> 3;
+  const int Lt = (b & 7) * per + (b >> 3);
+  int e, row0, rows, nt;
+  if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 2, wn = wv & 3;
+  const int n0 = nt * (PAIRED ? 128 : 256);
+  const size_t Brows_e = PAIRED ? (size_t)2 * f : (size_t)Ncols;
+  const bf16_t* Be = B + (size_t)e * Brows_e * K;
+  const bf16_t* asrc[XA_INS];
+  const bf16_t* bsrc[XB_INS];
+#pragma unroll
+  for (int i = 0; i < XA_INS; ++i) {
+    const int R = wv * (GBM / XW) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ (R & 7);
+    asrc[i] = A + (size_t)(row0 + min(R, rows - 1)) * K + c * 8;
+  }
+#pragma unroll
+  for (int i = 0; i < XB_INS; ++i) {
+    const int R = wv * (XBN / XW) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ (R & 7);
+    const int wrow = PAIRED ? (R < 128 ? n0 + R : f + n0 + (R - 128)) : n0 + R;
+    bsrc[i] = Be + (size_t)wrow * K + c * 8;
+  }
+  const int fr = lane & 31, fh = lane >> 5;
+  int aoff[4], asw[4], boff[2], bsw[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int R = wm * 128 + i * 32 + fr;
+    aoff[i] = R * 128;
+    asw[i] = R & 7;
+  }
+  // SwiGLU: wavefront wn owns 32 outputs: gate rows wn*32.., up rows 128+wn*32..
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int R = (PAIRED ? (j == 0 ? wn * 32 : 128 + wn * 32) : wn * 64 + j * 32) + fr;
+    boff[j] = XSTAGE_A + R * 128;
+    bsw[j] = R & 7;
+  }
+  f32x16 acc[4][2];
+  zero_acc(acc);
+  const int nk = K / XBK;
+#define X_ISSUE(kstep)                                                                         \
+  {                                                                                            \
+    char* st_ = lds + ((kstep) & 1) * XSTAGE;                                                  \
+    const int k0_ = (kstep) * XBK;                                                             \
+    _Pragma("unroll") for (int i = 0; i < XA_INS; ++i) __builtin_amdgcn_global_load_lds(       \
+        asrc[i] + k0_, (lds_void*)(st_ + (wv * (GBM / XW) + i * 8) * 128), 16, 0, 0);          \
+    _Pragma("unroll") for (int i = 0; i < XB_INS; ++i) __builtin_amdgcn_global_load_lds(       \
+        bsrc[i] + k0_, (lds_void*)(st_ + XSTAGE_A + (wv * (XBN / XW) + i * 8) * 128), 16, 0,   \
+        0);                                                                                    \
+  }
+#define X_READ(AF, BF, stp, ks)                                                          \
+  {                                                                                      \
+    const char* st_ = lds + ((stp) & 1) * XSTAGE;                                        \
+    const int c_ = (ks) * 2 + fh;                                                        \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) AF[i] =                                \
+        *(const bf16x8*)(st_ + aoff[i] + ((c_ ^ asw[i]) << 4));                          \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) BF[j] =                                \
+        *(const bf16x8*)(st_ + boff[j] + ((c_ ^ bsw[j]) << 4));                          \
+  }
+#define X_MFMA(AF, BF)                                                                   \
+  _Pragma("unroll") for (int i = 0; i < 4; ++i) _Pragma("unroll") for (int j = 0; j < 2; \
+                                                                       ++j) acc[i][j] =  \
+      __builtin_amdgcn_mfma_f32_32x32x16_bf16(BF[j], AF[i], acc[i][j], 0, 0, 0);
+  bf16x8 a0[4], b0[2], a1[4], b1[2];
+  X_ISSUE(0);
+  if (nk > 1) {
+    X_ISSUE(1);
+    WAIT_VM_LGKM0(XA_INS + XB_INS);
+  } else {
+    WAIT_VM_LGKM0(0);
+  }
+  stage_barrier();
+  X_READ(a0, b0, 0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    X_READ(a1, b1, kt, 1);
+    X_MFMA(a0, b0);
+    X_READ(a0, b0, kt, 2);
+    X_MFMA(a1, b1);
+    X_READ(a1, b1, kt, 3);
+    X_MFMA(a0, b0);
+    WAIT_VM_LGKM0(0);
+    stage_barrier();
+    if (kt + 2 < nk) X_ISSUE(kt + 2);
+    if (kt + 1 < nk) X_READ(a0, b0, kt + 1, 0);
+    X_MFMA(a1, b1);
+  }
+#undef X_ISSUE
+#undef X_READ
+#undef X_MFMA
+  WAIT_VM_LGKM0(0);
+  stage_barrier();
+
+  constexpr int CS = PAIRED ? 128 : 256;
+  constexpr int CLD = CS + 8;
+  bf16_t* Cs = (bf16_t*)lds;
+  const int cbase = fh * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rl = wm * 128 + i * 32 + fr;
+#pragma unroll
+    for (int j = 0; j < (PAIRED ? 1 : 2); ++j) {
+      const int col0 = PAIRED ? wn * 32 : wn * 64 + j * 32;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        bf16x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float x = acc[i][j][g * 4 + q];
+          if (PAIRED) v[q] = (bf16_t)(silu(x) * acc[i][1][g * 4 + q]);
+          else v[q] = (bf16_t)x;
+        }
+        *(bf16x4*)(Cs + rl * CLD + col0 + g * 8 + cbase) = v;
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int CPR = CS / 8;
+  for (int c = tid; c < GBM * CPR; c += 64 * XW) {
+    const int rr = c / CPR, cc = (c - rr * CPR) * 8;
+    if (rr >= rows) continue;
+    *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + (size_t)nt * CS + cc) =
+        *(const u32x4*)(Cs + rr * CLD + cc);
+  }
+}
+
+#define MOE_INST_WIDE(EPI)                                                                   \
+  template __global__ void gemm_bf16_wide<EPI>(                                              \
+      const bf16_t* __restrict__, const bf16_t* __restrict__, bf16_t* __restrict__,          \
+      const int32_t* __restrict__, const int32_t* __restrict__, int, int, int, int, int, int, \
+      int);
+MOE_INST_WIDE(EPI_SWIGLU)
+MOE_INST_WIDE(EPI_PLAIN)
+#undef MOE_INST_WIDE
+
 // ------------------------------------------------------------------ FP8
 // Per-block FP8 e4m3 quantisation (block amax, inv = 448 / amax, codes of
 // x * inv, scale = amax / 448; an all-zero block has scale 1 and codes 0).
@@ -1144,7 +1307,13 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
       hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, BM, w.tile_start);
     const int mt_big = (N + GBM - 1) / GBM + c.E;
     PROF_BEGIN("gemm1_swiglu", st);
-    if (big1) {
+    if (c.d_ff % 128 == 0 && c.d % XBK == 0) {
+      const int nt = c.d_ff / 128;
+      const int G = (mt_big * nt + 7) / 8 * 8;
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_SWIGLU>), dim3(G), dim3(64 * XW), 0,
+                         st, (const bf16_t*)X_perm, (const bf16_t*)W13, (bf16_t*)w.h, offsets,
+                         w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt, G);
+    } else if (big1) {
       const int nt = c.d_ff / 64;
       const int G = (mt_big * nt + 7) / 8 * 8;
       hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_SWIGLU, false>), dim3(G), dim3(256), 0,
@@ -1158,7 +1327,13 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
     }
     PROF_END("gemm1_swiglu", st);
     PROF_BEGIN("gemm2", st);
-    if (big2) {
+    if (c.d % 256 == 0 && c.d_ff % XBK == 0) {
+      const int nt = c.d / 256;
+      const int G = (mt_big * nt + 7) / 8 * 8;
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN>), dim3(G), dim3(64 * XW), 0, st,
+                         (const bf16_t*)w.h, (const bf16_t*)W2, (bf16_t*)Y, offsets,
+                         w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt, G);
+    } else if (big2) {
       const int nt = c.d / 128;
       const int G = (mt_big * nt + 7) / 8 * 8;
       hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_PLAIN, false>), dim3(G), dim3(256), 0,
