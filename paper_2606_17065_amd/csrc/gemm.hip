@@ -1069,29 +1069,33 @@ __global__ __launch_bounds__(256, 2) void gemm_wgrad(const bf16_t* __restrict__ 
 // out[b][c][r] = in[b][r][c], 64 x 64 tiles through LDS.
 __global__ __launch_bounds__(256) void batched_transpose(const bf16_t* __restrict__ in,
                                                          bf16_t* __restrict__ out, int R, int C) {
-  __shared__ bf16_t tile[64][64 + 2];
+  // 64 x 64 tiles, 16-byte loads along C and 16-byte stores along R (R and
+  // C are multiples of 64)
+  __shared__ __attribute__((aligned(16))) bf16_t tile[64][72];
   const size_t base = (size_t)blockIdx.z * R * C;
   const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
-  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-    const int r = i >> 6, c = i & 63;
-    if (r0 + r < R && c0 + c < C) tile[r][c] = in[base + (size_t)(r0 + r) * C + c0 + c];
+  for (int v = threadIdx.x; v < 512; v += 256) {
+    const int r = v >> 3, cc = (v & 7) * 8;
+    *(bf16x8*)&tile[r][cc] = *(const bf16x8*)(in + base + (size_t)(r0 + r) * C + c0 + cc);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-    const int c = i >> 6, r = i & 63;
-    if (r0 + r < R && c0 + c < C) out[base + (size_t)(c0 + c) * R + r0 + r] = tile[r][c];
+  for (int v = threadIdx.x; v < 512; v += 256) {
+    const int c = v >> 3, rr = (v & 7) * 8;
+    bf16x8 y;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[u] = tile[rr + u][c];
+    *(bf16x8*)(out + base + (size_t)(c0 + c) * R + r0 + rr) = y;
   }
 }
-
-// outT[c][p] for padded slot positions p: the source row of slot
-// offsets[e] + (p - pad_off[e]) (through row_map when gathering), or zero in
-// an expert's pad.  64 positions x 64 channels per block.
 __global__ __launch_bounds__(256) void slot_transpose(const bf16_t* __restrict__ src,
                                                       const int32_t* __restrict__ row_map, int T,
                                                       int C, const int32_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ ptile, int E,
                                                       bf16_t* __restrict__ outT, int ldT) {
-  __shared__ bf16_t tile[64][64 + 2];
+  // 64 padded slots x 64 channels per block; 16-byte loads of token rows,
+  // 16-byte stores along the slots (C, ldT and the slot offset are
+  // multiples of 64)
+  __shared__ __attribute__((aligned(16))) bf16_t tile[64][72];
   __shared__ int srow[64];
   const int p0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   const int total = ptile[E] * 32;
@@ -1115,15 +1119,26 @@ __global__ __launch_bounds__(256) void slot_transpose(const bf16_t* __restrict__
     srow[threadIdx.x] = r;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-    const int pl = i >> 6, c = i & 63;
+  for (int v = threadIdx.x; v < 512; v += 256) {
+    const int pl = v >> 3, cc = (v & 7) * 8;
     const int r = srow[pl];
-    tile[pl][c] = (r >= 0 && c0 + c < C) ? src[(size_t)r * C + c0 + c] : (bf16_t)0.0f;
+    bf16x8 x;
+    if (r >= 0) {
+      x = *(const bf16x8*)(src + (size_t)r * C + c0 + cc);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = (bf16_t)0.0f;
+    }
+    *(bf16x8*)&tile[pl][cc] = x;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-    const int c = i >> 6, pl = i & 63;
-    if (c0 + c < C && p0 + pl < total) outT[(size_t)(c0 + c) * ldT + p0 + pl] = tile[pl][c];
+  for (int v = threadIdx.x; v < 512; v += 256) {
+    const int c = v >> 3, pr = (v & 7) * 8;
+    if (p0 + pr >= total) continue;
+    bf16x8 y;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[u] = tile[pr + u][c];
+    *(bf16x8*)(outT + (size_t)(c0 + c) * ldT + p0 + pr) = y;
   }
 }
 
