@@ -140,3 +140,49 @@ def test_fp8_ffn_rejects_unaligned_widths():
                          x.data_ptr(), x.data_ptr(), x.data_ptr(), x.data_ptr(), x.data_ptr(),
                          1 << 30, 0)
     assert e.value.status == L.MOE_EUNSUPPORTED
+
+
+def test_fp8_experts_config_sampled():
+    """The FP8-expert workload at full size (T=65536, d=4096, E=64, top-8,
+    d_ff=1408) in the configuration the benchmark times; two tokens are
+    checked against the FP8-emulating oracle on two of their experts each
+    (the oracle quantises those experts' BF16 weights itself)."""
+    shape = synth.SHAPES[3]
+    inp = synth.make_inputs(shape, 3)
+    X = torch.from_numpy(inp["X"]).to(torch.bfloat16).cuda()
+    Wr = torch.from_numpy(inp["Wr"]).cuda()
+    br = torch.from_numpy(inp["br"]).cuda()
+    W13 = torch.from_numpy(inp["W13"]).to(torch.bfloat16).cuda()
+    W2 = torch.from_numpy(inp["W2"]).to(torch.bfloat16).cuda()
+    del inp
+    q13, s13 = layer.quantize_fp8(W13, 128)
+    q2, s2 = layer.quantize_fp8(W2, 128)
+    cfg = cfg_for(shape)
+    r = layer.forward(cfg, X, Wr, br, q13, q2, W13_scale=s13, W2_scale=s2)
+    torch.cuda.synchronize()
+    info = r["info"].cpu().numpy()
+    assert int(info[L.INFO_STATUS]) == 0
+    assert int(r["load"].max()) <= cfg.capacity
+    sel = r["idx"].cpu().numpy()
+    inv = r["inv_map"].cpu().numpy()
+    Y = r["Y"]
+    for t in (0, shape.T - 1):
+        xt = X[t:t + 1].float().cpu().numpy()
+        xq, xs = fp8.quantize_blocks(xt, 1, 128)
+        slot = int(inv[t, 0])
+        np.testing.assert_array_equal(r["X_perm"][slot].cpu().numpy(), xq[0])
+        np.testing.assert_array_equal(r["X_perm_scale"][slot].cpu().numpy(), xs[0])
+        xd = fp8.dequantize_blocks(xq, xs, 1, 128)
+        for j in (0, shape.k - 1):
+            e = int(sel[t, j])
+            w13q, w13s = fp8.quantize_blocks(W13[e].float().cpu().numpy(), 128, 128)
+            np.testing.assert_array_equal(q13[e].cpu().numpy(), w13q)
+            w2q, w2s = fp8.quantize_blocks(W2[e].float().cpu().numpy(), 128, 128)
+            Wd = fp8.dequantize_blocks(w13q, w13s, 128, 128)
+            A = xd @ Wd[:shape.f].T
+            B = xd @ Wd[shape.f:].T
+            h = fp8.round_bf16(A / (1.0 + np.exp(-A)) * B)
+            hq, hs = fp8.quantize_blocks(h.astype(np.float32), 1, 128)
+            y = fp8.dequantize_blocks(hq, hs, 1, 128) @ fp8.dequantize_blocks(w2q, w2s, 128, 128).T
+            got = Y[int(inv[t, j])].float().cpu().numpy()
+            assert rel_fro(got, y[0]) <= 1e-2, (t, j)

@@ -221,3 +221,36 @@ def test_learned_prices_train_and_route_bit_exact():
         assert rr["V"] == 0.0 and rr["gap"] <= P.GAP_TOL
         cg = _cfg(T, E, k, mode=L.MOE_PRICE_GIVEN)
         assert_route_matches(cg, rr, replica_route(cg, s, phat))
+
+
+def test_learned_price_path_at_full_size():
+    """Learned-price workload shapes (E=256, d=2048, top-8, T=16384 tokens
+    through the router): features against the oracle, warm-started routing
+    bit-exact against the replica started from gamma * p_hat, and the
+    certificate against the oracle's objectives."""
+    from _helpers import device_inputs
+    from paper_2606_17065_amd import layer
+    shape = synth.SHAPES[5]
+    inp = synth.make_inputs(shape, 5, rep=2, experts=False)
+    d, h = device_inputs(shape, inp)
+    T, E, k = shape.T, shape.E, shape.k
+    cfg = L.make_cfg(T, shape.d, E, k, shape.f, shape.capacity, 50, L.MOE_BF16, L.MOE_BF16,
+                     L.MOE_PRICE_ACP)
+    logits = layer.route(cfg, d["X"], d["Wr"], d["br"])["logits"]
+    torch.cuda.synchronize()
+    s = logits.cpu().numpy()
+    feats, _ = P.logit_stats(cfg, logits)
+    ref = M.features(s, k, cfg.capacity)
+    got = feats.cpu().numpy().astype(np.float64)
+    assert (np.abs(got - ref) / np.maximum(1.0, np.abs(ref))).max() <= 2e-6
+    params = torch.from_numpy(M.init_params(21)).cuda()
+    rw = P.learned_route(cfg, logits, params, mode="warm")
+    torch.cuda.synchronize()
+    cw = _cfg(T, E, k, mode=L.MOE_PRICE_WARM)
+    assert_route_matches(cw, rw, replica_route(cw, s, rw["p_hat"].cpu().numpy()))
+    cert = P.certify(cfg, logits, rw["price"], rw["idx"]).cpu().numpy()
+    sel = rw["idx"].cpu().numpy()
+    prim = R.primal_objective(s, sel)
+    dual = R.dual_objective(s, rw["price"].cpu().numpy(), k, cfg.capacity)
+    assert abs(cert[0] - prim) <= 1e-12 * abs(prim)
+    assert abs(cert[1] - dual) <= 1e-12 * abs(dual)
