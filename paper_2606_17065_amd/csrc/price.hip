@@ -7,9 +7,9 @@
 //                holding rank k (defines the plain top-k set at p = 0)
 //   ls_cols      64-token x 64-expert tiles: margins m0, transposed sortable
 //                keys of s and m0, per-tile FP64 column partials
-//   ls_expert    per expert: fold the partials in tile order, (C+1)-th
+//   ls_expert    per expert: fold the tile partials (fixed order), (C+1)-th
 //                largest s and m0 by radix select
-//   ls_features  global mean / std (fixed order over experts), features
+//   ls_features  global mean / std (fixed tree over experts), features
 #include <math.h>
 
 #include "common.h"
@@ -133,31 +133,83 @@ __global__ __launch_bounds__(256) void ls_cols(const float* __restrict__ s, int 
 }
 
 // r-th largest key (1-based, r <= n) of col[0..n) by four 8-bit radix
-// passes; 1024 threads.
+// passes; 1024 threads.  With KPT > 0 the column is loaded once into
+// registers (n <= 1024 * KPT), otherwise it is re-read every pass.
+// Wavefront aggregation: when every counted key of a wavefront falls in one
+// bin (the usual case in the first passes, where the logits of a column
+// share sign and exponent) one atomic adds them all.
+__device__ __forceinline__ void hist_add(bool ok, uint32_t dg, int lane, int* hist) {
+  const unsigned long long act = __ballot(ok);
+  if (act == 0ull) return;
+  const int first = __ffsll((long long)act) - 1;
+  const uint32_t d0 = (uint32_t)__shfl((int)dg, first, 64);
+  const unsigned long long same = __ballot(ok && dg == d0);
+  if (same == act) {
+    if (lane == first) atomicAdd(&hist[d0], __popcll(act));
+  } else if (ok) {
+    atomicAdd(&hist[dg], 1);
+  }
+}
+
+template <int KPT>
 __device__ uint32_t block_rth_key(const uint32_t* __restrict__ col, int n, int r, int* hist,
                                   int* sh) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  constexpr int NT = 1024;
+  uint32_t kk[KPT > 0 ? KPT : 1];
+  if (KPT > 0) {
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const int i = j * NT + tid;
+      kk[j] = i < n ? col[i] : 0u;
+    }
+  }
   uint32_t prefix = 0u, mask = 0u;
   int need = r;
   for (int shift = 24; shift >= 0; shift -= 8) {
-    for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0;
+    for (int i = tid; i < 256; i += NT) hist[i] = 0;
     __syncthreads();
-    for (int i = tid; i < n; i += blockDim.x) {
-      const uint32_t key = col[i];
-      if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1);
+    if (KPT > 0) {
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        const int i = j * NT + tid;
+        hist_add(i < n && (kk[j] & mask) == prefix, (kk[j] >> shift) & 255u, lane, hist);
+      }
+    } else {
+      for (int i0 = 0; i0 < n; i0 += NT) {
+        const int i = i0 + tid;
+        const uint32_t key = i < n ? col[i] : 0u;
+        hist_add(i < n && (key & mask) == prefix, (key >> shift) & 255u, lane, hist);
+      }
     }
     __syncthreads();
-    if (tid == 0) {
-      int acc = 0, dg = 0;
-      for (int b = 255; b >= 0; --b) {
-        if (acc + hist[b] >= need) {
-          dg = b;
-          break;
-        }
-        acc += hist[b];
+    if (tid < 64) {
+      // wavefront 0: lane l owns bins 4l..4l+3; suffix sums over the lanes
+      // find the bin holding the need-th largest key
+      int c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c[u] = hist[4 * tid + u];
+      const int loc = c[0] + c[1] + c[2] + c[3];
+      int suf = loc;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_down(suf, off, 64);
+        if (tid + off < 64) suf += o;
       }
-      sh[0] = dg;
-      sh[1] = need - acc;
+      const int above = suf - loc;
+      if (above < need && need <= suf) {
+        int acc = above, dg = 4 * tid;
+#pragma unroll
+        for (int u = 3; u >= 0; --u) {
+          if (acc + c[u] >= need) {
+            dg = 4 * tid + u;
+            break;
+          }
+          acc += c[u];
+        }
+        sh[0] = dg;
+        sh[1] = need - acc;
+      }
     }
     __syncthreads();
     prefix |= (uint32_t)sh[0] << shift;
@@ -168,8 +220,8 @@ __device__ uint32_t block_rth_key(const uint32_t* __restrict__ col, int n, int r
   return prefix;
 }
 
-// One block per expert: fold the tile partials in tile order and select
-// the (C+1)-th largest s and m0 of the expert's column.
+// One block per expert: fold the tile partials and select the (C+1)-th
+// largest s and m0 of the expert's column.
 __global__ __launch_bounds__(1024) void ls_expert(const uint32_t* __restrict__ sT,
                                                   const uint32_t* __restrict__ mT,
                                                   const double* __restrict__ part, int ntile,
@@ -177,38 +229,65 @@ __global__ __launch_bounds__(1024) void ls_expert(const uint32_t* __restrict__ s
                                                   float* __restrict__ q) {
   __shared__ int hist[256];
   __shared__ int sh[2];
+  __shared__ double red[1024];
   const int e = blockIdx.x, tid = threadIdx.x;
-  if (tid < NSTAT) {
-    double a = tid == 2 ? -INFINITY : 0.0;
-    for (int b = 0; b < ntile; ++b) {
-      const double v = part[((size_t)b * E + e) * NSTAT + tid];
-      a = tid == 2 ? fmax(a, v) : a + v;
+  // each statistic: thread i folds tiles i, i+1024, ... in order, then a
+  // fixed halving tree (deterministic, independent of scheduling)
+  for (int st = 0; st < NSTAT; ++st) {
+    double a = st == 2 ? -INFINITY : 0.0;
+    for (int b = tid; b < ntile; b += 1024) {
+      const double v = part[((size_t)b * E + e) * NSTAT + st];
+      a = st == 2 ? fmax(a, v) : a + v;
     }
-    col[e * NSTAT + tid] = a;
+    red[tid] = a;
+    __syncthreads();
+    for (int h = 512; h >= 1; h >>= 1) {
+      if (tid < h) red[tid] = st == 2 ? fmax(red[tid], red[tid + h]) : red[tid] + red[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) col[e * NSTAT + st] = red[0];
+    __syncthreads();
   }
   const int r = C + 1 < T ? C + 1 : T;
-  const uint32_t ks = block_rth_key(sT + (size_t)e * T, T, r, hist, sh);
-  const uint32_t km = block_rth_key(mT + (size_t)e * T, T, r, hist, sh);
+  uint32_t ks, km;
+  if (T <= 1024 * 16) {
+    ks = block_rth_key<16>(sT + (size_t)e * T, T, r, hist, sh);
+    km = block_rth_key<16>(mT + (size_t)e * T, T, r, hist, sh);
+  } else if (T <= 1024 * 64) {
+    ks = block_rth_key<64>(sT + (size_t)e * T, T, r, hist, sh);
+    km = block_rth_key<64>(mT + (size_t)e * T, T, r, hist, sh);
+  } else {
+    ks = block_rth_key<0>(sT + (size_t)e * T, T, r, hist, sh);
+    km = block_rth_key<0>(mT + (size_t)e * T, T, r, hist, sh);
+  }
   if (tid == 0) {
     q[2 * e] = key_f32(ks);
     q[2 * e + 1] = key_f32(km);
   }
 }
 
-// One block: global mean / std over all T*E logits (experts summed in
-// index order), then the eight features of every expert.
+// One block: global mean / std over all T*E logits (expert totals summed
+// by a fixed tree), then the eight features of every expert.
 __global__ __launch_bounds__(1024) void ls_features(const double* __restrict__ col,
                                                     const float* __restrict__ q, int T, int E,
                                                     int C, float* __restrict__ feats,
                                                     float* __restrict__ sigma_out) {
   __shared__ double g[2];
+  __shared__ double r1[1024], r2[1024];
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    double s1 = 0.0, s2 = 0.0;
-    for (int e = 0; e < E; ++e) {
-      s1 += col[e * NSTAT + 0];
-      s2 += col[e * NSTAT + 1];
+  // expert sums by a fixed halving tree (E <= 1024)
+  r1[tid] = tid < E ? col[tid * NSTAT + 0] : 0.0;
+  r2[tid] = tid < E ? col[tid * NSTAT + 1] : 0.0;
+  __syncthreads();
+  for (int h = 512; h >= 1; h >>= 1) {
+    if (tid < h) {
+      r1[tid] = r1[tid] + r1[tid + h];
+      r2[tid] = r2[tid] + r2[tid + h];
     }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double s1 = r1[0], s2 = r2[0];
     const double n = (double)T * (double)E;
     const double mu = s1 / n;
     double var = s2 / n - mu * mu;
