@@ -293,6 +293,7 @@ __device__ __forceinline__ void mma_pipeline(char* lds, const bf16_t* (&asrc)[AI
   stage_barrier();
   READ_FRAGS(a0, b0, 0, 0);
   for (int kt = 0; kt + 1 < nk; ++kt) {
+    __builtin_amdgcn_iglp_opt(1);
     READ_FRAGS(a1, b1, kt, 1);
     MFMA8(a0, b0);
     // step kt+1 must have landed: at most step kt+2 remains in flight
@@ -557,6 +558,9 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   stage_barrier();
   X_READ(a0, b0, 0, 0);
   for (int kt = 0; kt < nk; ++kt) {
+    // LLVM's single-wavefront MFMA interleave strategy for the loop body
+    // (measured 5-8% faster on both forward products)
+    __builtin_amdgcn_iglp_opt(1);
     X_READ(a1, b1, kt, 1);
     X_MFMA(a0, b0);
     X_READ(a0, b0, kt, 2);
