@@ -702,13 +702,21 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // FP8 grouped GEMM with per-block scales: A codes [N,K] with scales
 // [N, K/128] (1 x 128 blocks), B codes [E, Brows, K] with scales
-// [E, Brows/128, K/128] (128 x 128 blocks).  Same tiles, tile order, DMA
-// staging and LDS layout as gemm_bf16_big, with 64 FP8 values of K per
-// 64-byte stage row: one v_mfma_f32_32x32x64_f8f6f4 per 32x32 tile and
-// stage.  Each 128-wide K block is accumulated on its own (two stages) and
-// then promoted into the FP32 result: acc += partial * (sa * sb).
-// A lane holds one token row of each 32x32 tile, so sa is one value per
-// row tile and sb one value per column tile.
+// [E, Brows/128, K/128] (128 x 128 blocks).  Tiles and tile order as
+// gemm_bf16_big (256 tokens x 128 weight rows, 4 wavefronts of 128 x 64);
+// one stage is one 128-wide K block: 128-byte LDS rows (a full cache line
+// per row) with the chunk swizzle physical = logical ^ (row & 7), three
+// stages of 48 KB, one block per CU.  Per stage and 32x32 tile, two
+// v_mfma_f32_32x32x64_f8f6f4 accumulate the block on its own, which is then
+// promoted into the FP32 result: acc += partial * (sa * sb).  A lane holds
+// one token row of each tile, so sa is one value per row tile and sb one
+// value per column tile (wavefront-uniform).
+constexpr int F8_STAGE_A = GBM * 128, F8_STAGE_B = GBN * 128;
+constexpr int F8_STAGE = F8_STAGE_A + F8_STAGE_B;
+constexpr int F8_NSTAGE = 3;
+constexpr int F8_LDS = F8_NSTAGE * F8_STAGE > EPI_BYTES ? F8_NSTAGE * F8_STAGE : EPI_BYTES;
+constexpr int F8_A_INS = GBM * 128 / 1024 / 4, F8_B_INS = GBN * 128 / 1024 / 4;
+
 template <int EPI>
 __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
     const fp8_t* __restrict__ A, const float* __restrict__ As, const fp8_t* __restrict__ B,
@@ -717,7 +725,7 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
     int grid_total) {
   typedef __attribute__((address_space(3))) void lds_void;
   constexpr bool PAIRED = EPI == EPI_SWIGLU;
-  __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
+  __shared__ __attribute__((aligned(1024))) char lds[F8_LDS];
   const int b = blockIdx.x;
   const int per = grid_total >> 3;
   const int Lt = (b & 7) * per + (b >> 3);
@@ -729,30 +737,43 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   const int Brows_e = PAIRED ? 2 * f : Ncols;
   const int nkb = K / 128;
   const fp8_t* Be = B + (size_t)e * Brows_e * K;
-  const fp8_t* asrc[A_INS];
-  const fp8_t* bsrc[B_INS];
+  // DMA: one instruction = 8 rows x 128 bytes; lane -> (row + lane/8,
+  // physical chunk lane%8)
+  const fp8_t* asrc[F8_A_INS];
+  const fp8_t* bsrc[F8_B_INS];
 #pragma unroll
-  for (int i = 0; i < A_INS; ++i) {
-    const int R = wv * (GBM / 4) + i * 16 + (lane >> 2);
-    const int c = (lane & 3) ^ swz(R);
+  for (int i = 0; i < F8_A_INS; ++i) {
+    const int R = wv * (GBM / 4) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ (R & 7);
     asrc[i] = A + (size_t)(row0 + min(R, rows - 1)) * K + c * 16;
   }
 #pragma unroll
-  for (int i = 0; i < B_INS; ++i) {
-    const int R = wv * (GBN / 4) + i * 16 + (lane >> 2);
-    const int c = (lane & 3) ^ swz(R);
+  for (int i = 0; i < F8_B_INS; ++i) {
+    const int R = wv * (GBN / 4) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ (R & 7);
     const int wrow = PAIRED ? (R < 64 ? n0 + R : f + n0 + (R - 64)) : n0 + R;
     bsrc[i] = Be + (size_t)wrow * K + c * 16;
   }
+  const int fr = lane & 31, fh = lane >> 5;
   int aoff[4], asw[4], boff[2], bsw[2];
-  frag_offsets(wm, PAIRED ? wn * 32 : wn * 64, PAIRED ? 64 + wn * 32 : wn * 64 + 32, lane, aoff,
-               asw, boff, bsw);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int R = wm * 128 + i * 32 + fr;
+    aoff[i] = R * 128;
+    asw[i] = R & 7;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int R = (PAIRED ? (j == 0 ? wn * 32 : 64 + wn * 32) : wn * 64 + j * 32) + fr;
+    boff[j] = F8_STAGE_A + R * 128;
+    bsw[j] = R & 7;
+  }
   // scale rows: token rows of the lane in each row tile, weight row blocks
   // of the wavefront's two column tiles
   const float* sa_row[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
-    sa_row[i] = As + (size_t)(row0 + min(wm * 128 + i * 32 + (lane & 31), rows - 1)) * nkb;
+    sa_row[i] = As + (size_t)(row0 + min(wm * 128 + i * 32 + fr, rows - 1)) * nkb;
   const int wr0 = PAIRED ? n0 + wn * 32 : n0 + wn * 64;
   const int wr1 = PAIRED ? f + n0 + wn * 32 : n0 + wn * 64 + 32;
   const float* sb_row0 = Bs + ((size_t)e * (Brows_e / 128) + wr0 / 128) * nkb;
@@ -761,30 +782,32 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   f32x16 acc[4][2], part[4][2];
   zero_acc(acc);
   zero_acc(part);
-  const int nk = K / 64;
-  constexpr int VMS = A_INS + B_INS;
-  const int fh = lane >> 5;
+  const int nk = nkb;
+  constexpr int VMS = F8_A_INS + F8_B_INS;
 #define F8_ISSUE(kstep)                                                                        \
   {                                                                                            \
-    char* st_ = lds + ((kstep) % NSTAGE) * STAGE_BYTES;                                        \
-    const int k0_ = (kstep) * 64;                                                              \
-    _Pragma("unroll") for (int i = 0; i < A_INS; ++i) __builtin_amdgcn_global_load_lds(        \
-        asrc[i] + k0_, (lds_void*)(st_ + (wv * (GBM / 4) + i * 16) * 64), 16, 0, 0);           \
-    _Pragma("unroll") for (int i = 0; i < B_INS; ++i) __builtin_amdgcn_global_load_lds(        \
-        bsrc[i] + k0_, (lds_void*)(st_ + STAGE_A + (wv * (GBN / 4) + i * 16) * 64), 16, 0, 0); \
+    char* st_ = lds + ((kstep) % F8_NSTAGE) * F8_STAGE;                                        \
+    const int k0_ = (kstep) * 128;                                                             \
+    _Pragma("unroll") for (int i = 0; i < F8_A_INS; ++i) __builtin_amdgcn_global_load_lds(     \
+        asrc[i] + k0_, (lds_void*)(st_ + (wv * (GBM / 4) + i * 8) * 128), 16, 0, 0);           \
+    _Pragma("unroll") for (int i = 0; i < F8_B_INS; ++i) __builtin_amdgcn_global_load_lds(     \
+        bsrc[i] + k0_, (lds_void*)(st_ + F8_STAGE_A + (wv * (GBN / 4) + i * 8) * 128), 16, 0,  \
+        0);                                                                                    \
   }
-#define F8_READ(AF, BF, stp)                                                                  \
+  // K half h of a stage: chunks 4h + fh and 4h + 2 + fh of each row
+#define F8_READ(AF, BF, stp, h)                                                               \
   {                                                                                           \
-    const char* st_ = lds + ((stp) % NSTAGE) * STAGE_BYTES;                                   \
+    const char* st_ = lds + ((stp) % F8_NSTAGE) * F8_STAGE;                                   \
+    const int c0_ = 4 * (h) + fh, c1_ = 4 * (h) + 2 + fh;                                     \
     _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                           \
-      const u32x4 lo_ = *(const u32x4*)(st_ + aoff[i] + ((fh ^ asw[i]) << 4));                \
-      const u32x4 hi_ = *(const u32x4*)(st_ + aoff[i] + (((2 + fh) ^ asw[i]) << 4));          \
+      const u32x4 lo_ = *(const u32x4*)(st_ + aoff[i] + ((c0_ ^ asw[i]) << 4));               \
+      const u32x4 hi_ = *(const u32x4*)(st_ + aoff[i] + ((c1_ ^ asw[i]) << 4));               \
       AF[i] = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                     \
                       (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};                    \
     }                                                                                         \
     _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                           \
-      const u32x4 lo_ = *(const u32x4*)(st_ + boff[j] + ((fh ^ bsw[j]) << 4));                \
-      const u32x4 hi_ = *(const u32x4*)(st_ + boff[j] + (((2 + fh) ^ bsw[j]) << 4));          \
+      const u32x4 lo_ = *(const u32x4*)(st_ + boff[j] + ((c0_ ^ bsw[j]) << 4));               \
+      const u32x4 hi_ = *(const u32x4*)(st_ + boff[j] + ((c1_ ^ bsw[j]) << 4));               \
       BF[j] = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                     \
                       (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};                    \
     }                                                                                         \
@@ -793,49 +816,43 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   _Pragma("unroll") for (int i = 0; i < 4; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) \
       part[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(BF[j], AF[i], part[i][j], \
                                                                     0, 0, 0, 0, 0, 0);
-  i32x8 a0[4], b0[2], a1[4], b1[2];
-  float sa[4], sb[2];
-  F8_ISSUE(0);
-  if (nk > 1) F8_ISSUE(1);
-  if (nk > 2) F8_ISSUE(2);
-  if (nk > 2) {
-    WAIT_VM_LGKM0(2 * VMS);
-  } else if (nk > 1) {
-    WAIT_VM_LGKM0(VMS);
-  } else {
-    WAIT_VM_LGKM0(0);
+#define F8_WAITN(n_)                         \
+  switch (n_) {                              \
+    case 0: WAIT_VM_LGKM0(0); break;         \
+    case 1: WAIT_VM_LGKM0(VMS); break;       \
+    default: WAIT_VM_LGKM0(2 * VMS); break;  \
   }
-  stage_barrier();
-  F8_READ(a0, b0, 0);
-  for (int kt = 0; kt < nk; kt += 2) {
-    // K block kt/2: stages kt (in a0/b0) and kt+1
-    const int kb = kt >> 1;
-    // stage kt+1 landed (stage kt+2 may still be in flight)
-    if (kt + 2 < nk) {
-      WAIT_VM_LGKM0(VMS);
-    } else {
-      WAIT_VM_LGKM0(0);
-    }
-    stage_barrier();
-    // the scale loads go out before the next DMA issue, so the next
-    // vmcnt(VMS) wait covers them without waiting for that issue
+  i32x8 a0[4], b0[2], a1[4], b1[2];
+  float sa[4], sb[2], san[4], sbn[2];
+  const int pre = nk < F8_NSTAGE ? nk : F8_NSTAGE;
+  for (int s_ = 0; s_ < pre; ++s_) F8_ISSUE(s_);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sa[i] = sa_row[i][kb];
-    sb[0] = sb_row0[kb];
-    sb[1] = sb_row1[kb];
-    if (kt + 3 < nk) F8_ISSUE(kt + 3);
-    F8_READ(a1, b1, kt + 1);
+  for (int i = 0; i < 4; ++i) san[i] = sa_row[i][0];
+  sbn[0] = sb_row0[0];
+  sbn[1] = sb_row1[0];
+  F8_WAITN(pre - 1);
+  stage_barrier();
+  F8_READ(a0, b0, 0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sa[i] = san[i];
+    sb[0] = sbn[0];
+    sb[1] = sbn[1];
+    F8_READ(a1, b1, kt, 1);
     F8_MFMA(a0, b0);
-    // stage kt+2 landed (kt+3 may be in flight); everyone is done with kt+1
-    if (kt + 2 < nk) {
-      if (kt + 3 < nk) {
-        WAIT_VM_LGKM0(VMS);
-      } else {
-        WAIT_VM_LGKM0(0);
-      }
+    if (kt + 1 < nk) {
+      // stage kt+1 landed; every wavefront is done reading stage kt
+      const int last = nk - 1 < kt + F8_NSTAGE - 1 ? nk - 1 : kt + F8_NSTAGE - 1;
+      F8_WAITN(last - (kt + 1));
       stage_barrier();
-      if (kt + 4 < nk) F8_ISSUE(kt + 4);
-      F8_READ(a0, b0, kt + 2);
+      // next block's scales go out before the next DMA issue, so the
+      // following vmcnt waits cover them without waiting for that issue
+#pragma unroll
+      for (int i = 0; i < 4; ++i) san[i] = sa_row[i][kt + 1];
+      sbn[0] = sb_row0[kt + 1];
+      sbn[1] = sb_row1[kt + 1];
+      if (kt + F8_NSTAGE < nk) F8_ISSUE(kt + F8_NSTAGE);
+      F8_READ(a0, b0, kt + 1, 0);
     }
     F8_MFMA(a1, b1);
 #pragma unroll
@@ -853,13 +870,14 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
 #undef F8_ISSUE
 #undef F8_READ
 #undef F8_MFMA
+#undef F8_WAITN
   WAIT_VM_LGKM0(0);
   stage_barrier();
 
   constexpr int CS = EPI == EPI_SWIGLU ? 64 : 128;
   constexpr int CLD = CS + 8;
   bf16_t* Cs = (bf16_t*)lds;
-  const int fr = lane & 31, cbase = (lane >> 5) * 4;
+  const int cbase = (lane >> 5) * 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int rl = wm * 128 + i * 32 + fr;

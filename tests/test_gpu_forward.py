@@ -182,3 +182,24 @@ def test_layer_forward_bf16_scale_config_sampled():
             _, _, _, y = ffn.expert_forward(h["X"][t:t + 1], W13e, W2e)
             exp[i] += w64[i, j] * y[0]
     assert rel_fro(got, exp) <= 1.5e-2
+
+
+@pytest.mark.parametrize("T", [0, 1, 5])
+def test_layer_forward_tiny_batches(T):
+    """Empty and single-token batches through every stage of the layer."""
+    shape = MID.with_tokens(T)
+    cfg = cfg_for(shape, capacity=max(1, synth.capacity(T, shape.k, shape.E)))
+    inp = synth.make_inputs(MID.with_tokens(max(T, 1)), 19)
+    d, h = device_inputs(shape, {**inp, "X": inp["X"][:T]})
+    r = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"])
+    torch.cuda.synchronize()
+    assert int(r["info"][L.INFO_STATUS]) == 0
+    assert r["out"].shape == (T, shape.d)
+    if T == 0:
+        assert int(r["load"].sum()) == 0
+        return
+    sel = r["idx"].cpu().numpy()
+    assert all(len(set(row)) == shape.k for row in sel)
+    ref = ffn.layer_forward(h["X"], sel, r["w"].cpu().numpy().astype(np.float64), h["W13"],
+                            h["W2"])
+    assert rel_fro(r["out"].float().cpu().numpy(), ref["out"]) <= 1.5e-2
