@@ -1488,11 +1488,11 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
       hipLaunchKernelGGL(gemm_dgrad1, dim3(G), dim3(256), 0, st, dYb, w.W2T, w.AB, w.dAB, w.dABT,
                          w.hT, w.ldT, offsets, w.tile_start, w.ptile, E, N, d, f, nt, G);
     }
-    {  // dX_perm = [dA|dB] W13
-      const int nt = d / 128, G = (mt * nt + 7) / 8 * 8;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_PLAIN, false>), dim3(G), dim3(256), 0,
-                         st, w.dAB, nullptr, 0, w.W13T, (bf16_t*)dX_perm, offsets, w.tile_start, E,
-                         N, 2 * f, f, d, nt, G);
+    {  // dX_perm = [dA|dB] W13 (d % 256 == 0: the 256 x 256 tile)
+      const int nt = d / 256, G = (mt * nt + 7) / 8 * 8;
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN>), dim3(G), dim3(64 * XW), 0, st,
+                         w.dAB, w.W13T, (bf16_t*)dX_perm, offsets, w.tile_start, E, N, 2 * f, f,
+                         d, nt, G);
     }
     const int pblocks = (w.ldT + 63) / 64;
     hipLaunchKernelGGL(slot_transpose, dim3(pblocks, d / 64), dim3(256), 0, st, Xb, row_map, c.T,
