@@ -473,13 +473,17 @@ constexpr int XLDS = 2 * XSTAGE > XEPI ? 2 * XSTAGE : XEPI;
 constexpr int XW = 8;  // wavefronts per block: 2 (rows) x 4 (columns), each 128 x 64
 constexpr int XA_INS = GBM * 128 / 1024 / XW, XB_INS = XBN * 128 / 1024 / XW;
 
-template <int EPI>
+// EPI_AB (backward): the SwiGLU tiles, storing A and B themselves (row
+// length 2f: A at column n, B at column f + n).  GATHER: token row r of
+// the A operand is X[row_map[r]] (the permute recomputed, not read).
+template <int EPI, bool GATHER>
 __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
-    const bf16_t* __restrict__ A, const bf16_t* __restrict__ B, bf16_t* __restrict__ C,
-    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start, int E, int N,
-    int K, int f, int Ncols, int n_tiles, int grid_total) {
+    const bf16_t* __restrict__ A, const int32_t* __restrict__ row_map, int T,
+    const bf16_t* __restrict__ B, bf16_t* __restrict__ C, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ tile_start, int E, int N, int K, int f, int Ncols, int n_tiles,
+    int grid_total) {
   typedef __attribute__((address_space(3))) void lds_void;
-  constexpr bool PAIRED = EPI == EPI_SWIGLU;
+  constexpr bool PAIRED = EPI != EPI_PLAIN;
   __shared__ __attribute__((aligned(1024))) char lds[XLDS];
   const int b = blockIdx.x;
   const int per = grid_total >> 3;
@@ -497,7 +501,9 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   for (int i = 0; i < XA_INS; ++i) {
     const int R = wv * (GBM / XW) + i * 8 + (lane >> 3);
     const int c = (lane & 7) ^ (R & 7);
-    asrc[i] = A + (size_t)(row0 + min(R, rows - 1)) * K + c * 8;
+    const int r = row0 + min(R, rows - 1);
+    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
+    asrc[i] = A + arow * K + c * 8;
   }
 #pragma unroll
   for (int i = 0; i < XB_INS; ++i) {
@@ -579,7 +585,9 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   WAIT_VM_LGKM0(0);
   stage_barrier();
 
-  constexpr int CS = PAIRED ? 128 : 256;
+  // SwiGLU: 128 h columns per tile; EPI_AB: the A half in columns 0..127 of
+  // the LDS tile and the B half in 128..255; plain: 256 columns
+  constexpr int CS = EPI == EPI_SWIGLU ? 128 : 256;
   constexpr int CLD = CS + 8;
   bf16_t* Cs = (bf16_t*)lds;
   const int cbase = fh * 4;
@@ -587,15 +595,16 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   for (int i = 0; i < 4; ++i) {
     const int rl = wm * 128 + i * 32 + fr;
 #pragma unroll
-    for (int j = 0; j < (PAIRED ? 1 : 2); ++j) {
-      const int col0 = PAIRED ? wn * 32 : wn * 64 + j * 32;
+    for (int j = 0; j < (EPI == EPI_SWIGLU ? 1 : 2); ++j) {
+      const int col0 = EPI == EPI_SWIGLU ? wn * 32
+                                         : (EPI == EPI_AB ? j * 128 + wn * 32 : wn * 64 + j * 32);
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         bf16x4 v;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const float x = acc[i][j][g * 4 + q];
-          if (PAIRED) v[q] = (bf16_t)(silu(x) * acc[i][1][g * 4 + q]);
+          if (EPI == EPI_SWIGLU) v[q] = (bf16_t)(silu(x) * acc[i][1][g * 4 + q]);
           else v[q] = (bf16_t)x;
         }
         *(bf16x4*)(Cs + rl * CLD + col0 + g * 8 + cbase) = v;
@@ -607,18 +616,21 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   for (int c = tid; c < GBM * CPR; c += 64 * XW) {
     const int rr = c / CPR, cc = (c - rr * CPR) * 8;
     if (rr >= rows) continue;
-    *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + (size_t)nt * CS + cc) =
-        *(const u32x4*)(Cs + rr * CLD + cc);
+    size_t col;
+    if (EPI == EPI_AB) col = cc < 128 ? (size_t)n0 + cc : (size_t)f + n0 + (cc - 128);
+    else col = (size_t)nt * CS + cc;
+    *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + col) = *(const u32x4*)(Cs + rr * CLD + cc);
   }
 }
 
-#define MOE_INST_WIDE(EPI)                                                                   \
-  template __global__ void gemm_bf16_wide<EPI>(                                              \
-      const bf16_t* __restrict__, const bf16_t* __restrict__, bf16_t* __restrict__,          \
-      const int32_t* __restrict__, const int32_t* __restrict__, int, int, int, int, int, int, \
-      int);
-MOE_INST_WIDE(EPI_SWIGLU)
-MOE_INST_WIDE(EPI_PLAIN)
+#define MOE_INST_WIDE(EPI, GATHER)                                                          \
+  template __global__ void gemm_bf16_wide<EPI, GATHER>(                                     \
+      const bf16_t* __restrict__, const int32_t* __restrict__, int, const bf16_t* __restrict__, \
+      bf16_t* __restrict__, const int32_t* __restrict__, const int32_t* __restrict__, int, int, \
+      int, int, int, int, int);
+MOE_INST_WIDE(EPI_SWIGLU, false)
+MOE_INST_WIDE(EPI_PLAIN, false)
+MOE_INST_WIDE(EPI_AB, true)
 #undef MOE_INST_WIDE
 
 // ------------------------------------------------------------------ FP8
@@ -1347,9 +1359,10 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
     if (c.d_ff % 128 == 0 && c.d % XBK == 0) {
       const int nt = c.d_ff / 128;
       const int G = (mt_big * nt + 7) / 8 * 8;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_SWIGLU>), dim3(G), dim3(64 * XW), 0,
-                         st, (const bf16_t*)X_perm, (const bf16_t*)W13, (bf16_t*)w.h, offsets,
-                         w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt, G);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_SWIGLU, false>), dim3(G),
+                         dim3(64 * XW), 0, st, (const bf16_t*)X_perm, nullptr, 0,
+                         (const bf16_t*)W13, (bf16_t*)w.h, offsets, w.tile_start_big, c.E, N, c.d,
+                         c.d_ff, c.d_ff, nt, G);
     } else if (big1) {
       const int nt = c.d_ff / 64;
       const int G = (mt_big * nt + 7) / 8 * 8;
@@ -1367,9 +1380,10 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
     if (c.d % 256 == 0 && c.d_ff % XBK == 0) {
       const int nt = c.d / 256;
       const int G = (mt_big * nt + 7) / 8 * 8;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN>), dim3(G), dim3(64 * XW), 0, st,
-                         (const bf16_t*)w.h, (const bf16_t*)W2, (bf16_t*)Y, offsets,
-                         w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt, G);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G),
+                         dim3(64 * XW), 0, st, (const bf16_t*)w.h, nullptr, 0, (const bf16_t*)W2,
+                         (bf16_t*)Y, offsets, w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt,
+                         G);
     } else if (big2) {
       const int nt = c.d / 128;
       const int G = (mt_big * nt + 7) / 8 * 8;
@@ -1477,11 +1491,11 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
                      (const bf16_t*)W2, w.W2T, d, f);
   const int mt = (N + GBM - 1) / GBM + E;
   if (N > 0) {
-    {  // [A|B] = Xp W13^T with the permute recomputed
-      const int nt = f / 64, G = (mt * nt + 7) / 8 * 8;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_AB, true>), dim3(G), dim3(256), 0, st,
-                         Xb, row_map, c.T, (const bf16_t*)W13, w.AB, offsets, w.tile_start, E, N,
-                         d, f, 2 * f, nt, G);
+    {  // [A|B] = Xp W13^T with the permute recomputed (f % 128 == 0)
+      const int nt = f / 128, G = (mt * nt + 7) / 8 * 8;
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_AB, true>), dim3(G), dim3(64 * XW), 0,
+                         st, Xb, row_map, c.T, (const bf16_t*)W13, w.AB, offsets, w.tile_start, E,
+                         N, d, f, 2 * f, nt, G);
     }
     {  // U = dY W2, then dA, dB, h
       const int nt = f / 128, G = (mt * nt + 7) / 8 * 8;
@@ -1490,9 +1504,9 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
     }
     {  // dX_perm = [dA|dB] W13 (d % 256 == 0: the 256 x 256 tile)
       const int nt = d / 256, G = (mt * nt + 7) / 8 * 8;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN>), dim3(G), dim3(64 * XW), 0, st,
-                         w.dAB, w.W13T, (bf16_t*)dX_perm, offsets, w.tile_start, E, N, 2 * f, f,
-                         d, nt, G);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G),
+                         dim3(64 * XW), 0, st, w.dAB, nullptr, 0, w.W13T, (bf16_t*)dX_perm,
+                         offsets, w.tile_start, E, N, 2 * f, f, d, nt, G);
     }
     const int pblocks = (w.ldT + 63) / 64;
     hipLaunchKernelGGL(slot_transpose, dim3(pblocks, d / 64), dim3(256), 0, st, Xb, row_map, c.T,
