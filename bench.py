@@ -174,7 +174,10 @@ def main():
     stages["gemm1_swiglu"].update(flop=gemm1_flop,
                                   tflops=gemm1_flop / (stages["gemm1_swiglu"]["ms"] * 1e9))
     stages["gemm2"].update(flop=gemm2_flop, tflops=gemm2_flop / (stages["gemm2"]["ms"] * 1e9))
-    disp_bytes = T * d * b + N * d * b + 4.0 * (T * shape.k * 3 + E + 1)
+    # with the permute fused into GEMM 1 the dispatch stage only builds the
+    # slot maps (idx read, row_map and inv_map written)
+    fused = layer.gather_fused(cfg)
+    disp_bytes = 4.0 * (T * shape.k * 3 + E + 1) + (0.0 if fused else T * d * b + N * d * b)
     comb_bytes = N * d * b + T * d * b + 8.0 * N
     stages["dispatch"].update(bytes=disp_bytes, gbs=disp_bytes / (stages["dispatch"]["ms"] * 1e6))
     stages["combine"].update(bytes=comb_bytes, gbs=comb_bytes / (stages["combine"]["ms"] * 1e6))
@@ -214,7 +217,8 @@ def main():
         "dtype": "bf16" if shape.act == "bf16" else "f32", "data": "synthetic",
         "config": {"workload": f"moe-{shape.name}", "T": T, "d_model": d, "E": E, "top_k": shape.k,
                    "d_ff": f, "capacity": shape.capacity, "zipf": shape.zipf,
-                   "router": "fp32", "price": "acp", "global_batch": T, "seq_len": 1,
+                   "router": "fp32", "price": "acp", "permute": "fused into GEMM 1" if fused
+                   else "explicit", "global_batch": T, "seq_len": 1,
                    "parallelism": "single-gpu"},
         "price_iters": int(info[0]), "converged": bool(info[1]),
         "slots_per_s": value * shape.k, "wall_s": wall,

@@ -234,7 +234,8 @@ moe_status moe_adam_step(int n, float* params, const float* grads, float* m, flo
  *   FP8 experts (cfg.w == MOE_FP8E4M3, d % 128 == 0): every token row is
  *   quantised per 1 x 128 block as moe_quantize_fp8 does and X_perm [N,d]
  *   u8 receives the codes, X_perm_scale [N, d/128] f32 the scales (NULL
- *   otherwise).
+ *   otherwise).  Other dtypes: X_perm may be NULL, in which case only the
+ *   maps are written (for moe_expert_ffn_gather, which gathers itself).
  */
 moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int32_t* topk_idx,
                         int32_t* offsets, int32_t* row_map, int32_t* inv_map, void* X_perm,
@@ -264,6 +265,18 @@ moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm, const float* X
                           const int32_t* offsets, const void* W13, const float* W13_scale,
                           const void* W2, const float* W2_scale, void* Y, void* ws,
                           size_t ws_bytes, void* stream);
+
+/*
+ * moe_expert_ffn_gather -- moe_expert_ffn with the permute fused into the
+ *   first product: row r of the experts' input is X[row_map[r]], read
+ *   straight from X [T,d] (no X_perm).  Same definition and results as
+ *   moe_dispatch followed by moe_expert_ffn.  Requires BF16 activations and
+ *   weights, d_ff % 128 == 0 and d % 256 == 0 (else MOE_EUNSUPPORTED).
+ *   row_map [N] and offsets [E+1] as moe_dispatch writes them.
+ */
+moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X, const int32_t* row_map,
+                                 const int32_t* offsets, const void* W13, const void* W2, void* Y,
+                                 void* ws, size_t ws_bytes, void* stream);
 
 /*
  * moe_quantize_fp8 -- OCP FP8 e4m3 block quantisation of src [rows, cols]

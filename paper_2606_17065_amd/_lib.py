@@ -54,6 +54,7 @@ SIGNATURES = {
     "moe_route": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_dispatch": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_expert_ffn": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_expert_ffn_gather": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_quantize_fp8": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P],
     "moe_combine": [_CFG, _P, _P, _P, _P, _P],
     "moe_combine_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P],
@@ -131,6 +132,11 @@ def moe_expert_ffn(cfg, X_perm, X_perm_scale, offsets, W13, W13_scale, W2, W2_sc
                    ws_bytes, stream):
     _check(lib().moe_expert_ffn(ctypes.byref(cfg), X_perm, X_perm_scale, offsets, W13, W13_scale,
                                 W2, W2_scale, Y, ws, ws_bytes, stream), "moe_expert_ffn")
+
+
+def moe_expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, Y, ws, ws_bytes, stream):
+    _check(lib().moe_expert_ffn_gather(ctypes.byref(cfg), X, row_map, offsets, W13, W2, Y, ws,
+                                       ws_bytes, stream), "moe_expert_ffn_gather")
 
 
 def moe_quantize_fp8(rows, cols, block_rows, src_dtype, src, codes, scales, stream):

@@ -253,7 +253,9 @@ extern "C" moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int3
   const moe_cfg& c = *cfg;
   const bool fp8 = c.w == MOE_FP8E4M3;
   if (!offsets) return MOE_EINVAL;
-  if (c.T > 0 && (!X || !topk_idx || !row_map || !inv_map || !X_perm)) return MOE_EINVAL;
+  if (c.T > 0 && (!topk_idx || !row_map || !inv_map)) return MOE_EINVAL;
+  if (c.T > 0 && (fp8 || X_perm) && !X) return MOE_EINVAL;
+  if (c.T > 0 && fp8 && !X_perm) return MOE_EINVAL;
   if (fp8 && c.d % 128 != 0) return MOE_EUNSUPPORTED;
   if (fp8 && c.T > 0 && !X_perm_scale) return MOE_EINVAL;
   if (!aligned(X_perm_scale, 4)) return MOE_EINVAL;
@@ -273,9 +275,12 @@ extern "C" moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int3
     hipLaunchKernelGGL(dispatch_scatter, dim3(nb), dim3(TB), 0, st, topk_idx, c.T, c.E, c.k, w.cnt,
                        row_map, inv_map);
     if (!fp8) {
-      const int row_vec = c.d * act_bytes(c.act) / 16;
-      hipLaunchKernelGGL(dispatch_gather, dim3((c.T + 3) / 4), dim3(256), 0, st, (const u32x4*)X,
-                         c.T, row_vec, c.k, inv_map, (u32x4*)X_perm);
+      // X_perm NULL: maps only (the first expert product gathers X itself)
+      if (X_perm) {
+        const int row_vec = c.d * act_bytes(c.act) / 16;
+        hipLaunchKernelGGL(dispatch_gather, dim3((c.T + 3) / 4), dim3(256), 0, st,
+                           (const u32x4*)X, c.T, row_vec, c.k, inv_map, (u32x4*)X_perm);
+      }
     } else if (c.act == MOE_BF16) {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_gather_fp8<bf16_t>), dim3((c.T + 3) / 4),
                          dim3(256), 0, st, (const bf16_t*)X, c.T, c.d, c.k, inv_map,

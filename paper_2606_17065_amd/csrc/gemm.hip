@@ -629,6 +629,7 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
       bf16_t* __restrict__, const int32_t* __restrict__, const int32_t* __restrict__, int, int, \
       int, int, int, int, int);
 MOE_INST_WIDE(EPI_SWIGLU, false)
+MOE_INST_WIDE(EPI_SWIGLU, true)
 MOE_INST_WIDE(EPI_PLAIN, false)
 MOE_INST_WIDE(EPI_AB, true)
 #undef MOE_INST_WIDE
@@ -1560,6 +1561,49 @@ extern "C" moe_status moe_quantize_fp8(int rows, int cols, int block_rows, int s
     else
       hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_tiles<float>), g, dim3(256), 0, st,
                          (const float*)src, rows, cols, codes, scales);
+  }
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X,
+                                            const int32_t* row_map, const int32_t* offsets,
+                                            const void* W13, const void* W2, void* Y, void* ws,
+                                            size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.act != MOE_BF16 || c.w != MOE_BF16) return MOE_EUNSUPPORTED;
+  if (c.d_ff % 128 != 0 || c.d % 256 != 0) return MOE_EUNSUPPORTED;
+  if (!offsets || !W13 || !W2) return MOE_EINVAL;
+  if (c.T > 0 && (!X || !row_map || !Y)) return MOE_EINVAL;
+  if (!aligned(X, 16) || !aligned(W13, 16) || !aligned(W2, 16) || !aligned(Y, 16) ||
+      !aligned(offsets, 4) || !aligned(row_map, 4))
+    return MOE_EINVAL;
+  if (ws_bytes < ffn_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  if (c.T == 0) return MOE_OK;
+  hipStream_t st = (hipStream_t)stream;
+  FfnWs w = carve_ffn(c, ws, nullptr);
+  const int N = c.T * c.k;
+  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
+  const int mt_big = (N + GBM - 1) / GBM + c.E;
+  {
+    const int nt = c.d_ff / 128;
+    const int G = (mt_big * nt + 7) / 8 * 8;
+    PROF_BEGIN("gemm1_swiglu", st);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_SWIGLU, true>), dim3(G), dim3(64 * XW),
+                       0, st, (const bf16_t*)X, row_map, c.T, (const bf16_t*)W13, (bf16_t*)w.h,
+                       offsets, w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt, G);
+    PROF_END("gemm1_swiglu", st);
+  }
+  {
+    const int nt = c.d / 256;
+    const int G = (mt_big * nt + 7) / 8 * 8;
+    PROF_BEGIN("gemm2", st);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G), dim3(64 * XW),
+                       0, st, (const bf16_t*)w.h, nullptr, 0, (const bf16_t*)W2, (bf16_t*)Y,
+                       offsets, w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt, G);
+    PROF_END("gemm2", st);
   }
   MOE_LAUNCH_CHECK();
   return MOE_OK;

@@ -68,18 +68,21 @@ def route(cfg, X, Wr, br, price=None, ws=None):
     return out
 
 
-def dispatch(cfg, X, idx, ws=None):
+def dispatch(cfg, X, idx, ws=None, permute=True):
     """Slot maps and permuted tokens; with FP8 experts X_perm holds e4m3
-    codes (uint8) and X_perm_scale the per-1x128-block scales."""
+    codes (uint8) and X_perm_scale the per-1x128-block scales.  With
+    permute=False (not FP8) only the maps are produced (X_perm is None)."""
     T, d, E, k = cfg.T, cfg.d, cfg.E, cfg.k
     _need(X, "X", _DT[cfg.act], (T, d))
     _need(idx, "topk_idx", torch.int32, (T, k))
     dev = X.device
     fp8 = cfg.w == L.MOE_FP8E4M3
+    permute = permute or fp8
     out = dict(offsets=torch.empty(E + 1, dtype=torch.int32, device=dev),
                row_map=torch.empty(T * k, dtype=torch.int32, device=dev),
                inv_map=torch.empty(T, k, dtype=torch.int32, device=dev),
-               X_perm=torch.empty(T * k, d, dtype=torch.uint8 if fp8 else X.dtype, device=dev),
+               X_perm=(torch.empty(T * k, d, dtype=torch.uint8 if fp8 else X.dtype, device=dev)
+                       if permute else None),
                X_perm_scale=(torch.empty(T * k, d // 128, dtype=torch.float32, device=dev)
                              if fp8 else None))
     ws = _WS.get(cfg, dev) if ws is None else ws
@@ -143,12 +146,37 @@ def combine(cfg, Y, inv_map, w):
     return out
 
 
-def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None):
-    """The whole layer forward; returns every intermediate."""
+def gather_fused(cfg) -> bool:
+    """True when the first expert product can read X through row_map."""
+    return (cfg.act == L.MOE_BF16 and cfg.w == L.MOE_BF16 and cfg.d_ff % 128 == 0
+            and cfg.d % 256 == 0)
+
+
+def expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, ws=None):
+    N, d, E, f = cfg.T * cfg.k, cfg.d, cfg.E, cfg.d_ff
+    _need(X, "X", _DT[cfg.act], (cfg.T, d))
+    _need(row_map, "row_map", torch.int32, (N,))
+    _need(offsets, "offsets", torch.int32, (E + 1,))
+    _need(W13, "W13", _DT[cfg.w], (E, 2 * f, d))
+    _need(W2, "W2", _DT[cfg.w], (E, d, f))
+    Y = torch.empty(N, d, dtype=X.dtype, device=X.device)
+    ws = _WS.get(cfg, X.device) if ws is None else ws
+    L.moe_expert_ffn_gather(cfg, _p(X), _p(row_map), _p(offsets), _p(W13), _p(W2), _p(Y), _p(ws),
+                            ws.numel(), _stream())
+    return Y
+
+
+def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None, fuse=True):
+    """The whole layer forward; returns every intermediate (X_perm is None
+    when the permute is fused into the first expert product)."""
     r = route(cfg, X, Wr, br, price)
-    dsp = dispatch(cfg, X, r["idx"])
-    Y = expert_ffn(cfg, dsp["X_perm"], dsp["offsets"], W13, W2, W13_scale, W2_scale,
-                   X_perm_scale=dsp["X_perm_scale"])
+    if fuse and gather_fused(cfg):
+        dsp = dispatch(cfg, X, r["idx"], permute=False)
+        Y = expert_ffn_gather(cfg, X, dsp["row_map"], dsp["offsets"], W13, W2)
+    else:
+        dsp = dispatch(cfg, X, r["idx"])
+        Y = expert_ffn(cfg, dsp["X_perm"], dsp["offsets"], W13, W2, W13_scale, W2_scale,
+                       X_perm_scale=dsp["X_perm_scale"])
     out = combine(cfg, Y, dsp["inv_map"], r["w"])
     r.update(dsp)
     r["Y"] = Y

@@ -98,6 +98,18 @@ def test_entry_points_reject_bad_arguments_on_the_host():
         L.moe_dispatch(_cfg(w=L.MOE_FP8E4M3), fake, fake, fake, fake, fake, fake, None, fake,
                        1 << 30, None)
     assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:  # FP8 dispatch needs the code output too
+        L.moe_dispatch(_cfg(w=L.MOE_FP8E4M3), fake, fake, fake, fake, fake, None, fake, fake,
+                       1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:  # the fused gather is BF16-only
+        L.moe_expert_ffn_gather(_cfg(act=L.MOE_F32, w=L.MOE_F32), fake, fake, fake, fake, fake,
+                                fake, fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EUNSUPPORTED
+    with pytest.raises(L.MoEError) as e:  # row_map missing
+        L.moe_expert_ffn_gather(_cfg(d=256, act=L.MOE_BF16, w=L.MOE_BF16), fake, None, fake, fake, fake,
+                                fake, fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL
     with pytest.raises(L.MoEError) as e:
         L.moe_quantize_fp8(4, 100, 1, L.MOE_BF16, fake, fake, fake, None)  # cols % 128
     assert e.value.status == L.MOE_EINVAL

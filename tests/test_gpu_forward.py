@@ -203,3 +203,18 @@ def test_layer_forward_tiny_batches(T):
     ref = ffn.layer_forward(h["X"], sel, r["w"].cpu().numpy().astype(np.float64), h["W13"],
                             h["W2"])
     assert rel_fro(r["out"].float().cpu().numpy(), ref["out"]) <= 1.5e-2
+
+
+def test_fused_gather_matches_separate_permute():
+    """The first expert product reading X through row_map gives the same
+    bits as the explicit permute followed by the product."""
+    shape = BIG_TILES
+    cfg = cfg_for(shape)
+    assert layer.gather_fused(cfg)
+    inp = synth.make_inputs(shape, 23)
+    d, _ = device_inputs(shape, inp, host_weights=False)
+    a = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"], fuse=True)
+    b = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"], fuse=False)
+    torch.cuda.synchronize()
+    assert a["X_perm"] is None and b["X_perm"] is not None
+    assert torch.equal(a["Y"], b["Y"]) and torch.equal(a["out"], b["out"])
