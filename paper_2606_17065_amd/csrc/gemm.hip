@@ -12,7 +12,9 @@
 
 namespace moe_gemm {
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 
 // tile_start[e] = sum_{e' < e} ceil(rows_e' / BM); tile_start[E] = total.
 __global__ __launch_bounds__(1024) void ffn_tiles(const int32_t* __restrict__ offsets, int E,
@@ -462,7 +464,11 @@ MOE_INST_BIG(EPI_AB, true)
 // each 128 x 64 as 4 x 2 tiles of v_mfma_f32_32x32x16_bf16), so two
 // wavefronts per SIMD as in the 256 x 128 kernel but half the L2 bytes per
 // flop and one barrier per 32 MFMAs.  Chunk swizzle over the eight 16-byte
-// chunks of a row: physical = logical ^ (row & 7).  SwiGLU: weight rows
+// chunks of a row: physical = logical ^ ((row >> 1) & 7).  A 128-byte row is
+// half of the 64 four-byte LDS banks and a 128-bit fragment read serves 16
+// lanes (16 consecutive rows, one chunk each) per cycle, so rows r and r + 8
+// must differ in their chunk too; with ^ (row & 7) they met in the same
+// banks, a two-way conflict on every read.  SwiGLU: weight rows
 // 0..127 are W1 rows n0.., 128..255 the matching W3 rows; wavefront wn owns
 // outputs wn*32 .. wn*32+31 (gate tile and up tile).
 constexpr int XBN = 256, XBK = 64;
@@ -500,7 +506,7 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
 #pragma unroll
   for (int i = 0; i < XA_INS; ++i) {
     const int R = wv * (GBM / XW) + i * 8 + (lane >> 3);
-    const int c = (lane & 7) ^ (R & 7);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
     const int r = row0 + min(R, rows - 1);
     const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
     asrc[i] = A + arow * K + c * 8;
@@ -508,7 +514,7 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
 #pragma unroll
   for (int i = 0; i < XB_INS; ++i) {
     const int R = wv * (XBN / XW) + i * 8 + (lane >> 3);
-    const int c = (lane & 7) ^ (R & 7);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
     const int wrow = PAIRED ? (R < 128 ? n0 + R : f + n0 + (R - 128)) : n0 + R;
     bsrc[i] = Be + (size_t)wrow * K + c * 8;
   }
@@ -518,14 +524,14 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   for (int i = 0; i < 4; ++i) {
     const int R = wm * 128 + i * 32 + fr;
     aoff[i] = R * 128;
-    asw[i] = R & 7;
+    asw[i] = (R >> 1) & 7;
   }
   // SwiGLU: wavefront wn owns 32 outputs: gate rows wn*32.., up rows 128+wn*32..
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int R = (PAIRED ? (j == 0 ? wn * 32 : 128 + wn * 32) : wn * 64 + j * 32) + fr;
     boff[j] = XSTAGE_A + R * 128;
-    bsw[j] = R & 7;
+    bsw[j] = (R >> 1) & 7;
   }
   f32x16 acc[4][2];
   zero_acc(acc);
@@ -718,7 +724,8 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 // [E, Brows/128, K/128] (128 x 128 blocks).  Tiles and tile order as
 // gemm_bf16_big (256 tokens x 128 weight rows, 4 wavefronts of 128 x 64);
 // one stage is one 128-wide K block: 128-byte LDS rows (a full cache line
-// per row) with the chunk swizzle physical = logical ^ (row & 7), three
+// per row) with the chunk swizzle physical = logical ^ ((row >> 1) & 7) of
+// the 256 x 256 kernel (conflict-free 128-bit fragment reads), three
 // stages of 48 KB, one block per CU.  Per stage and 32x32 tile, two
 // v_mfma_f32_32x32x64_f8f6f4 accumulate the block on its own, which is then
 // promoted into the FP32 result: acc += partial * (sa * sb).  A lane holds
@@ -757,13 +764,13 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
 #pragma unroll
   for (int i = 0; i < F8_A_INS; ++i) {
     const int R = wv * (GBM / 4) + i * 8 + (lane >> 3);
-    const int c = (lane & 7) ^ (R & 7);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
     asrc[i] = A + (size_t)(row0 + min(R, rows - 1)) * K + c * 16;
   }
 #pragma unroll
   for (int i = 0; i < F8_B_INS; ++i) {
     const int R = wv * (GBN / 4) + i * 8 + (lane >> 3);
-    const int c = (lane & 7) ^ (R & 7);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
     const int wrow = PAIRED ? (R < 64 ? n0 + R : f + n0 + (R - 64)) : n0 + R;
     bsrc[i] = Be + (size_t)wrow * K + c * 16;
   }
@@ -773,13 +780,13 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   for (int i = 0; i < 4; ++i) {
     const int R = wm * 128 + i * 32 + fr;
     aoff[i] = R * 128;
-    asw[i] = R & 7;
+    asw[i] = (R >> 1) & 7;
   }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int R = (PAIRED ? (j == 0 ? wn * 32 : 64 + wn * 32) : wn * 64 + j * 32) + fr;
     boff[j] = F8_STAGE_A + R * 128;
-    bsw[j] = R & 7;
+    bsw[j] = (R >> 1) & 7;
   }
   // scale rows: token rows of the lane in each row tile, weight row blocks
   // of the wavefront's two column tiles
@@ -971,7 +978,7 @@ __device__ __forceinline__ void dgrad1_pass(const f32x16 (&acc)[4][2], char* lds
         for (int q = 0; q < 4; ++q) {
           const float u = acc[i][j][g * 4 + q];
           const float a = (float)av[q], bb = (float)bv[q];
-          const float sg = 1.0f / (1.0f + __expf(-a));
+          const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-a));
           const float sa = a * sg;
           float v;
           if (PASS == 0) v = u * bb * (sg + sa * (1.0f - sg));  // dA
