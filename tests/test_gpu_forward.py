@@ -184,12 +184,17 @@ def test_layer_forward_bf16_scale_config_sampled():
     assert rel_fro(got, exp) <= 1.5e-2
 
 
-@pytest.mark.parametrize("T", [0, 1, 5])
-def test_layer_forward_tiny_batches(T):
-    """Empty and single-token batches through every stage of the layer."""
-    shape = MID.with_tokens(T)
+@pytest.mark.parametrize("base", ["ragged", "fused"])
+@pytest.mark.parametrize("T", [0, 1, 5, 130])
+def test_layer_forward_tiny_batches(T, base):
+    """Empty, single-token and sub-tile batches through every stage of the
+    layer, on the explicit-permute path (d_ff = 192) and on the path with
+    the permute fused into the first expert product."""
+    full = MID if base == "ragged" else BIG_TILES
+    shape = full.with_tokens(T)
     cfg = cfg_for(shape, capacity=max(1, synth.capacity(T, shape.k, shape.E)))
-    inp = synth.make_inputs(MID.with_tokens(max(T, 1)), 19)
+    assert layer.gather_fused(cfg) == (base == "fused")
+    inp = synth.make_inputs(full.with_tokens(max(T, 1)), 19)
     d, h = device_inputs(shape, {**inp, "X": inp["X"][:T]})
     r = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"])
     torch.cuda.synchronize()
