@@ -137,6 +137,20 @@ moe_status moe_route_logits(const moe_cfg* cfg, const float* logits, float* pric
                             void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * moe_price_update -- the capacity-price update alone (the ascending
+ *   clearing-price iteration of moe_route, its sigma_s and eps, in
+ *   cfg.price_mode), from caller-supplied logits [T,E] f32 (read only):
+ *   price [E] f32 in/out receives the final prices and info
+ *   [MOE_INFO_LEN] i32 the iteration count, convergence flag, overflow of
+ *   the final ranking and status, exactly as moe_route_logits reports them
+ *   for the same inputs.  The routing the update ends with is kept in the
+ *   workspace and not returned.  ws: at least moe_workspace_bytes(cfg)
+ *   (MOE_EWORKSPACE otherwise).  Other arguments as in moe_route.
+ */
+moe_status moe_price_update(const moe_cfg* cfg, const float* logits, float* price, int32_t* info,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/*
  * moe_route_certify -- duality certificate of a routing under prices p:
  *   cert[0] = primal  sum_t sum_j s[t, topk_idx[t,j]]
  *   cert[1] = dual    D(p) = C sum_e p_e + sum_t (sum of the k largest

@@ -62,6 +62,7 @@ SIGNATURES = {
     "moe_dispatch_bwd": [_CFG, _P, _P, _P, _P],
     "moe_route_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_route_logits": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_price_update": [_CFG, _P, _P, _P, _P, _S, _P],
     "moe_route_certify": [_CFG, _P, _P, _P, _P, _P, _S, _P],
     "moe_logit_stats": [_CFG, _P, _P, _P, _P, _S, _P],
     "moe_price_mlp_sizes": [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
@@ -173,6 +174,11 @@ def moe_route_bwd(cfg, X, Wr, topk_idx, topk_w, dtopk_w, row_map, offsets, inv_m
 def moe_route_logits(cfg, logits, price, topk_idx, topk_w, load, info, ws, ws_bytes, stream):
     _check(lib().moe_route_logits(ctypes.byref(cfg), logits, price, topk_idx, topk_w, load, info,
                                   ws, ws_bytes, stream), "moe_route_logits")
+
+
+def moe_price_update(cfg, logits, price, info, ws, ws_bytes, stream):
+    _check(lib().moe_price_update(ctypes.byref(cfg), logits, price, info, ws, ws_bytes, stream),
+           "moe_price_update")
 
 
 def moe_route_certify(cfg, logits, price, topk_idx, cert, ws, ws_bytes, stream):

@@ -37,7 +37,7 @@ extern "C" moe_status moe_workspace_bytes(const moe_cfg* cfg, size_t* bytes) {
   if (!bytes) return MOE_EINVAL;
   moe_status st = check_cfg_shape(cfg);
   if (st != MOE_OK) return st;
-  size_t b = std::max(route_ws_bytes(*cfg), dispatch_ws_bytes(*cfg));
+  size_t b = std::max(price_ws_bytes(*cfg), dispatch_ws_bytes(*cfg));
   b = std::max(b, ffn_ws_bytes(*cfg));
   b = std::max(b, route_bwd_ws_bytes(*cfg));
   b = std::max(b, cert_ws_bytes(*cfg));

@@ -7,6 +7,7 @@
 
 // Workspace bytes each entry point carves from the caller's buffer.
 size_t route_ws_bytes(const moe_cfg& c);
+size_t price_ws_bytes(const moe_cfg& c);
 size_t dispatch_ws_bytes(const moe_cfg& c);
 size_t ffn_ws_bytes(const moe_cfg& c);
 size_t ffn_bwd_ws_bytes(const moe_cfg& c);

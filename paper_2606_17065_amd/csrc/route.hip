@@ -1201,3 +1201,39 @@ extern "C" moe_status moe_route_logits(const moe_cfg* cfg, const float* logits, 
                      logits, c.T, c.E, w.sT);
   return route_from_scores(c, w, logits, price, topk_idx, topk_w, load, info, st);
 }
+
+// The price update alone: the routing it ends with (idx, w, load) goes to
+// the tail of the workspace, after what moe_route_logits needs.
+namespace {
+struct PriceScratch {
+  int32_t* idx;
+  float* w;
+  int32_t* load;
+};
+
+PriceScratch carve_price_scratch(const moe_cfg& c, void* base, size_t* total) {
+  const size_t head = route_ws_bytes(c);
+  WsCarve wc{base ? (char*)base + head : nullptr, 0};
+  PriceScratch r;
+  r.idx = wc.take<int32_t>((size_t)c.T * c.k);
+  r.w = wc.take<float>((size_t)c.T * c.k);
+  r.load = wc.take<int32_t>((size_t)c.E);
+  if (total) *total = head + align_up(wc.off, 256);
+  return r;
+}
+}  // namespace
+
+size_t price_ws_bytes(const moe_cfg& c) {
+  size_t total = 0;
+  carve_price_scratch(c, nullptr, &total);
+  return total;
+}
+
+extern "C" moe_status moe_price_update(const moe_cfg* cfg, const float* logits, float* price,
+                                       int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  if (ws_bytes < price_ws_bytes(*cfg) || !ws) return MOE_EWORKSPACE;
+  PriceScratch sc = carve_price_scratch(*cfg, ws, nullptr);
+  return moe_route_logits(cfg, logits, price, sc.idx, sc.w, sc.load, info, ws, ws_bytes, stream);
+}

@@ -38,6 +38,20 @@ def route_logits(cfg, logits, price=None, ws=None):
     return out
 
 
+def price_update(cfg, logits, price=None, ws=None):
+    """moe_price_update: (price [E], info) after the price update on logits."""
+    _need(logits, "logits", torch.float32, (cfg.T, cfg.E))
+    dev = logits.device
+    if price is None:
+        price = torch.zeros(cfg.E, dtype=torch.float32, device=dev)
+    else:
+        _need(price, "price", torch.float32, (cfg.E,))
+    info = torch.zeros(L.INFO_LEN, dtype=torch.int32, device=dev)
+    ws = _WS.get(cfg, dev) if ws is None else ws
+    L.moe_price_update(cfg, _p(logits), _p(price), _p(info), _p(ws), ws.numel(), _stream())
+    return price, info
+
+
 def certify(cfg, logits, price, idx, ws=None):
     """[primal, dual, gap_rel] (f64 device tensor) of a routing under prices."""
     _need(logits, "logits", torch.float32, (cfg.T, cfg.E))

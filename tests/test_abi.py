@@ -119,3 +119,9 @@ def test_entry_points_reject_bad_arguments_on_the_host():
     with pytest.raises(L.MoEError) as e:
         L.moe_combine(cfg, None, fake, fake, fake, None)
     assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:
+        L.moe_price_update(cfg, fake, fake, fake, fake, 16, None)
+    assert e.value.status == L.MOE_EWORKSPACE
+    with pytest.raises(L.MoEError) as e:
+        L.moe_price_update(cfg, None, fake, fake, fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL

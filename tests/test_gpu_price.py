@@ -158,6 +158,26 @@ def test_route_logits_bit_exact(mode):
     assert_route_matches(cfg, r, ref)
 
 
+@pytest.mark.parametrize("mode", [L.MOE_PRICE_ACP, L.MOE_PRICE_WARM])
+def test_price_update_alone_matches_route(mode):
+    """moe_price_update gives the prices and info of moe_route_logits (and
+    of the FP32 replica of the update) bit for bit."""
+    s, sd = _logits(2049, 40, 63)
+    cfg = _cfg(2049, 40, 5, mode=mode)
+    p0 = torch.full((40,), 0.05, dtype=torch.float32, device="cuda")
+    price, info = P.price_update(cfg, sd, p0.clone())
+    r = P.route_logits(cfg, sd, p0.clone())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(price.cpu().numpy().view(np.uint32),
+                                  r["price"].cpu().numpy().view(np.uint32))
+    np.testing.assert_array_equal(info.cpu().numpy(), r["info"].cpu().numpy())
+    ref = replica_route(cfg, s, p0.cpu().numpy())
+    assert ref["iters"] > 0
+    np.testing.assert_array_equal(price.cpu().numpy().view(np.uint32),
+                                  np.asarray(ref["p"], np.float32).view(np.uint32))
+    assert int(info[L.INFO_ITERS]) == ref["iters"]
+
+
 def test_route_logits_empty_batch():
     cfg = _cfg(0, 8, 2, 0)
     r = P.route_logits(cfg, torch.empty(0, 8, device="cuda"))
