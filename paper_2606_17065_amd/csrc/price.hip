@@ -22,10 +22,12 @@ constexpr int NSTAT = 6;  // sum s, sum s^2, max s, sum m0, sum m0^2, load0
 
 template <int L>
 __device__ __forceinline__ void top_insert(uint32_t (&K)[L], int (&X)[L], uint32_t key, int e) {
-  // sorted descending; strict comparison keeps the lower expert first
+  // sorted by (key descending, expert ascending).  An entry pushed down
+  // the list can meet an equal key of a higher expert inserted after it,
+  // so the expert index takes part in every comparison, not only the key.
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    const bool gt = key > K[j];
+    const bool gt = key > K[j] || (key == K[j] && e < X[j]);
     const uint32_t hi = gt ? key : K[j], lo = gt ? K[j] : key;
     const int eh = gt ? e : X[j], el = gt ? X[j] : e;
     K[j] = hi;

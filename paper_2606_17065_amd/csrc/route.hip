@@ -348,14 +348,16 @@ __device__ __forceinline__ int key_expert(uint64_t v) { return (int)(0xFFFFFFFFu
 constexpr int RANK_WAVES = 4;
 
 // Top-L list as parallel arrays of sortable keys and expert indices, best
-// first.  Experts are inserted in increasing index order, so a strict
-// comparison keeps the lower expert ahead of an equal key.
+// first in the order (key descending, expert ascending).  The expert index
+// takes part in every comparison: an entry pushed down the list by a better
+// key can meet an equal key of a higher expert inserted after it, and must
+// stay ahead of it.
 template <int L>
 __device__ __forceinline__ void insert_kv(uint32_t (&K)[L], int (&X)[L], uint32_t key, int e) {
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    const bool gt = key > K[j];
-    const uint32_t hi = max(key, K[j]), lo = min(key, K[j]);
+    const bool gt = key > K[j] || (key == K[j] && e < X[j]);
+    const uint32_t hi = gt ? key : K[j], lo = gt ? K[j] : key;
     const int eh = gt ? e : X[j], el = gt ? X[j] : e;
     K[j] = hi;
     X[j] = eh;

@@ -158,6 +158,38 @@ def test_route_logits_bit_exact(mode):
     assert_route_matches(cfg, r, ref)
 
 
+# shapes at the limits of the ranking kernel: more than 64 experts per
+# wavefront range (logits streamed in chunks, E = 300 and the maximum
+# E = 1024), the top-17 lists (k = 12 and the maximum k = 16), and k = 1.
+# The raised prices make price-adjusted scores of different experts equal
+# (several experts' prices sit on the same token's margin), and these
+# shapes were the first to show a tie broken against the lower expert.
+@pytest.mark.parametrize("T,E,k,seed", [(1500, 300, 12, 81), (700, 1024, 16, 82),
+                                        (900, 8, 1, 83)])
+def test_route_logits_bit_exact_at_shape_limits(T, E, k, seed):
+    s, sd = _logits(T, E, seed)
+    cfg = _cfg(T, E, k)
+    r = P.route_logits(cfg, sd)
+    torch.cuda.synchronize()
+    ref = replica_route(cfg, s)
+    assert ref["iters"] > 0
+    assert_route_matches(cfg, r, ref)
+
+
+# logits on a grid of 0.25: exact ties between experts everywhere, in the
+# register-cached ranking (E = 64) and the chunked one (E = 200)
+@pytest.mark.parametrize("T,E,k,seed", [(1000, 64, 8, 84), (600, 200, 6, 85)])
+def test_route_logits_bit_exact_with_tied_logits(T, E, k, seed):
+    s = (np.round(synth.make_logits(T, E, 1.2, seed) * 4.0) / 4.0).astype(np.float32)
+    sd = torch.from_numpy(s).cuda()
+    cfg = _cfg(T, E, k)
+    r = P.route_logits(cfg, sd)
+    torch.cuda.synchronize()
+    ref = replica_route(cfg, s)
+    assert ref["iters"] > 0
+    assert_route_matches(cfg, r, ref)
+
+
 @pytest.mark.parametrize("mode", [L.MOE_PRICE_ACP, L.MOE_PRICE_WARM])
 def test_price_update_alone_matches_route(mode):
     """moe_price_update gives the prices and info of moe_route_logits (and
