@@ -347,25 +347,6 @@ __device__ __forceinline__ int key_expert(uint64_t v) { return (int)(0xFFFFFFFFu
 // blockIdx.x of cnt[nblk][E] (no global atomics).
 constexpr int RANK_WAVES = 4;
 
-// Top-L list as parallel arrays of sortable keys and expert indices, best
-// first in the order (key descending, expert ascending).  The expert index
-// takes part in every comparison: an entry pushed down the list by a better
-// key can meet an equal key of a higher expert inserted after it, and must
-// stay ahead of it.
-template <int L>
-__device__ __forceinline__ void insert_kv(uint32_t (&K)[L], int (&X)[L], uint32_t key, int e) {
-#pragma unroll
-  for (int j = 0; j < L; ++j) {
-    const bool gt = key > K[j] || (key == K[j] && e < X[j]);
-    const uint32_t hi = gt ? key : K[j], lo = gt ? K[j] : key;
-    const int eh = gt ? e : X[j], el = gt ? X[j] : e;
-    K[j] = hi;
-    X[j] = eh;
-    key = lo;
-    e = el;
-  }
-}
-
 // Token group of sub-group tg: gbase + tg * gstride (64 tokens each);
 // the block's per-expert counts go to row crow of cnt.  With a state
 // pointer the pass is skipped once the price loop is done.
@@ -407,18 +388,16 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
     ps[e] = price[e];
   }
   __syncthreads();
-  uint32_t K[L];
-  int X[L];
+  // the top-L list of this wavefront's experts as composite rank keys
+  // (key, then lower expert first): one 64-bit comparison per step
+  uint64_t V[L];
 #pragma unroll
-  for (int j = 0; j < L; ++j) {
-    K[j] = 0u;
-    X[j] = 0;
-  }
+  for (int j = 0; j < L; ++j) V[j] = 0ull;
   if (cached) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const uint32_t key = i < ne ? f32_key(sv[i] - ps[e_lo + min(i, max(ne - 1, 0))]) : 0u;
-      insert_kv<L>(K, X, key, e_lo + i);
+      insert_top<L>(V, ((uint64_t)key << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)(e_lo + i)));
     }
   } else {
     for (int c0 = 0; c0 < ne; c0 += NV) {
@@ -427,14 +406,15 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
         const uint32_t key = c0 + i < ne ? f32_key(sv[i] - ps[e_lo + min(c0 + i, ne - 1)]) : 0u;
-        insert_kv<L>(K, X, key, e_lo + c0 + i);
+        insert_top<L>(V, ((uint64_t)key << 32) |
+                             (uint64_t)(0xFFFFFFFFu - (uint32_t)(e_lo + c0 + i)));
       }
     }
   }
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    partk[tg][wv][j][lane] = K[j];
-    parte[tg][wv][j][lane] = X[j];
+    partk[tg][wv][j][lane] = (uint32_t)(V[j] >> 32);
+    parte[tg][wv][j][lane] = key_expert(V[j]);
   }
   __syncthreads();
   if (wv == 0 && valid) {
