@@ -56,6 +56,27 @@ def test_key_order_matches_float_order():
     assert R.f32_key(np.array([-0.0], F32))[0] < R.f32_key(np.array([0.0], F32))[0]
 
 
+@pytest.mark.parametrize("mode", ["none", "given"])
+def test_ties_rank_the_lower_expert_first(mode):
+    """Equal price-adjusted scores are ranked by expert index, lowest first:
+    the oracle's selection equals a brute-force Python sort of each token's
+    (-key, e) pairs, on logits with exact ties everywhere (a 0.5 grid) and,
+    in the given-price mode, prices on the same grid (more ties)."""
+    rng = np.random.default_rng(11)
+    T, E, k = 60, 12, 4
+    s = (np.round(rng.standard_normal((T, E)) * 2.0) / 2.0).astype(F32)
+    p = None
+    if mode == "given":
+        p = (np.round(rng.uniform(0.0, 1.0, E) * 2.0) / 2.0).astype(F32)
+    r = R.route(s, k, T * k, 0, p, mode)
+    a = s if p is None else (s - p[None, :]).astype(F32)
+    key = R.f32_key(a)
+    for t in range(T):
+        want = [e for _, e in sorted((-int(key[t, e]), e) for e in range(E))[:k]]
+        assert r["sel"][t].tolist() == want, t
+    assert (np.sort(key, axis=1)[:, :-1] == np.sort(key, axis=1)[:, 1:]).any()  # ties exist
+
+
 def test_sigma_is_the_population_std():
     s = synth.make_logits(3000, 17, 1.2, seed=5)
     S1, S2 = R.score_sums(s)
