@@ -91,113 +91,6 @@ __device__ __forceinline__ bool find_tile_grouped(const int32_t* __restrict__ ti
   return rows > 0;
 }
 
-// ---------------------------------------------------------------- BF16 MFMA
-// Block tile: 128 rows x 128 B-rows, K step 32; 4 wavefronts in 2 x 2, each
-// owning 64 rows x 64 B-rows as 2 x 2 tiles of v_mfma_f32_32x32x16_bf16.
-// SwiGLU mode: B-rows 0..63 are W1 rows n0..n0+63 and 64..127 the matching
-// W3 rows, so a wavefront's two column tiles are (W1 cols, W3 cols) of the
-// same 32 outputs and the epilogue combines them in registers.
-
-constexpr int BM = 128, BNE = 128, BK = 32, LDK = BK + 8;
-
-template <bool SWIGLU>
-__global__ __launch_bounds__(256) void gemm_bf16(const bf16_t* __restrict__ A,
-                                                 const bf16_t* __restrict__ B,
-                                                 bf16_t* __restrict__ C,
-                                                 const int32_t* __restrict__ offsets,
-                                                 const int32_t* __restrict__ tile_start, int E,
-                                                 int N, int K, int f, int Ncols) {
-  // K: reduction length; f: W1/W3 row split (SwiGLU); Ncols: C row length
-  __shared__ __attribute__((aligned(16))) bf16_t As[BM * LDK];
-  __shared__ __attribute__((aligned(16))) bf16_t Bs[BNE * LDK];
-  int e, row0, rows;
-  if (!find_tile(tile_start, offsets, E, BM, N, blockIdx.x, e, row0, rows)) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
-  const int n0 = blockIdx.y * (SWIGLU ? 64 : 128);
-  const size_t Brows_e = SWIGLU ? (size_t)2 * f : (size_t)Ncols;
-  const bf16_t* Be = B + (size_t)e * Brows_e * K;
-
-  // global -> register staging: 2 chunks of 16 B for A and for B per thread
-  u32x4 ra[2], rb[2];
-  int a_row[2], a_col[2], b_src[2];
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int c = tid + 256 * r;
-    a_row[r] = c >> 2;
-    a_col[r] = (c & 3) * 8;
-    const int br = c >> 2;
-    b_src[r] = SWIGLU ? (br < 64 ? n0 + br : f + n0 + (br - 64)) : n0 + br;
-  }
-#define GLOAD(k0)                                                                     \
-  _Pragma("unroll") for (int r = 0; r < 2; ++r) {                                     \
-    if (a_row[r] < rows)                                                              \
-      ra[r] = *(const u32x4*)(A + (size_t)(row0 + a_row[r]) * K + (k0) + a_col[r]);   \
-    else                                                                              \
-      ra[r] = u32x4{0u, 0u, 0u, 0u};                                                   \
-    rb[r] = *(const u32x4*)(Be + (size_t)b_src[r] * K + (k0) + a_col[r]);             \
-  }
-#define SSTORE()                                                    \
-  _Pragma("unroll") for (int r = 0; r < 2; ++r) {                    \
-    *(u32x4*)(As + a_row[r] * LDK + a_col[r]) = ra[r];               \
-    *(u32x4*)(Bs + a_row[r] * LDK + a_col[r]) = rb[r];               \
-  }
-
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
-
-  // B-row base of the wavefront's two column tiles
-  const int bro0 = SWIGLU ? wn * 32 : wn * 64;
-  const int bro1 = SWIGLU ? 64 + wn * 32 : wn * 64 + 32;
-  const int fr = lane & 31, fk = (lane >> 5) * 8;
-
-  GLOAD(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    SSTORE();
-    __syncthreads();
-    if (k0 + BK < K) { GLOAD(k0 + BK); }
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 16) {
-      bf16x8 af[2], bfr[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        af[i] = *(const bf16x8*)(As + (wm * 64 + i * 32 + fr) * LDK + ks + fk);
-      bfr[0] = *(const bf16x8*)(Bs + (bro0 + fr) * LDK + ks + fk);
-      bfr[1] = *(const bf16x8*)(Bs + (bro1 + fr) * LDK + ks + fk);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
-  }
-#undef GLOAD
-#undef SSTORE
-
-  // epilogue: lane holds column fr, rows (q/4)*8 + (lane/32)*4 + q%4
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int rl = wm * 64 + i * 32 + (q >> 2) * 8 + (lane >> 5) * 4 + (q & 3);
-      if (rl >= rows) continue;
-      const size_t row = (size_t)(row0 + rl);
-      if (SWIGLU) {
-        const float a = acc[i][0][q], b = acc[i][1][q];
-        C[row * Ncols + n0 + wn * 32 + fr] = (bf16_t)(silu(a) * b);
-      } else {
-        C[row * Ncols + n0 + wn * 64 + fr] = (bf16_t)acc[i][0][q];
-        C[row * Ncols + n0 + wn * 64 + 32 + fr] = (bf16_t)acc[i][1][q];
-      }
-    }
-  }
-}
 
 // ------------------------------------------------------- BF16 MFMA, 256x128
 // Macro tile 256 token rows x 128 weight rows, 4 wavefronts (2 x 2) each
@@ -1355,13 +1248,10 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
                        G2);
     PROF_END("gemm2", st);
   } else if (bf16path) {
-    // 256-row tiles where the shape allows them, 128-row tiles otherwise
-    const bool big1 = c.d_ff % 64 == 0 && c.d % GBK == 0;
-    const bool big2 = c.d % 128 == 0 && c.d_ff % GBK == 0;
-    if (big1 || big2)
-      hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
-    if (!big1 || !big2)
-      hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, BM, w.tile_start);
+    // 256-row tiles (d_ff % 64 == 0 and d % 128 == 0 were checked above):
+    // 256 x 256 where d_ff % 128 (GEMM 1) or d % 256 (GEMM 2) allows it,
+    // 256 x 128 otherwise
+    hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
     const int mt_big = (N + GBM - 1) / GBM + c.E;
     PROF_BEGIN("gemm1_swiglu", st);
     if (c.d_ff % 128 == 0 && c.d % XBK == 0) {
@@ -1371,17 +1261,12 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
                          dim3(64 * XW), 0, st, (const bf16_t*)X_perm, nullptr, 0,
                          (const bf16_t*)W13, (bf16_t*)w.h, offsets, w.tile_start_big, c.E, N, c.d,
                          c.d_ff, c.d_ff, nt, G);
-    } else if (big1) {
+    } else {
       const int nt = c.d_ff / 64;
       const int G = (mt_big * nt + 7) / 8 * 8;
       hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_SWIGLU, false>), dim3(G), dim3(256), 0,
                          st, (const bf16_t*)X_perm, nullptr, 0, (const bf16_t*)W13, (bf16_t*)w.h,
                          offsets, w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt, G);
-    } else {
-      dim3 g1((N + BM - 1) / BM + c.E, c.d_ff / 64);
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16<true>), g1, dim3(256), 0, st,
-                         (const bf16_t*)X_perm, (const bf16_t*)W13, (bf16_t*)w.h, offsets,
-                         w.tile_start, c.E, N, c.d, c.d_ff, c.d_ff);
     }
     PROF_END("gemm1_swiglu", st);
     PROF_BEGIN("gemm2", st);
@@ -1392,17 +1277,12 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
                          dim3(64 * XW), 0, st, (const bf16_t*)w.h, nullptr, 0, (const bf16_t*)W2,
                          (bf16_t*)Y, offsets, w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt,
                          G);
-    } else if (big2) {
+    } else {
       const int nt = c.d / 128;
       const int G = (mt_big * nt + 7) / 8 * 8;
       hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_PLAIN, false>), dim3(G), dim3(256), 0,
                          st, (const bf16_t*)w.h, nullptr, 0, (const bf16_t*)W2, (bf16_t*)Y, offsets,
                          w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt, G);
-    } else {
-      dim3 g2((N + BM - 1) / BM + c.E, c.d / 128);
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16<false>), g2, dim3(256), 0, st,
-                         (const bf16_t*)w.h, (const bf16_t*)W2, (bf16_t*)Y, offsets, w.tile_start,
-                         c.E, N, c.d_ff, c.d_ff, c.d);
     }
     PROF_END("gemm2", st);
   } else {

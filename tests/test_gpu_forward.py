@@ -132,6 +132,13 @@ def test_layer_forward_fp32_small_config():
     _layer_check(synth.SHAPES[1], 1, 1e-5)
 
 
+def test_layer_forward_fp32_unaligned_widths():
+    """FP32 layer with d and d_ff that fill no tile (d = 72, d_ff = 40):
+    the guarded FP32 kernels against the FP64 oracle."""
+    shape = synth.MoEShape("fp32-odd", T=300, d=72, E=6, k=2, f=40, zipf=1.1, act="f32", w="f32")
+    _layer_check(shape, 41, 1e-5)
+
+
 def test_layer_forward_bf16_ragged():
     _layer_check(MID, 18, 1.5e-2)
 
