@@ -20,6 +20,10 @@ pytestmark = pytest.mark.gpu
 # d % 256 == 0 and f % 128 == 0 (the backward GEMM tiling); ragged experts
 BWD = synth.MoEShape("bf16-bwd", T=1500, d=256, E=8, k=2, f=256, zipf=1.2, act="bf16", w="bf16")
 BWD2 = synth.MoEShape("bf16-bwd-k4", T=1100, d=512, E=16, k=4, f=384, zipf=1.3, act="bf16", w="bf16")
+# top-1 over an odd number of experts (the gate gradient vanishes: one
+# softmax weight is identically 1) and top-3 over seven experts
+BWD_K1 = synth.MoEShape("bf16-bwd-k1", T=333, d=256, E=5, k=1, f=128, zipf=1.1, act="bf16", w="bf16")
+BWD_K3 = synth.MoEShape("bf16-bwd-k3", T=250, d=256, E=7, k=3, f=256, zipf=1.2, act="bf16", w="bf16")
 
 
 def _setup(shape, config):
@@ -32,7 +36,7 @@ def _setup(shape, config):
     return cfg, d, h, fw, dOut
 
 
-@pytest.mark.parametrize("shape,config", [(BWD, 31), (BWD2, 32)])
+@pytest.mark.parametrize("shape,config", [(BWD, 31), (BWD2, 32), (BWD_K1, 34), (BWD_K3, 35)])
 def test_backward_pieces_match_oracle(shape, config):
     cfg, d, h, fw, dOut = _setup(shape, config)
     dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
@@ -61,6 +65,11 @@ def test_backward_pieces_match_oracle(shape, config):
     assert rel_fro(dW13.cpu().numpy(), ref["dW13"]) <= 2e-2
     assert rel_fro(dW2.cpu().numpy(), ref["dW2"]) <= 2e-2
     assert rel_fro(dX.cpu().numpy(), ref["dX"]) <= 2e-2
+    if shape.k == 1:
+        # a single softmax weight is 1 whatever the logit: no router gradient
+        assert np.abs(ref["dWr"]).max() == 0.0 and np.abs(ref["dbr"]).max() == 0.0
+        assert np.abs(dWr.cpu().numpy()).max() == 0.0 and np.abs(dbr.cpu().numpy()).max() == 0.0
+        return
     assert rel_fro(dWr.cpu().numpy(), ref["dWr"]) <= 2e-2
     assert rel_fro(dbr.cpu().numpy(), ref["dbr"]) <= 2e-2
 
