@@ -48,9 +48,17 @@ STATS_CASES = [(1000, 64, 8, None, 51), (333, 40, 3, None, 52), (50, 5, 4, None,
                (65, 3, 2, 70, 57)]
 
 
+@pytest.mark.parametrize("tied", [False, True])
 @pytest.mark.parametrize("T,E,k,C,seed", STATS_CASES)
-def test_logit_stats_match_oracle(T, E, k, C, seed):
+def test_logit_stats_match_oracle(T, E, k, C, seed, tied):
+    """tied: logits on a 0.25 grid, so the plain top-k behind f4 meets equal
+    keys (broken towards the lower expert)."""
     s, sd = _logits(T, E, seed)
+    if tied:
+        # + 0.0 turns the -0.0 that rounding leaves into +0.0 (float order
+        # and key order then agree on the grid)
+        s = (np.round(s * 4.0) / 4.0 + 0.0).astype(np.float32)
+        sd = torch.from_numpy(s).cuda()
     cfg = _cfg(T, E, k, C)
     feats, sigma = P.logit_stats(cfg, sd)
     torch.cuda.synchronize()
@@ -180,7 +188,7 @@ def test_route_logits_bit_exact_at_shape_limits(T, E, k, seed):
 # register-cached ranking (E = 64) and the chunked one (E = 200)
 @pytest.mark.parametrize("T,E,k,seed", [(1000, 64, 8, 84), (600, 200, 6, 85)])
 def test_route_logits_bit_exact_with_tied_logits(T, E, k, seed):
-    s = (np.round(synth.make_logits(T, E, 1.2, seed) * 4.0) / 4.0).astype(np.float32)
+    s = (np.round(synth.make_logits(T, E, 1.2, seed) * 4.0) / 4.0 + 0.0).astype(np.float32)
     sd = torch.from_numpy(s).cuda()
     cfg = _cfg(T, E, k)
     r = P.route_logits(cfg, sd)
