@@ -30,6 +30,8 @@ import math
 import numpy as np
 import scipy.special
 
+from .routing import f32_key
+
 H = 256
 NF = 8
 SIZES = [("W1", (H, NF)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("w3", (H,)), ("b3", (1,))]
@@ -125,13 +127,18 @@ def _qdesc(col: np.ndarray, r: int) -> float:
 
 
 def features(s, k, C):
-    """The eight per-expert statistics [E,8] of logits s (FP64)."""
+    """The eight per-expert statistics [E,8] of FP32 logits s (computed in
+    FP64).  The plain top-k behind kappa and load0 ranks each token's
+    experts by the total-order key of the FP32 logit, descending, ties to
+    the lower expert (the ranking rule of the price update), so -0.0 ranks
+    below +0.0."""
+    key = f32_key(np.asarray(s, np.float32)).astype(np.int64)
     s = np.asarray(s, np.float64)
     T, E = s.shape
     mu = s.mean()
     sig = s.std()
     sig = sig if sig > 0 else 1.0
-    order = np.argsort(-s, axis=1, kind="stable")
+    order = np.lexsort((np.broadcast_to(np.arange(E), (T, E)), -key), axis=1)
     rows = np.arange(T)
     kap1 = s[rows, order[:, k - 1]]
     kap2 = s[rows, order[:, k]] if k < E else np.full(T, -np.inf)

@@ -55,9 +55,8 @@ def test_logit_stats_match_oracle(T, E, k, C, seed, tied):
     keys (broken towards the lower expert)."""
     s, sd = _logits(T, E, seed)
     if tied:
-        # + 0.0 turns the -0.0 that rounding leaves into +0.0 (float order
-        # and key order then agree on the grid)
-        s = (np.round(s * 4.0) / 4.0 + 0.0).astype(np.float32)
+        # rounding also leaves -0.0 next to +0.0: the key order ranks it lower
+        s = (np.round(s * 4.0) / 4.0).astype(np.float32)
         sd = torch.from_numpy(s).cuda()
     cfg = _cfg(T, E, k, C)
     feats, sigma = P.logit_stats(cfg, sd)
@@ -188,7 +187,7 @@ def test_route_logits_bit_exact_at_shape_limits(T, E, k, seed):
 # register-cached ranking (E = 64) and the chunked one (E = 200)
 @pytest.mark.parametrize("T,E,k,seed", [(1000, 64, 8, 84), (600, 200, 6, 85)])
 def test_route_logits_bit_exact_with_tied_logits(T, E, k, seed):
-    s = (np.round(synth.make_logits(T, E, 1.2, seed) * 4.0) / 4.0 + 0.0).astype(np.float32)
+    s = (np.round(synth.make_logits(T, E, 1.2, seed) * 4.0) / 4.0).astype(np.float32)
     sd = torch.from_numpy(s).cuda()
     cfg = _cfg(T, E, k)
     r = P.route_logits(cfg, sd)

@@ -316,3 +316,23 @@ def test_feature_seven_is_the_first_clearing_price():
     p1 = r1["p"].astype(np.float64)
     np.testing.assert_allclose(Fm[over, 6] * sig, p1[over] - float(r1["eps"]), rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(Fm[:, 4] * C, R.acp_prices(s, k, C, max_iters=0)["load"])
+
+
+def test_feature_loads_follow_the_ranking_rule_on_ties():
+    """On logits with exact ties and signed zeros, the zero-price loads behind
+    f4 are those of a brute-force ranking by (total-order key desc, expert
+    asc), and those of the routing oracle's first ranking."""
+    rng = np.random.default_rng(17)
+    T, E, k = 40, 6, 2
+    s = (np.round(rng.standard_normal((T, E)) * 2.0) / 2.0).astype(np.float32)
+    s[0, :2] = [-0.0, 0.0]
+    s[1, :3] = [0.0, -0.0, 0.0]
+    C = synth.capacity(T, k, E)
+    Fm = mlp.features(s, k, C)
+    key = R.f32_key(s)
+    load = np.zeros(E, np.int64)
+    for t in range(T):
+        for _, e in sorted((-int(key[t, e]), e) for e in range(E))[:k]:
+            load[e] += 1
+    np.testing.assert_array_equal(np.rint(Fm[:, 4] * C).astype(np.int64), load)
+    np.testing.assert_array_equal(load, R.acp_prices(s, k, C, max_iters=0)["load"])
