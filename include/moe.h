@@ -362,8 +362,10 @@ moe_status moe_dispatch_bwd(const moe_cfg* cfg, const void* dX_perm, const int32
  *   ds[t,j] = w[t,j] (dw[t,j] - sum_i w[t,i] dw[t,i])   (softmax over the
  *             chosen experts' raw logits; dw = dtopk_w)
  *   dX[t]   = sum_j dX_perm[inv_map[t,j]] + sum_j ds[t,j] W_r[e_j]   (f32 out)
- *   dWr[e]  = sum over the slots of e, in slot order, of ds * X[t]   [E,d] f32
+ *   dWr[e]  = sum over the slots of e of ds * X[t]                    [E,d] f32
  *   dbr[e]  = sum of the same ds                                      [E] f32
+ *   (the sums run over chunks of 64 slots in slot order, whose partial
+ *   sums are added in a fixed order: the result is deterministic)
  *   (topk_idx, topk_w, row_map, offsets, inv_map as produced by the forward.)
  */
 moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const float* Wr,

@@ -110,27 +110,78 @@ __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
   }
 }
 
-// dW_r[e, c] = sum over the slots r of expert e (slot order) of
-// ds(slot) * X[row_map[r], c];  db_r[e] = sum of ds(slot).  Block = (expert,
-// 256 columns); each thread owns one column and walks the expert's slots.
+// dW_r[e, c] = sum over the slots r of expert e of ds(slot) * X[row_map[r], c]
+// and db_r[e] = sum of ds(slot), in two passes.  Pass 1: block (expert, 256
+// columns, q) sums the chunks q, q + nq, q + 2 nq, ... of RW_CH slots of
+// the expert (slot order inside a chunk, chunks in increasing order); the
+// chunk's ds values and token rows are staged in LDS once, so the X loads
+// of a chunk are independent.  Pass 2 adds the nq partial sums of each
+// (expert, column) in q order.  Both orders are fixed: the result is
+// deterministic.
+constexpr int RW_CH = 64;
+
+int rw_nq(const moe_cfg& c) {
+  // at most 32 partial sums per (expert, column), and at most 64 MB of them
+  const size_t per = (size_t)c.E * (size_t)c.d * sizeof(float);
+  const size_t cap = ((size_t)64 << 20) / (per > 0 ? per : 1);
+  return (int)(cap < 1 ? 1 : (cap > 32 ? 32 : cap));
+}
+
 template <typename TA>
-__global__ __launch_bounds__(256) void router_wgrad_kernel(
+__global__ __launch_bounds__(256) void router_wgrad_partial(
     const TA* __restrict__ X, int T, int d, int k, int E, const int32_t* __restrict__ row_map,
     const int32_t* __restrict__ offsets, const int32_t* __restrict__ slot_src,
-    const float* __restrict__ ds_tk, float* __restrict__ dWr, float* __restrict__ dbr) {
-  const int e = blockIdx.x;
-  const int c = blockIdx.y * 256 + threadIdx.x;
+    const float* __restrict__ ds_tk, int nq, float* __restrict__ part, float* __restrict__ partb) {
+  __shared__ float sg[RW_CH];
+  __shared__ int st[RW_CH];
+  const int e = blockIdx.x, q = blockIdx.z, tid = threadIdx.x;
+  const int c = blockIdx.y * 256 + tid;
   const int N = T * k;
   const int r0 = clampi(offsets[e], 0, N), r1 = clampi(offsets[e + 1], r0, N);
   float acc = 0.0f, accb = 0.0f;
-  for (int r = r0; r < r1; ++r) {
-    const float g = ds_tk[clampi(slot_src[r], 0, N - 1)];
-    const int t = clampi(row_map[r], 0, T - 1);
-    if (c < d) acc = __builtin_fmaf(g, ActIO<TA>::ld(X, (size_t)t * d + c), acc);
-    accb = accb + g;
+  for (int lo = r0 + q * RW_CH; lo < r1; lo += nq * RW_CH) {  // uniform over the block
+    const int n = min(RW_CH, r1 - lo);
+    __syncthreads();  // the previous chunk's LDS reads are done
+    if (tid < RW_CH) {
+      float g = 0.0f;
+      int t = 0;
+      if (tid < n) {
+        g = ds_tk[clampi(slot_src[lo + tid], 0, N - 1)];
+        t = clampi(row_map[lo + tid], 0, T - 1);
+      }
+      sg[tid] = g;
+      st[tid] = t;
+    }
+    __syncthreads();
+    if (c < d) {
+#pragma unroll 8
+      for (int i = 0; i < n; ++i)
+        acc = __builtin_fmaf(sg[i], ActIO<TA>::ld(X, (size_t)st[i] * d + c), acc);
+    }
+    if (tid == 0)
+      for (int i = 0; i < n; ++i) accb = accb + sg[i];
   }
-  if (c < d) dWr[(size_t)e * d + c] = acc;
-  if (blockIdx.y == 0 && threadIdx.x == 0) dbr[e] = accb;
+  if (c < d) part[((size_t)q * E + e) * d + c] = acc;
+  if (blockIdx.y == 0 && tid == 0) partb[(size_t)q * E + e] = accb;
+}
+
+__global__ __launch_bounds__(256) void router_wgrad_reduce(const float* __restrict__ part,
+                                                           const float* __restrict__ partb,
+                                                           int E, int d, int nq,
+                                                           float* __restrict__ dWr,
+                                                           float* __restrict__ dbr) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t Ed = (size_t)E * d;
+  if (i < Ed) {
+    float acc = 0.0f;
+    for (int q = 0; q < nq; ++q) acc = acc + part[(size_t)q * Ed + i];
+    dWr[i] = acc;
+  }
+  if (i < (size_t)E) {
+    float acc = 0.0f;
+    for (int q = 0; q < nq; ++q) acc = acc + partb[(size_t)q * E + i];
+    dbr[i] = acc;
+  }
 }
 
 // slot_src[inv_map[t,j]] = t*k + j: the (token, choice) behind each slot.
@@ -143,14 +194,19 @@ __global__ __launch_bounds__(256) void slot_source(const int32_t* __restrict__ i
 struct RouteBwdWs {
   int32_t* slot_src;
   float* ds;
+  float* part;   // [nq][E][d] partial sums of dW_r
+  float* partb;  // [nq][E] partial sums of db_r
 };
 
 RouteBwdWs carve_route_bwd(const moe_cfg& c, void* base, size_t* total) {
   WsCarve wc{(char*)base, 0};
   RouteBwdWs r;
   const size_t N = (size_t)c.T * c.k;
+  const size_t nq = (size_t)rw_nq(c);
   r.slot_src = wc.take<int32_t>(N > 0 ? N : 1);
   r.ds = wc.take<float>(N > 0 ? N : 1);
+  r.part = wc.take<float>(nq * c.E * c.d);
+  r.partb = wc.take<float>(nq * c.E);
   if (total) *total = align_up(wc.off, 256);
   return r;
 }
@@ -245,15 +301,19 @@ extern "C" moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const flo
                          dim3(256), 0, st, (const bf16_t*)dX_perm, c.T, c.d, c.k, c.E, inv_map,
                          topk_idx, topk_w, dtopk_w, Wr, dX, w.ds);
   }
-  dim3 g(c.E, (c.d + 255) / 256);
+  const int nq = rw_nq(c);
+  dim3 g(c.E, (c.d + 255) / 256, nq);
   if (c.act == MOE_F32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_wgrad_kernel<float>), g, dim3(256), 0, st,
-                       (const float*)X, c.T, c.d, c.k, c.E, row_map, offsets, w.slot_src, w.ds, dWr,
-                       dbr);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_wgrad_partial<float>), g, dim3(256), 0, st,
+                       (const float*)X, c.T, c.d, c.k, c.E, row_map, offsets, w.slot_src, w.ds, nq,
+                       w.part, w.partb);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_wgrad_kernel<bf16_t>), g, dim3(256), 0, st,
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_wgrad_partial<bf16_t>), g, dim3(256), 0, st,
                        (const bf16_t*)X, c.T, c.d, c.k, c.E, row_map, offsets, w.slot_src, w.ds,
-                       dWr, dbr);
+                       nq, w.part, w.partb);
+  const size_t Ed = (size_t)c.E * c.d;
+  hipLaunchKernelGGL(router_wgrad_reduce, dim3((unsigned)((Ed + 255) / 256)), dim3(256), 0, st,
+                     w.part, w.partb, c.E, c.d, nq, dWr, dbr);
   PROF_END("route_bwd", st);
   MOE_LAUNCH_CHECK();
   return MOE_OK;
