@@ -138,18 +138,24 @@ __global__ __launch_bounds__(256) void router_split(const float* __restrict__ Wr
   W3[2 * n + i] = (bf16_t)r2;
 }
 
-// Block: 128 tokens (32 per wavefront) x 64 experts, K step 32.  The three
-// weight planes of the block's experts go through LDS; each wavefront reads
-// its own token fragments straight from HBM.
-constexpr int RLDK = 32 + 8;
-
+// Block: 128 tokens (32 per wavefront) x 64 experts, K step KS (32, or 128
+// when d % 128 == 0: four times fewer steps, each with four times the
+// MFMAs behind the next step's loads).  The three weight planes of the
+// block's experts go through LDS; each wavefront reads its own token
+// fragments straight from HBM.  Every product is exact in FP32 and the
+// accumulation runs plane by plane within each K step.
+template <int KS>
 __global__ __launch_bounds__(256) void router_logits_mfma(const bf16_t* __restrict__ X,
                                                           const bf16_t* __restrict__ W3,
                                                           const float* __restrict__ br,
                                                           float* __restrict__ s,
                                                           float* __restrict__ sT, int T, int d,
                                                           int E) {
-  __shared__ __attribute__((aligned(16))) bf16_t Ws[3 * 64 * RLDK];
+  constexpr int LDK = KS + 8;
+  constexpr int CPR = KS / 8;               // 16-byte chunks per weight row and step
+  constexpr int WCH = 3 * 64 * CPR / 256;   // chunks per thread
+  constexpr int KSUB = KS / 16;             // MFMA K steps per K step
+  __shared__ __attribute__((aligned(16))) bf16_t Ws[3 * 64 * LDK];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int t0 = blockIdx.x * 128 + wv * 32;
   const int e0 = blockIdx.y * 64;
@@ -158,47 +164,47 @@ __global__ __launch_bounds__(256) void router_logits_mfma(const bf16_t* __restri
   const int trow = t0 + fr;
   const bf16_t* xr = X + (size_t)min(trow, T - 1) * d + fk;
   const bool tvalid = trow < T;
-  // weight tile chunks: 3 planes x 64 rows x 4 chunks of 16 B = 768
-  int wrow[3], wcol[3], wpl[3];
-  bool wok[3];
+  int wrow[WCH], wcol[WCH], wpl[WCH];
+  bool wok[WCH];
 #pragma unroll
-  for (int r = 0; r < 3; ++r) {
+  for (int r = 0; r < WCH; ++r) {
     const int c = tid + 256 * r;
-    wpl[r] = c / 256;
-    wrow[r] = (c % 256) >> 2;
-    wcol[r] = (c & 3) * 8;
+    wpl[r] = c / (64 * CPR);
+    wrow[r] = (c % (64 * CPR)) / CPR;
+    wcol[r] = (c % CPR) * 8;
     wok[r] = e0 + wrow[r] < E;
   }
-  u32x4 wreg[3];
-  bf16x8 xa0, xa1;
+  u32x4 wreg[WCH];
+  bf16x8 xa[KSUB];
 #define RLOAD(k0)                                                                         \
-  _Pragma("unroll") for (int r = 0; r < 3; ++r) wreg[r] =                                 \
+  _Pragma("unroll") for (int r = 0; r < WCH; ++r) wreg[r] =                               \
       wok[r] ? *(const u32x4*)(W3 + wpl[r] * plane + (size_t)(e0 + wrow[r]) * d + (k0) +  \
                                wcol[r])                                                   \
              : u32x4{0u, 0u, 0u, 0u};                                                     \
-  xa0 = *(const bf16x8*)(xr + (k0));                                                      \
-  xa1 = *(const bf16x8*)(xr + (k0) + 16);
+  _Pragma("unroll") for (int u = 0; u < KSUB; ++u) xa[u] = *(const bf16x8*)(xr + (k0) + 16 * u);
   f32x16 acc[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j)
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[j][q] = 0.0f;
   RLOAD(0);
-  for (int k0 = 0; k0 < d; k0 += 32) {
+  for (int k0 = 0; k0 < d; k0 += KS) {
 #pragma unroll
-    for (int r = 0; r < 3; ++r) *(u32x4*)(Ws + (wpl[r] * 64 + wrow[r]) * RLDK + wcol[r]) = wreg[r];
-    const bf16x8 x0 = tvalid ? xa0 : bf16x8{}, x1 = tvalid ? xa1 : bf16x8{};
+    for (int r = 0; r < WCH; ++r) *(u32x4*)(Ws + (wpl[r] * 64 + wrow[r]) * LDK + wcol[r]) = wreg[r];
+    bf16x8 x[KSUB];
+#pragma unroll
+    for (int u = 0; u < KSUB; ++u) x[u] = tvalid ? xa[u] : bf16x8{};
     __syncthreads();
-    if (k0 + 32 < d) { RLOAD(k0 + 32); }
+    if (k0 + KS < d) { RLOAD(k0 + KS); }
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int pl = 0; pl < 3; ++pl) {
-        const bf16x8 w0 = *(const bf16x8*)(Ws + (pl * 64 + j * 32 + fr) * RLDK + fk);
-        const bf16x8 w1 = *(const bf16x8*)(Ws + (pl * 64 + j * 32 + fr) * RLDK + 16 + fk);
-        acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, x0, acc[j], 0, 0, 0);
-        acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, x1, acc[j], 0, 0, 0);
-      }
+      for (int pl = 0; pl < 3; ++pl)
+#pragma unroll
+        for (int u = 0; u < KSUB; ++u) {
+          const bf16x8 w = *(const bf16x8*)(Ws + (pl * 64 + j * 32 + fr) * LDK + 16 * u + fk);
+          acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x[u], acc[j], 0, 0, 0);
+        }
     __syncthreads();
   }
 #undef RLOAD
@@ -1127,8 +1133,13 @@ extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* 
   else {
     const int n = c.E * c.d;
     hipLaunchKernelGGL(router_split, dim3((n + 255) / 256), dim3(256), 0, st, Wr, n, w.W3);
-    hipLaunchKernelGGL(router_logits_mfma, dim3((c.T + 127) / 128, (c.E + 63) / 64), dim3(256), 0,
-                       st, (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+    const dim3 g((c.T + 127) / 128, (c.E + 63) / 64);
+    if (c.d % 128 == 0)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<128>), g, dim3(256), 0, st,
+                         (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<32>), g, dim3(256), 0, st,
+                         (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
   }
   PROF_END("router_logits", st);
   return route_from_scores(c, w, logits, price, topk_idx, topk_w, load, info, st);
