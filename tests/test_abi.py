@@ -125,3 +125,23 @@ def test_entry_points_reject_bad_arguments_on_the_host():
     with pytest.raises(L.MoEError) as e:
         L.moe_price_update(cfg, None, fake, fake, fake, 1 << 30, None)
     assert e.value.status == L.MOE_EINVAL
+
+
+def test_missing_library_fails_loudly():
+    """Without libmoe.so the binding raises on first use (no CPU fallback)."""
+    import subprocess
+    import sys
+    code = ("import paper_2606_17065_amd._lib as L\n"
+            "L.LIB_PATH = '/nonexistent/libmoe.so'\n"
+            "L._lib = None\n"
+            "try:\n"
+            "    L.moe_workspace_bytes(L.make_cfg(8, 8, 2, 1, 8, 8, 1, L.MOE_F32, L.MOE_F32,"
+            " L.MOE_PRICE_ACP))\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    raise SystemExit('no error')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "missing" in r.stdout
