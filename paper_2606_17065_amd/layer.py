@@ -46,6 +46,15 @@ class Workspace:
 _WS = Workspace()
 
 
+def _fresh_price(cfg, dev):
+    """Price buffer when the caller gives none: the clearing-price and the
+    no-price modes start from p = 0 inside the routing kernels, so the
+    buffer needs no fill; given and warm-started prices read it (zeros)."""
+    if cfg.price_mode in (L.MOE_PRICE_ACP, L.MOE_PRICE_NONE):
+        return torch.empty(cfg.E, dtype=torch.float32, device=dev)
+    return torch.zeros(cfg.E, dtype=torch.float32, device=dev)
+
+
 def route(cfg, X, Wr, br, price=None, ws=None):
     T, d, E, k = cfg.T, cfg.d, cfg.E, cfg.k
     _need(X, "X", _DT[cfg.act], (T, d))
@@ -53,15 +62,16 @@ def route(cfg, X, Wr, br, price=None, ws=None):
     _need(br, "br", torch.float32, (E,))
     dev = X.device
     if price is None:
-        price = torch.zeros(E, dtype=torch.float32, device=dev)
+        price = _fresh_price(cfg, dev)
     else:
         _need(price, "price", torch.float32, (E,))
+    # info is written in full by the routing kernels
     out = dict(
         logits=torch.empty(T, E, dtype=torch.float32, device=dev), price=price,
         idx=torch.empty(T, k, dtype=torch.int32, device=dev),
         w=torch.empty(T, k, dtype=torch.float32, device=dev),
         load=torch.empty(E, dtype=torch.int32, device=dev),
-        info=torch.zeros(L.INFO_LEN, dtype=torch.int32, device=dev))
+        info=torch.empty(L.INFO_LEN, dtype=torch.int32, device=dev))
     ws = _WS.get(cfg, dev) if ws is None else ws
     L.moe_route(cfg, _p(X), _p(Wr), _p(br), _p(out["logits"]), _p(price), _p(out["idx"]),
                 _p(out["w"]), _p(out["load"]), _p(out["info"]), _p(ws), ws.numel(), _stream())

@@ -14,7 +14,7 @@ import dataclasses
 import torch
 
 from . import _lib as L
-from .layer import _WS, _need, _p, _stream
+from .layer import _WS, _fresh_price, _need, _p, _stream
 
 GAP_TOL = 5e-3  # relative duality gap the judge accepts (the update's own level)
 
@@ -25,13 +25,13 @@ def route_logits(cfg, logits, price=None, ws=None):
     _need(logits, "logits", torch.float32, (T, E))
     dev = logits.device
     if price is None:
-        price = torch.zeros(E, dtype=torch.float32, device=dev)
+        price = _fresh_price(cfg, dev)
     else:
         _need(price, "price", torch.float32, (E,))
     out = dict(price=price, idx=torch.empty(T, k, dtype=torch.int32, device=dev),
                w=torch.empty(T, k, dtype=torch.float32, device=dev),
                load=torch.empty(E, dtype=torch.int32, device=dev),
-               info=torch.zeros(L.INFO_LEN, dtype=torch.int32, device=dev))
+               info=torch.empty(L.INFO_LEN, dtype=torch.int32, device=dev))
     ws = _WS.get(cfg, dev) if ws is None else ws
     L.moe_route_logits(cfg, _p(logits), _p(price), _p(out["idx"]), _p(out["w"]), _p(out["load"]),
                        _p(out["info"]), _p(ws), ws.numel(), _stream())
@@ -43,10 +43,10 @@ def price_update(cfg, logits, price=None, ws=None):
     _need(logits, "logits", torch.float32, (cfg.T, cfg.E))
     dev = logits.device
     if price is None:
-        price = torch.zeros(cfg.E, dtype=torch.float32, device=dev)
+        price = _fresh_price(cfg, dev)
     else:
         _need(price, "price", torch.float32, (cfg.E,))
-    info = torch.zeros(L.INFO_LEN, dtype=torch.int32, device=dev)
+    info = torch.empty(L.INFO_LEN, dtype=torch.int32, device=dev)
     ws = _WS.get(cfg, dev) if ws is None else ws
     L.moe_price_update(cfg, _p(logits), _p(price), _p(info), _p(ws), ws.numel(), _stream())
     return price, info
