@@ -344,19 +344,18 @@ __device__ __forceinline__ uint64_t pick(const uint64_t (&v)[L], int j) {
 __device__ __forceinline__ int key_expert(uint64_t v) { return (int)(0xFFFFFFFFu - (uint32_t)v); }
 
 // One ranking pass of the price loop.  A block owns TG groups of 64 tokens
-// (one token per lane) and splits the experts into four contiguous ranges,
+// (one token per lane) and splits the experts into RW contiguous ranges,
 // one wavefront per (token group, range); each wavefront keeps its logits
 // in registers and builds a partial top-L list per token.  One wavefront
-// per token group merges the four sorted lists (k+1 steps) and writes the
+// per token group merges the RW sorted lists (k+1 steps) and writes the
 // routing for the current prices; then every wavefront writes the margin
 // keys mT[e][t] of its experts.  The block's per-expert counts go to row
 // blockIdx.x of cnt[nblk][E] (no global atomics).
-constexpr int RANK_WAVES = 4;
 
 // Token group of sub-group tg: gbase + tg * gstride (64 tokens each);
 // the block's per-expert counts go to row crow of cnt.  With a state
 // pointer the pass is skipped once the price loop is done.
-template <int L, int NV, int TG>
+template <int L, int NV, int TG, int RW>
 __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
                                           const float* __restrict__ price, int T, int E, int k,
                                           const int32_t* __restrict__ state,
@@ -365,27 +364,29 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
                                           int crow) {
   __shared__ int hist[MOE_MAX_E];
   __shared__ float ps[MOE_MAX_E];
-  __shared__ uint32_t partk[TG][RANK_WAVES][L][64];
-  __shared__ int parte[TG][RANK_WAVES][L][64];
+  __shared__ uint32_t partk[TG][RW][L][64];
+  __shared__ int parte[TG][RW][L][64];
   __shared__ uint32_t kthk_s[TG][64];
   __shared__ int kthe_s[TG][64];
   __shared__ float k1_s[TG][64], k2_s[TG][64];
-  constexpr int NT = 64 * RANK_WAVES * TG;
-  const int tid = threadIdx.x, lane = tid & 63, wv = (tid >> 6) & (RANK_WAVES - 1);
-  const int tg = tid / (64 * RANK_WAVES);
+  constexpr int NT = 64 * RW * TG;
+  const int tid = threadIdx.x, lane = tid & 63, wv = (tid >> 6) & (RW - 1);
+  const int tg = tid / (64 * RW);
   const int t = (gbase + tg * gstride) * 64 + lane;
   const bool valid = t < T;
   const int tl = valid ? t : T - 1;  // out-of-range lanes read a valid row, write nothing
-  const int per = (E + RANK_WAVES - 1) / RANK_WAVES;
+  const int per = (E + RW - 1) / RW;
   const int e_lo = wv * per;
   const int ne = max(0, min(E, e_lo + per) - e_lo);
   const bool cached = ne <= NV;
   // the logits, the prices and the done flag are independent loads: issue
-  // them together so their latencies overlap
+  // them together so their latencies overlap (a wavefront whose expert
+  // range is empty, E < the number of ranges, reads row E - 1 and uses none)
   float sv[NV];
   if (cached) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) sv[i] = sT[(size_t)(e_lo + min(i, max(ne - 1, 0))) * T + tl];
+    for (int i = 0; i < NV; ++i)
+      sv[i] = sT[(size_t)min(e_lo + min(i, max(ne - 1, 0)), E - 1) * T + tl];
   }
   const int done = state ? state[ST_DONE] : 0;
   if (done) return;  // uniform: every thread read the same flag
@@ -402,7 +403,7 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
   if (cached) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const uint32_t key = i < ne ? f32_key(sv[i] - ps[e_lo + min(i, max(ne - 1, 0))]) : 0u;
+      const uint32_t key = i < ne ? f32_key(sv[i] - ps[min(e_lo + i, E - 1)]) : 0u;
       insert_top<L>(V, ((uint64_t)key << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)(e_lo + i)));
     }
   } else {
@@ -424,27 +425,28 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
   }
   __syncthreads();
   if (wv == 0 && valid) {
-    // merge the four sorted lists (k+1 steps); on equal keys the list of
+    // merge the RW sorted lists (k+1 steps); on equal keys the list of
     // the lower expert range wins
-    int h0 = 0, h1 = 0, h2 = 0, h3 = 0;
+    int h[RW];
+#pragma unroll
+    for (int w = 0; w < RW; ++w) h[w] = 0;
     uint32_t kk1 = 0, kk2 = 0;
     int ek1 = 0;
     for (int j = 0; j <= k && j < L; ++j) {
-      const uint32_t c0 = h0 < L ? partk[tg][0][h0][lane] : 0u;
-      const uint32_t c1 = h1 < L ? partk[tg][1][h1][lane] : 0u;
-      const uint32_t c2 = h2 < L ? partk[tg][2][h2][lane] : 0u;
-      const uint32_t c3 = h3 < L ? partk[tg][3][h3][lane] : 0u;
-      int src = 0;
-      uint32_t m = c0;
-      if (c1 > m) { m = c1; src = 1; }
-      if (c2 > m) { m = c2; src = 2; }
-      if (c3 > m) { m = c3; src = 3; }
-      const int hs = src == 0 ? h0 : (src == 1 ? h1 : (src == 2 ? h2 : h3));
+      uint32_t m = 0u;
+      int src = 0, hs = 0;
+#pragma unroll
+      for (int w = 0; w < RW; ++w) {
+        const uint32_t c = h[w] < L ? partk[tg][w][h[w]][lane] : 0u;
+        if (w == 0 || c > m) {
+          m = c;
+          src = w;
+          hs = h[w];
+        }
+      }
       const int ej = parte[tg][src][hs][lane];
-      if (src == 0) ++h0;
-      else if (src == 1) ++h1;
-      else if (src == 2) ++h2;
-      else ++h3;
+#pragma unroll
+      for (int w = 0; w < RW; ++w) h[w] += (w == src) ? 1 : 0;
       if (j < k) {
         idx[(size_t)t * k + j] = ej;
         atomicAdd(&hist[ej], 1);
@@ -490,12 +492,13 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
   for (int e = tid; e < E; e += NT) cnt[(size_t)crow * E + e] = hist[e];
 }
 
-template <int L, int NV, int TG>
-__global__ __launch_bounds__(64 * RANK_WAVES * TG) void acp_rank(
+template <int L, int NV, int TG, int RW>
+__global__ __launch_bounds__(64 * RW * TG) void acp_rank(
     const float* __restrict__ sT, const float* __restrict__ price, int T, int E, int k,
     const int32_t* __restrict__ state, uint32_t* __restrict__ mT, int32_t* __restrict__ idx,
     int32_t* __restrict__ cnt) {
-  rank_pass<L, NV, TG>(sT, price, T, E, k, state, mT, idx, cnt, blockIdx.x * TG, 1, blockIdx.x);
+  rank_pass<L, NV, TG, RW>(sT, price, T, E, k, state, mT, idx, cnt, blockIdx.x * TG, 1,
+                           blockIdx.x);
 }
 
 // Gate weights of the final routing: softmax of the raw logits over each
@@ -1052,20 +1055,26 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
   // T = 16384 (four groups per block left three quarters of the chip idle)
   constexpr int TG = 1;
   const int nblk = (T + 64 * TG - 1) / (64 * TG);
-  const int per = (E + RANK_WAVES - 1) / RANK_WAVES;
+  // eight wavefronts per token group (two per SIMD) for lists of up to 9,
+  // four for the longer lists (their LDS would not fit twice)
+  constexpr int RW = L <= 9 ? 8 : 4;
+  const int per = (E + RW - 1) / RW;
   // one ranking and one update kernel per iteration, each exiting at once
   // after the loop has stopped
   for (int it = 0; it <= max_iters; ++it) {
-    const dim3 rb(64 * RANK_WAVES * TG);
+    const dim3 rb(64 * RW * TG);
     if (per <= 4)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 4, TG>), dim3(nblk), rb, 0, st, ws.sT, price,
-                         T, E, k, ws.state, ws.mT, idx, ws.cnt);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 4, TG, RW>), dim3(nblk), rb, 0, st, ws.sT,
+                         price, T, E, k, ws.state, ws.mT, idx, ws.cnt);
+    else if (per <= 8)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 8, TG, RW>), dim3(nblk), rb, 0, st, ws.sT,
+                         price, T, E, k, ws.state, ws.mT, idx, ws.cnt);
     else if (per <= 16)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 16, TG>), dim3(nblk), rb, 0, st, ws.sT, price,
-                         T, E, k, ws.state, ws.mT, idx, ws.cnt);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 16, TG, RW>), dim3(nblk), rb, 0, st, ws.sT,
+                         price, T, E, k, ws.state, ws.mT, idx, ws.cnt);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 64, TG>), dim3(nblk), rb, 0, st, ws.sT, price,
-                         T, E, k, ws.state, ws.mT, idx, ws.cnt);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 64, TG, RW>), dim3(nblk), rb, 0, st, ws.sT,
+                         price, T, E, k, ws.state, ws.mT, idx, ws.cnt);
     hipLaunchKernelGGL(acp_select, dim3(E), dim3(SEL_THREADS), 0, st, ws.mT, price, T, E, C, it,
                        max_iters, nblk, ws.cnt, ws.state, load);
   }
