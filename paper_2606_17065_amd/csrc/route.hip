@@ -1072,6 +1072,9 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
     else if (per <= 16)
       hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 16, TG, RW>), dim3(nblk), rb, 0, st, ws.sT,
                          price, T, E, k, ws.state, ws.mT, idx, ws.cnt);
+    else if (per <= 32)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 32, TG, RW>), dim3(nblk), rb, 0, st, ws.sT,
+                         price, T, E, k, ws.state, ws.mT, idx, ws.cnt);
     else
       hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 64, TG, RW>), dim3(nblk), rb, 0, st, ws.sT,
                          price, T, E, k, ws.state, ws.mT, idx, ws.cnt);

@@ -184,8 +184,11 @@ def test_route_logits_bit_exact_at_shape_limits(T, E, k, seed):
 
 
 # logits on a grid of 0.25: exact ties between experts everywhere, in the
-# register-cached ranking (E = 64) and the chunked one (E = 200)
-@pytest.mark.parametrize("T,E,k,seed", [(1000, 64, 8, 84), (600, 200, 6, 85)])
+# register-cached ranking (E = 64: 8 experts per wavefront range; E = 200:
+# 25) and the chunked one (E = 600: 75 experts per range, more than the
+# 64 a wavefront keeps in registers)
+@pytest.mark.parametrize("T,E,k,seed", [(1000, 64, 8, 84), (600, 200, 6, 85),
+                                        (500, 600, 6, 86)])
 def test_route_logits_bit_exact_with_tied_logits(T, E, k, seed):
     s = (np.round(synth.make_logits(T, E, 1.2, seed) * 4.0) / 4.0).astype(np.float32)
     sd = torch.from_numpy(s).cuda()
