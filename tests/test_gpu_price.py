@@ -200,6 +200,23 @@ def test_route_logits_bit_exact_with_tied_logits(T, E, k, seed):
     assert_route_matches(cfg, r, ref)
 
 
+# one case per ranking variant the other tests leave out: lists of k + 1
+# = 3, 5, 9 and 17 entries (the longest up to k = 16), eight expert ranges
+# for k <= 8 and four above, and 4, 16, 32 or 64 logits per lane in
+# registers (the range size rounded up)
+@pytest.mark.parametrize("T,E,k,seed", [(500, 6, 2, 97), (700, 20, 4, 91), (700, 400, 8, 92),
+                                        (600, 16, 10, 96), (600, 60, 12, 95),
+                                        (600, 120, 10, 93), (600, 240, 9, 94)])
+def test_route_logits_bit_exact_for_every_ranking_variant(T, E, k, seed):
+    s, sd = _logits(T, E, seed)
+    cfg = _cfg(T, E, k)
+    r = P.route_logits(cfg, sd)
+    torch.cuda.synchronize()
+    ref = replica_route(cfg, s)
+    assert ref["iters"] > 0
+    assert_route_matches(cfg, r, ref)
+
+
 @pytest.mark.parametrize("mode", [L.MOE_PRICE_ACP, L.MOE_PRICE_WARM])
 def test_price_update_alone_matches_route(mode):
     """moe_price_update gives the prices and info of moe_route_logits (and
