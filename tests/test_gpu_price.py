@@ -200,13 +200,19 @@ def test_route_logits_bit_exact_with_tied_logits(T, E, k, seed):
     assert_route_matches(cfg, r, ref)
 
 
-# one case per ranking variant the other tests leave out: lists of k + 1
-# = 3, 5, 9 and 17 entries (the longest up to k = 16), eight expert ranges
-# for k <= 8 and four above, and 4, 16, 32 or 64 logits per lane in
-# registers (the range size rounded up)
-@pytest.mark.parametrize("T,E,k,seed", [(500, 6, 2, 97), (700, 20, 4, 91), (700, 400, 8, 92),
-                                        (600, 16, 10, 96), (600, 60, 12, 95),
-                                        (600, 120, 10, 93), (600, 240, 9, 94)])
+# every instantiation of the ranking kernel: top-k lists padded to 3, 5, 9
+# or 17 entries (k = 2, 4, 8, 10), eight expert ranges for k <= 8 and four
+# above, and each register cache of 4, 8, 16, 32 or 64 logits per lane (the
+# range size rounded up); T = 450 leaves a ragged last token group
+_RANK_E8 = (24, 60, 100, 200, 400)
+_RANK_E4 = (16, 30, 60, 120, 240)
+RANK_VARIANTS = [(450, E, k, 100 + 10 * i + j)
+                 for i, (k, Es) in enumerate(((2, _RANK_E8), (4, _RANK_E8), (8, _RANK_E8),
+                                              (10, _RANK_E4)))
+                 for j, E in enumerate(Es)]
+
+
+@pytest.mark.parametrize("T,E,k,seed", RANK_VARIANTS)
 def test_route_logits_bit_exact_for_every_ranking_variant(T, E, k, seed):
     s, sd = _logits(T, E, seed)
     cfg = _cfg(T, E, k)
