@@ -32,6 +32,18 @@ per operation, no contraction:
       p_e = max(p_e, fl32(nextafter(q, +inf) + eps)).  Other prices stay.
    4. iters += 1, repeat.
 
+Variant rule, epsilon-scaled restarts ("scaled", reading stated here): the
+update above is stage 0.  While the previous stage ended converged with
+some expert priced above zero and below capacity (a nonzero certificate
+gap), and fewer than ``stages`` restarts have run: p = max(0, fl32(p - fl32(4 *
+eps))), eps = fl32(eps / 8), and the update runs again from those prices
+(at most ``max_iters`` updates per stage; a lowered price that is not
+positive becomes +0).  Lowering every price by a few
+increments puts it back below the clearing level that the previous stage
+overshot by up to one increment; the next stage climbs back with a smaller
+increment, so the certificate gap shrinks with each stage.  The iteration
+count reported is the sum over the stages.
+
 The routing returned is S_t of the last ranking, in rank order.  Gate
 weights are the softmax of the raw logits over the k chosen experts.  If the
 final routing still overloads an expert, ``enforce_capacity`` repairs it.
@@ -192,6 +204,39 @@ def acp_prices(s32, k, C, max_iters=50, p0=None, eps=None):
         iters += 1
 
 
+SCALED_BACK = F32(4.0)    # restart: prices lowered by this many increments
+SCALED_SHRINK = F32(8.0)  # and the increment divided by this
+
+
+def _slack_free(p, load, C) -> bool:
+    """Complementary slackness of a feasible top-k routing: every expert with
+    a positive price is full, so the certificate gap is zero (optimal)."""
+    return bool(np.all((p == 0) | (load == C)))
+
+
+def acp_scaled_prices(s32, k, C, max_iters=50, p0=None, eps=None, stages=3):
+    """Epsilon-scaled restarts of the ascending clearing price (module
+    header, "Variant rule").  Returns the dict of ``acp_prices`` for the
+    last stage with ``iters`` summed over the stages and ``stages_run``."""
+    s32 = np.ascontiguousarray(s32, dtype=F32)
+    if eps is None:
+        eps = price_eps(s32)
+    eps = F32(eps)
+    r = acp_prices(s32, k, C, max_iters, p0, eps)
+    total = r["iters"]
+    run = 0
+    while r["converged"] and run < stages and not _slack_free(r["p"], r["load"], C):
+        lowered = (r["p"] - F32(SCALED_BACK * eps)).astype(F32)
+        p = np.where(lowered > F32(0.0), lowered, F32(0.0)).astype(F32)
+        eps = F32(eps / SCALED_SHRINK)
+        r = acp_prices(s32, k, C, max_iters, p, eps)
+        total += r["iters"]
+        run += 1
+    r["iters"] = total
+    r["stages_run"] = run
+    return r
+
+
 def enforce_capacity(s32, p32, sel, k, C):
     """Repair a routing that overloads some expert (reading stated here).
 
@@ -261,12 +306,13 @@ def gate_weights(s: np.ndarray, sel: np.ndarray) -> np.ndarray:
     return ez / ez.sum(axis=1, keepdims=True)
 
 
-def route(s32, k, C, max_iters=50, p0=None, mode="acp"):
+def route(s32, k, C, max_iters=50, p0=None, mode="acp", stages=0):
     """The whole routing step on FP32 logits.
 
     mode: "none" (p = 0, no update), "acp" (from p0 or 0), "given" (p = p0,
-    no update).  Returns dict with sel, w (FP64), load, p, iters, converged,
-    enforced, status, eps, sigma."""
+    no update).  stages > 0 (with "acp") runs the epsilon-scaled restarts
+    after the update.  Returns dict with sel, w (FP64), load, p, iters,
+    converged, enforced, status, eps, sigma."""
     s32 = np.ascontiguousarray(s32, dtype=F32)
     T, E = s32.shape
     res = dict(sel=None, w=None, load=None, p=None, iters=0, converged=False,
@@ -285,7 +331,11 @@ def route(s32, k, C, max_iters=50, p0=None, mode="acp"):
     res["eps"] = eps
     p = np.zeros(E, dtype=F32) if p0 is None else np.array(p0, dtype=F32)
     if mode == "acp":
-        r = acp_prices(s32, k, C, max_iters, p, eps)
+        if stages > 0 and max_iters > 0:
+            r = acp_scaled_prices(s32, k, C, max_iters, p, eps, stages)
+        else:
+            r = acp_prices(s32, k, C, max_iters, p, eps)
+        res["eps"] = r["eps"]  # the increment of the last stage
         p, sel, load = r["p"], r["sel"], r["load"]
         res["iters"], res["converged"] = r["iters"], r["converged"]
     else:
