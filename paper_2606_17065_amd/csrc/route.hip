@@ -502,14 +502,23 @@ __global__ __launch_bounds__(64 * RW * TG) void acp_rank(
 }
 
 // Gate weights of the final routing: softmax of the raw logits over each
-// token's k chosen experts (FP32, max-subtracted).
+// token's k chosen experts (FP32, max-subtracted).  After a non-finite
+// logit no ranking has run: every token gets the defined routing
+// idx[t][j] = j with NaN weights, so that nothing downstream reads
+// unwritten memory and every output the routing feeds is NaN.
 __global__ __launch_bounds__(256) void route_weights(const float* __restrict__ logits,
-                                                     const int32_t* __restrict__ idx, int T, int E,
+                                                     int32_t* __restrict__ idx, int T, int E,
                                                      int k, const int32_t* __restrict__ state,
                                                      float* __restrict__ w) {
-  if (state[ST_STATUS] != MOE_OK) return;
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= T) return;
+  if (state[ST_STATUS] != MOE_OK) {
+    for (int j = 0; j < k; ++j) {
+      idx[(size_t)t * k + j] = j;
+      w[(size_t)t * k + j] = __builtin_nanf("");
+    }
+    return;
+  }
   float z[MOE_MAX_K];
   float mx = -INFINITY;
 #pragma unroll
@@ -955,8 +964,11 @@ __global__ __launch_bounds__(REP_THREADS) void capacity_repair(
     }
   }
   __syncthreads();
+  // the proposal loop leaves only through a round with no short token
+  // (S.flag clear) or through a token with no untried expert (S.flag set)
+  const bool failed = S.flag != 0;
   // 3) rebuild every token's list in rank order, and its gate weights
-  if (state[ST_STATUS] == MOE_OK) {
+  if (!failed) {
     for (int e = tid; e < E; e += bd) S.load[e] = 0;
     __syncthreads();
     for (int t = tid; t < T; t += bd) {
@@ -991,6 +1003,12 @@ __global__ __launch_bounds__(REP_THREADS) void capacity_repair(
     }
     __syncthreads();
     for (int e = tid; e < E; e += bd) load_out[e] = S.load[e];
+  } else {
+    // the repair could not place every slot: idx and load keep the
+    // overloaded routing the price loop ended with, and the weights become
+    // NaN so that no output computed from it passes for a valid one
+    for (int t = tid; t < T; t += bd)
+      for (int j = 0; j < k; ++j) w[(size_t)t * k + j] = __builtin_nanf("");
   }
   if (tid == 0) {
     state[ST_ROUNDS] = rounds;
@@ -998,11 +1016,16 @@ __global__ __launch_bounds__(REP_THREADS) void capacity_repair(
   }
 }
 
-__global__ void route_finalize(const int32_t* state, int32_t* info, int32_t* load_out, int E,
-                               int empty) {
+// info[] from the state words.  An empty batch has zero loads; after a
+// non-finite logit the loads are those of the placeholder routing
+// idx[t][j] = j (T for experts below k, zero above).
+__global__ void route_finalize(const int32_t* state, int32_t* info, int32_t* load_out, int T,
+                               int E, int k, int empty) {
   const int tid = threadIdx.x;
   if (empty)
     for (int e = tid; e < E; e += blockDim.x) load_out[e] = 0;
+  else if (state[ST_STATUS] == MOE_ENAN)
+    for (int e = tid; e < E; e += blockDim.x) load_out[e] = e < k ? T : 0;
   if (tid == 0) {
     info[MOE_INFO_ITERS] = state[ST_ITERS];
     info[MOE_INFO_CONVERGED] = empty ? 1 : state[ST_CONVERGED];
@@ -1130,7 +1153,8 @@ extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* 
   hipLaunchKernelGGL(route_init, dim3(1), dim3(256), 0, st, w.state, c.E, price,
                      c.price_mode, c.warm_gamma);
   if (c.T == 0) {
-    hipLaunchKernelGGL(route_finalize, dim3(1), dim3(256), 0, st, w.state, info, load, c.E, 1);
+    hipLaunchKernelGGL(route_finalize, dim3(1), dim3(256), 0, st, w.state, info, load, c.T, c.E,
+                       c.k, 1);
     MOE_LAUNCH_CHECK();
     return MOE_OK;
   }
@@ -1180,7 +1204,8 @@ moe_status route_from_scores(const moe_cfg& c, const RouteWs& w, const float* lo
   else
     launch_rank_select_repair<17>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
   PROF_END("price_loop", st);
-  hipLaunchKernelGGL(route_finalize, dim3(1), dim3(64), 0, st, w.state, info, load, c.E, 0);
+  hipLaunchKernelGGL(route_finalize, dim3(1), dim3(64), 0, st, w.state, info, load, c.T, c.E,
+                     c.k, 0);
   MOE_LAUNCH_CHECK();
   return MOE_OK;
 }
@@ -1198,7 +1223,8 @@ extern "C" moe_status moe_route_logits(const moe_cfg* cfg, const float* logits, 
   hipLaunchKernelGGL(route_init, dim3(1), dim3(256), 0, st, w.state, c.E, price,
                      c.price_mode, c.warm_gamma);
   if (c.T == 0) {
-    hipLaunchKernelGGL(route_finalize, dim3(1), dim3(256), 0, st, w.state, info, load, c.E, 1);
+    hipLaunchKernelGGL(route_finalize, dim3(1), dim3(256), 0, st, w.state, info, load, c.T, c.E,
+                       c.k, 1);
     MOE_LAUNCH_CHECK();
     return MOE_OK;
   }

@@ -176,9 +176,24 @@ def expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, ws=None):
     return Y
 
 
-def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None, fuse=True):
+def check_status(info, where="moe_route"):
+    """Raise MoEError if a routing's device status (info[MOE_INFO_STATUS]) is
+    not MOE_OK.  Reads the value on the host, so it waits for the stream."""
+    st = int(info[L.INFO_STATUS].item())
+    if st != L.MOE_OK:
+        raise L.MoEError(st, where)
+
+
+def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None, fuse=True,
+            check=True):
     """The whole layer forward; returns every intermediate (X_perm is None
-    when the permute is fused into the first expert product)."""
+    when the permute is fused into the first expert product).
+
+    check: after enqueueing every stage, wait for the stream and raise
+    MoEError if the routing failed on the device (a non-finite logit, or a
+    capacity repair that could not place every slot).  With check=False
+    nothing waits; a failed routing then carries NaN gate weights, so the
+    layer output is NaN rather than a plausible-looking value."""
     r = route(cfg, X, Wr, br, price)
     if fuse and gather_fused(cfg):
         dsp = dispatch(cfg, X, r["idx"], permute=False)
@@ -191,6 +206,8 @@ def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None, 
     r.update(dsp)
     r["Y"] = Y
     r["out"] = out
+    if check:
+        check_status(r["info"])
     return r
 
 
@@ -244,8 +261,8 @@ class MoEFunction(torch.autograd.Function):
     and W2; none flows into the prices or through the expert selection."""
 
     @staticmethod
-    def forward(ctx, X, Wr, br, W13, W2, cfg):
-        r = forward(cfg, X, Wr, br, W13, W2)
+    def forward(ctx, X, Wr, br, W13, W2, cfg, check=True):
+        r = forward(cfg, X, Wr, br, W13, W2, check=check)
         ctx.cfg = cfg
         ctx.save_for_backward(X, Wr, W13, W2, r["idx"], r["w"], r["row_map"], r["offsets"],
                               r["inv_map"], r["Y"])
@@ -259,9 +276,9 @@ class MoEFunction(torch.autograd.Function):
         dY, dw = combine_bwd(cfg, dOut, Y, inv_map, w)
         dXp, dW13, dW2 = expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2)
         dX, dWr, dbr = route_bwd(cfg, X, Wr, idx, w, dw, row_map, offsets, inv_map, dXp)
-        return (dX.to(X.dtype), dWr, dbr, dW13.to(W13.dtype), dW2.to(W2.dtype), None)
+        return (dX.to(X.dtype), dWr, dbr, dW13.to(W13.dtype), dW2.to(W2.dtype), None, None)
 
 
-def moe_layer(cfg, X, Wr, br, W13, W2):
-    """Differentiable layer forward (see MoEFunction)."""
-    return MoEFunction.apply(X, Wr, br, W13, W2, cfg)
+def moe_layer(cfg, X, Wr, br, W13, W2, check=True):
+    """Differentiable layer forward (see MoEFunction; check as in forward)."""
+    return MoEFunction.apply(X, Wr, br, W13, W2, cfg, check)

@@ -53,6 +53,42 @@ def rel_fro(a, b) -> float:
     return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
 
 
+def max_abs_rel(a, b) -> float:
+    """max |a - b| / max |b| (0 for empty arrays)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    if b.size == 0:
+        return 0.0
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def row_rel_max(a, b) -> float:
+    """Worst row of a 2-D result: ||a_r - b_r|| / max(||b_r||, 1e-3 max_r ||b_r||).
+    A single wrong, stale or zeroed row shows up here at its own size even
+    when the norm of the whole matrix hides it."""
+    a = np.asarray(a, np.float64).reshape(np.shape(a)[0], -1)
+    b = np.asarray(b, np.float64).reshape(np.shape(b)[0], -1)
+    if b.size == 0:
+        return 0.0
+    nb = np.linalg.norm(b, axis=1)
+    floor = 1e-3 * nb.max() if nb.max() > 0 else 1.0
+    return float((np.linalg.norm(a - b, axis=1) / np.maximum(nb, floor)).max())
+
+
+def assert_close(got, ref, tol, what="", row_tol=None):
+    """Relative Frobenius error <= tol, max |diff| / max |ref| <= tol and, for
+    matrices of at least 64 columns, every row's relative error <= row_tol
+    (2 * tol unless given)."""
+    fro, mx = rel_fro(got, ref), max_abs_rel(got, ref)
+    row = 0.0
+    if np.ndim(ref) == 2 and np.shape(ref)[1] >= 64:
+        row = row_rel_max(got, ref)
+    row_tol = 2.0 * tol if row_tol is None else row_tol
+    assert fro <= tol and mx <= tol and row <= row_tol, (what, fro, mx, row)
+    return fro, mx, row
+
+
 def replica_route(cfg, logits32, price_in=None):
     """The FP32-replica routing the GPU must reproduce bit for bit."""
     mode = cfg.price_mode

@@ -4,7 +4,11 @@
 Tolerances (relative Frobenius against FP64): BF16 activations, weights and
 stored intermediates (h, dA, dB, dY) give about 2^-8 per element, so
 gradients are held to 2e-2; the FP32 dot products of the combine backward
-(dw) to 1e-5 given the GPU's own Y.
+(dw) to 1e-5 given the GPU's own Y.  Every gradient bar holds for the
+relative Frobenius error and for max |diff| / max |ref|, and (at twice the
+bar) for the worst row of each matrix of at least 64 columns; an FP64
+emulation of the BF16 roundings gives at most 2.9e-3, 4.4e-3 and 7.6e-3 on
+the three measures at these shapes.
 """
 import numpy as np
 import pytest
@@ -13,7 +17,7 @@ import torch
 from oracle import grad, routing as R
 from paper_2606_17065_amd import layer, synth
 
-from _helpers import cfg_for, device_inputs, rel_fro
+from _helpers import assert_close, assert_route_matches, cfg_for, device_inputs, replica_route
 
 pytestmark = pytest.mark.gpu
 
@@ -52,26 +56,28 @@ def test_backward_pieces_match_oracle(shape, config):
     Yg = fw["Y"].float().cpu().double().numpy()
     inv = fw["inv_map"].cpu().numpy()
     dw_exact = np.einsum("tkd,td->tk", Yg[inv], dO)
-    assert rel_fro(dw.cpu().numpy(), dw_exact) <= 1e-5
+    assert_close(dw.cpu().numpy(), dw_exact, 1e-5, "dw (exact)")
     # dY = w * dOut in slot order, BF16-rounded
     wg = fw["w"].cpu().numpy().astype(np.float64)
     dY_exact = np.zeros_like(Yg)
     for j in range(shape.k):
         dY_exact[inv[:, j]] = wg[:, j:j + 1] * dO
-    assert rel_fro(dY.float().cpu().numpy(), dY_exact) <= 4e-3
+    assert_close(dY.float().cpu().numpy(), dY_exact, 4e-3, "dY")
     # against the FP64 oracle
-    assert rel_fro(dw.cpu().numpy(), ref["dw"]) <= 2e-2
-    assert rel_fro(dXp.float().cpu().numpy(), ref["dXp"]) <= 2e-2
-    assert rel_fro(dW13.cpu().numpy(), ref["dW13"]) <= 2e-2
-    assert rel_fro(dW2.cpu().numpy(), ref["dW2"]) <= 2e-2
-    assert rel_fro(dX.cpu().numpy(), ref["dX"]) <= 2e-2
+    assert_close(dw.cpu().numpy(), ref["dw"], 2e-2, "dw")
+    assert_close(dXp.float().cpu().numpy(), ref["dXp"], 2e-2, "dXp")
+    assert_close(dW13.cpu().numpy().reshape(-1, shape.d), ref["dW13"].reshape(-1, shape.d), 2e-2,
+                 "dW13")
+    assert_close(dW2.cpu().numpy().reshape(-1, shape.f), ref["dW2"].reshape(-1, shape.f), 2e-2,
+                 "dW2")
+    assert_close(dX.cpu().numpy(), ref["dX"], 2e-2, "dX")
     if shape.k == 1:
         # a single softmax weight is 1 whatever the logit: no router gradient
         assert np.abs(ref["dWr"]).max() == 0.0 and np.abs(ref["dbr"]).max() == 0.0
         assert np.abs(dWr.cpu().numpy()).max() == 0.0 and np.abs(dbr.cpu().numpy()).max() == 0.0
         return
-    assert rel_fro(dWr.cpu().numpy(), ref["dWr"]) <= 2e-2
-    assert rel_fro(dbr.cpu().numpy(), ref["dbr"]) <= 2e-2
+    assert_close(dWr.cpu().numpy(), ref["dWr"], 2e-2, "dWr")
+    assert_close(dbr.cpu().numpy(), ref["dbr"], 2e-2, "dbr")
 
 
 def test_dispatch_backward_is_a_gather_sum():
@@ -83,7 +89,7 @@ def test_dispatch_backward_is_a_gather_sum():
     inv = fw["inv_map"].cpu().numpy()
     g = dXp.float().cpu().double().numpy()
     exp = sum(g[inv[:, j]] for j in range(cfg.k))
-    assert rel_fro(dX.cpu().numpy(), exp) <= 1e-6
+    assert_close(dX.cpu().numpy(), exp, 1e-6, "dX")
 
 
 def test_autograd_function_matches_oracle():
@@ -106,8 +112,10 @@ def test_autograd_function_matches_oracle():
                               dOut.float().cpu().double().numpy())
     for name, t, key in [("X", X, "dX"), ("Wr", Wr, "dWr"), ("br", br, "dbr"), ("W13", W13, "dW13"),
                          ("W2", W2, "dW2")]:
-        err = rel_fro(t.grad.float().cpu().numpy(), ref[key])
-        assert err <= 2e-2, (name, err)
+        g, r_ = t.grad.float().cpu().numpy(), ref[key]
+        if g.ndim == 3:
+            g, r_ = g.reshape(-1, g.shape[-1]), r_.reshape(-1, r_.shape[-1])
+        assert_close(g, r_, 2e-2, name)
 
 
 def test_backward_is_deterministic():
@@ -134,6 +142,10 @@ def test_backward_fwd_bwd_config_sampled():
     del inp
     cfg = cfg_for(shape)
     fw = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"])
+    torch.cuda.synchronize()
+    # routing of the full batch (32768 tokens: each selection block streams
+    # its margin column) bit-exact against the FP32 replica
+    assert_route_matches(cfg, fw, replica_route(cfg, fw["logits"].cpu().numpy()))
     dOut = torch.from_numpy(synth.make_upstream(shape.T, shape.d, 4)).to(torch.bfloat16).cuda()
     dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
     dXp, dW13, dW2 = layer.expert_ffn_bwd(cfg, d["X"], fw["row_map"], fw["offsets"], dY, d["W13"],
@@ -157,8 +169,8 @@ def test_backward_fwd_bwd_config_sampled():
         U = dYh[a:b] @ W2e
         dA = U * B * (g + A * g * (1 - g))
         dB = U * A * g
-        assert rel_fro(dW2[e].cpu().numpy(), dYh[a:b].T @ hh) <= 2e-2
-        assert rel_fro(dW13[e, :f].cpu().numpy(), dA.T @ x) <= 2e-2
-        assert rel_fro(dW13[e, f:].cpu().numpy(), dB.T @ x) <= 2e-2
+        assert_close(dW2[e].cpu().numpy(), dYh[a:b].T @ hh, 2e-2, "dW2")
+        assert_close(dW13[e, :f].cpu().numpy(), dA.T @ x, 2e-2, "dW1")
+        assert_close(dW13[e, f:].cpu().numpy(), dB.T @ x, 2e-2, "dW3")
         dxp = dA @ W13e[:f] + dB @ W13e[f:]
-        assert rel_fro(dXp[a:b].float().cpu().numpy(), dxp) <= 2e-2
+        assert_close(dXp[a:b].float().cpu().numpy(), dxp, 2e-2, "dXp")

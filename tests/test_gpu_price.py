@@ -36,8 +36,8 @@ def _cfg(T, E, k, C=None, mode=L.MOE_PRICE_ACP, gamma=0.9, max_iters=50):
     return L.make_cfg(T, 8, E, k, 1, C, max_iters, L.MOE_F32, L.MOE_F32, mode, gamma)
 
 
-def _logits(T, E, seed, s_z=1.2):
-    s = synth.make_logits(T, E, s_z, seed)
+def _logits(T, E, seed, s_z=1.2, scale=0.64):
+    s = synth.make_logits(T, E, s_z, seed, scale)
     return s, torch.from_numpy(s).cuda()
 
 
@@ -69,6 +69,28 @@ def test_logit_stats_match_oracle(T, E, k, C, seed, tied):
     np.testing.assert_array_equal(np.rint(got[:, 4] * cfg.capacity),
                                   np.rint(ref[:, 4] * cfg.capacity))
     assert abs(float(sigma.item()) - s.astype(np.float64).std()) <= 1e-6 * s.std()
+
+
+# batches longer than 16384 tokens: the statistics' per-expert selection
+# keeps 64 keys per lane up to 65536 tokens and streams the column beyond;
+# the fwd+bwd (32768 x 128) and FP8 (65536 x 64) workload shapes, the
+# learned-price workload's widest batches (E = 256) and a batch past 65536
+LONG_STATS_CASES = [(32768, 128, 8, 1.3, 61), (65536, 64, 8, 1.2, 62), (40001, 256, 8, 1.5, 63),
+                    (65536, 256, 8, 1.0, 64), (70001, 64, 8, 1.2, 65)]
+
+
+@pytest.mark.parametrize("T,E,k,s_z,seed", LONG_STATS_CASES)
+def test_logit_stats_match_oracle_long_batches(T, E, k, s_z, seed):
+    s, sd = _logits(T, E, seed, s_z)
+    cfg = _cfg(T, E, k)
+    feats, sigma = P.logit_stats(cfg, sd)
+    torch.cuda.synchronize()
+    ref = M.features(s, k, cfg.capacity)
+    got = feats.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 2e-6, (err.max(), np.unravel_index(err.argmax(), err.shape))
+    np.testing.assert_array_equal(np.rint(got[:, 4] * cfg.capacity),
+                                  np.rint(ref[:, 4] * cfg.capacity))
 
 
 def test_logit_stats_rejects_bad_shapes():
@@ -215,6 +237,28 @@ RANK_VARIANTS = [(450, E, k, 100 + 10 * i + j)
 @pytest.mark.parametrize("T,E,k,seed", RANK_VARIANTS)
 def test_route_logits_bit_exact_for_every_ranking_variant(T, E, k, seed):
     s, sd = _logits(T, E, seed)
+    cfg = _cfg(T, E, k)
+    r = P.route_logits(cfg, sd)
+    torch.cuda.synchronize()
+    ref = replica_route(cfg, s)
+    assert ref["iters"] > 0
+    assert_route_matches(cfg, r, ref)
+
+
+# batches longer than 16384 tokens, where each selection block streams its
+# margin column from memory in every radix pass instead of holding it in
+# registers: just past the switch, an uneven length, the FP8 workload
+# shape (65536 x 64, Zipf 1.2), the fwd+bwd workload shape (32768 x 128,
+# Zipf 1.3) and a batch past 65536 tokens
+# (logit scale 0.02 * sqrt(d_model): 1.28 at d = 4096, 0.905 at d = 2048)
+LONG_ROUTE_CASES = [(16385, 64, 8, 1.2, 0.64, 71), (40000, 64, 8, 1.2, 0.64, 72),
+                    (65536, 64, 8, 1.2, 1.28, 73), (32768, 128, 8, 1.3, 0.905, 74),
+                    (70001, 32, 4, 1.2, 0.64, 75)]
+
+
+@pytest.mark.parametrize("T,E,k,s_z,scale,seed", LONG_ROUTE_CASES)
+def test_route_logits_bit_exact_long_batches(T, E, k, s_z, scale, seed):
+    s, sd = _logits(T, E, seed, s_z, scale)
     cfg = _cfg(T, E, k)
     r = P.route_logits(cfg, sd)
     torch.cuda.synchronize()
