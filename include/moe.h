@@ -167,6 +167,41 @@ moe_status moe_route_certify(const moe_cfg* cfg, const float* logits, const floa
                              void* stream);
 
 /*
+ * moe_route_judged -- routing from learned prices p_hat with the exact
+ *   update as judge and fallback, all on the device (no host wait):
+ *   1) learned pass, cfg.price_mode MOE_PRICE_WARM (p0 = fl32(warm_gamma *
+ *      p_hat), then the clearing-price update of moe_route_logits, at most
+ *      cfg.max_iters updates) or MOE_PRICE_GIVEN (p = p_hat, no update; the
+ *      capacity repair of moe_route places any overflow);
+ *   2) judge: the certificate of moe_route_certify for that routing under
+ *      its prices; the routing is kept when its status is MOE_OK and the
+ *      relative gap (dual - primal) / |dual| is at most gap_tol (weak
+ *      duality makes the gap valid for any routing within capacity,
+ *      repaired ones included);
+ *   3) otherwise the batch is routed again by the update from p = 0 (as
+ *      moe_route_logits in MOE_PRICE_ACP with cfg.max_iters), whose
+ *      routing is returned.
+ *   logits [T,E] f32; price_hat [E] f32 (read only); gap_tol >= 0 (finite);
+ *   price, topk_idx, topk_w, load, info as moe_route_logits writes them for
+ *   the routing returned; verdict [5] f64 out (8-byte aligned):
+ *     verdict[0] = V = sum_e max(0, load_e - C) / N of the learned routing
+ *                  before any repair,
+ *     verdict[1] = relative gap of the learned routing (NaN if it failed),
+ *     verdict[2] = 1 if the learned routing was kept, 0 if routed again,
+ *     verdict[3] = relative gap of the routing returned,
+ *     verdict[4] = price updates of the learned pass.
+ *   A non-finite logit ends both passes with MOE_ENAN in info (verdict[2]
+ *   = 0, gaps NaN).  cfg.price_mode other than WARM or GIVEN: MOE_EINVAL.
+ *   ws: at least moe_workspace_bytes(cfg).  The fallback pass is always
+ *   enqueued; when the learned routing is kept each of its kernels returns
+ *   at once.
+ */
+moe_status moe_route_judged(const moe_cfg* cfg, const float* logits, const float* price_hat,
+                            float gap_tol, float* price, int32_t* topk_idx, float* topk_w,
+                            int32_t* load, int32_t* info, double* verdict, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/*
  * Learned starting prices.  Eight statistics of a batch of logits per
  * expert feed a small network shared by all experts whose output,
  * p_hat_e = sigma * softplus(z_e), predicts the prices the clearing-price

@@ -356,6 +356,55 @@ def route(s32, k, C, max_iters=50, p0=None, mode="acp", stages=0):
     return res
 
 
+def judged_route(s32, k, C, p_hat, mode="warm", gamma=0.9, gap_tol=5e-3, max_iters=50):
+    """Routing from learned prices, judged by the duality certificate, with
+    the update from zero prices as fallback (reading stated here).
+
+    Learned pass: "warm" runs the clearing-price update from p0 =
+    fl32(gamma * p_hat) (at most max_iters updates); "replace" routes under
+    p_hat alone (no update; the capacity repair places any overflow).  The
+    learned routing is kept when its status is OK and its relative gap
+    (D(p) - sum s x) / |D(p)| under its own prices is <= gap_tol (weak
+    duality makes this a valid bound for any routing within capacity,
+    repaired ones included).  Otherwise the batch is routed by the update
+    from p = 0.  A non-finite logit is reported as such, with no fallback.
+
+    Returns the dict of ``route`` for the routing kept, plus V (overflow of
+    the learned ranking before any repair, divided by N = T k), gap_learned,
+    kept, gap (of the routing returned) and learned_iters."""
+    s32 = np.ascontiguousarray(s32, dtype=F32)
+    T, E = s32.shape
+    ph = np.asarray(p_hat, dtype=F32)
+    if mode == "warm":
+        r = route(s32, k, C, max_iters, (F32(gamma) * ph).astype(F32), "acp")
+    elif mode == "replace":
+        r = route(s32, k, C, 0, ph, "given")
+    else:
+        raise ValueError(mode)
+    N = max(T * k, 1)
+    extra = dict(V=0.0, gap_learned=float("nan"), kept=False, gap=float("nan"),
+                 learned_iters=r["iters"])
+    if r["status"] == ENAN:
+        return {**r, **extra}
+    if r["p"] is not None:
+        sel0 = topk_under_prices(s32, r["p"], k)[0]
+        extra["V"] = float(np.maximum(loads(sel0, E) - C, 0).sum()) / N
+
+    def rel_gap(res):
+        prim = primal_objective(s32, res["sel"])
+        dual = dual_objective(s32, res["p"], k, C)
+        return (dual - prim) / (abs(dual) if dual != 0.0 else 1.0)
+
+    if r["status"] == OK:
+        extra["gap_learned"] = rel_gap(r)
+        extra["kept"] = extra["gap_learned"] <= gap_tol
+    if not extra["kept"]:
+        r = route(s32, k, C, max_iters, None, "acp")
+    if r["status"] == OK:
+        extra["gap"] = rel_gap(r)
+    return {**r, **extra}
+
+
 def primal_objective(s, sel) -> float:
     rows = np.arange(sel.shape[0])[:, None]
     return float(np.asarray(s, dtype=np.float64)[rows, sel].sum())

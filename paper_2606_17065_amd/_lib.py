@@ -64,6 +64,7 @@ SIGNATURES = {
     "moe_route_logits": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_price_update": [_CFG, _P, _P, _P, _P, _S, _P],
     "moe_route_certify": [_CFG, _P, _P, _P, _P, _P, _S, _P],
+    "moe_route_judged": [_CFG, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_logit_stats": [_CFG, _P, _P, _P, _P, _S, _P],
     "moe_price_mlp_sizes": [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
@@ -184,6 +185,13 @@ def moe_price_update(cfg, logits, price, info, ws, ws_bytes, stream):
 def moe_route_certify(cfg, logits, price, topk_idx, cert, ws, ws_bytes, stream):
     _check(lib().moe_route_certify(ctypes.byref(cfg), logits, price, topk_idx, cert, ws, ws_bytes,
                                    stream), "moe_route_certify")
+
+
+def moe_route_judged(cfg, logits, price_hat, gap_tol, price, topk_idx, topk_w, load, info,
+                     verdict, ws, ws_bytes, stream):
+    _check(lib().moe_route_judged(ctypes.byref(cfg), logits, price_hat, float(gap_tol), price,
+                                  topk_idx, topk_w, load, info, verdict, ws, ws_bytes, stream),
+           "moe_route_judged")
 
 
 def moe_logit_stats(cfg, logits, feats, sigma, ws, ws_bytes, stream):

@@ -41,6 +41,7 @@ extern "C" moe_status moe_workspace_bytes(const moe_cfg* cfg, size_t* bytes) {
   b = std::max(b, ffn_ws_bytes(*cfg));
   b = std::max(b, route_bwd_ws_bytes(*cfg));
   b = std::max(b, cert_ws_bytes(*cfg));
+  b = std::max(b, judged_ws_bytes(*cfg));
   if (cfg->T >= 1 && cfg->k < cfg->E) b = std::max(b, stats_ws_bytes(*cfg));
   if (cfg->act == MOE_BF16 && cfg->w == MOE_BF16 && cfg->d_ff % 128 == 0 && cfg->d % 256 == 0)
     b = std::max(b, ffn_bwd_ws_bytes(*cfg));

@@ -28,6 +28,7 @@ enum {
   ST_EPS = 7,         // float bits
   ST_NEED_REPAIR = 8,
   ST_REPAIRED = 9,
+  ST_SKIP_WEIGHTS = 10,  // the final routing is already in place (judged routing kept)
   ST_LEN = 16
 };
 

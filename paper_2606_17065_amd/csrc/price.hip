@@ -492,8 +492,14 @@ extern "C" moe_status moe_route_certify(const moe_cfg* cfg, const float* logits,
   if (!aligned(logits, 4) || !aligned(price, 4) || !aligned(topk_idx, 4) || !aligned(cert, 8))
     return MOE_EINVAL;
   if (!ws || ws_bytes < cert_ws_bytes(c)) return MOE_EWORKSPACE;
+  launch_certify(c, logits, price, topk_idx, (double*)ws, cert, stream);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+void launch_certify(const moe_cfg& c, const float* logits, const float* price,
+                    const int32_t* topk_idx, double* part, double* cert, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  double* part = (double*)ws;
   const int nb = (c.T + 255) / 256;
   if (nb > 0) {
     const int L = c.k;
@@ -512,8 +518,6 @@ extern "C" moe_status moe_route_certify(const moe_cfg* cfg, const float* logits,
   }
   hipLaunchKernelGGL(cert_final, dim3(1), dim3(64), 0, st, part, nb, price, c.E, c.capacity,
                      cert);
-  MOE_LAUNCH_CHECK();
-  return MOE_OK;
 }
 
 extern "C" moe_status moe_price_mse(int rows, int group, const float* price_hat,

@@ -511,7 +511,7 @@ __global__ __launch_bounds__(256) void route_weights(const float* __restrict__ l
                                                      int k, const int32_t* __restrict__ state,
                                                      float* __restrict__ w) {
   const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= T) return;
+  if (t >= T || state[ST_SKIP_WEIGHTS]) return;
   if (state[ST_STATUS] != MOE_OK) {
     for (int j = 0; j < k; ++j) {
       idx[(size_t)t * k + j] = j;
@@ -1183,6 +1183,21 @@ extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* 
 
 namespace {
 
+// The price loop (iters updates at most), the gate weights and the repair,
+// for the list length of k.
+void launch_loop(const moe_cfg& c, const RouteWs& w, const float* logits, float* price,
+                 int32_t* topk_idx, float* topk_w, int32_t* load, int iters, hipStream_t st) {
+  const int L = c.k + 1;
+  if (L <= 3)
+    launch_rank_select_repair<3>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
+  else if (L <= 5)
+    launch_rank_select_repair<5>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
+  else if (L <= 9)
+    launch_rank_select_repair<9>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
+  else
+    launch_rank_select_repair<17>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
+}
+
 // Everything after the logits: sigma_s, the price loop, weights, repair.
 moe_status route_from_scores(const moe_cfg& c, const RouteWs& w, const float* logits,
                              float* price, int32_t* topk_idx, float* topk_w, int32_t* load,
@@ -1193,16 +1208,8 @@ moe_status route_from_scores(const moe_cfg& c, const RouteWs& w, const float* lo
                      (double)c.T * (double)c.E, w.state);
   const int iters =
       (c.price_mode == MOE_PRICE_ACP || c.price_mode == MOE_PRICE_WARM) ? c.max_iters : 0;
-  const int L = c.k + 1;
   PROF_BEGIN("price_loop", st);
-  if (L <= 3)
-    launch_rank_select_repair<3>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
-  else if (L <= 5)
-    launch_rank_select_repair<5>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
-  else if (L <= 9)
-    launch_rank_select_repair<9>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
-  else
-    launch_rank_select_repair<17>(c, w, logits, price, topk_idx, topk_w, load, iters, st);
+  launch_loop(c, w, logits, price, topk_idx, topk_w, load, iters, st);
   PROF_END("price_loop", st);
   hipLaunchKernelGGL(route_finalize, dim3(1), dim3(64), 0, st, w.state, info, load, c.T, c.E,
                      c.k, 0);
@@ -1267,4 +1274,145 @@ extern "C" moe_status moe_price_update(const moe_cfg* cfg, const float* logits, 
   if (ws_bytes < price_ws_bytes(*cfg) || !ws) return MOE_EWORKSPACE;
   PriceScratch sc = carve_price_scratch(*cfg, ws, nullptr);
   return moe_route_logits(cfg, logits, price, sc.idx, sc.w, sc.load, info, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------ judged learned prices
+// moe_route_judged: route from learned prices (warm start or replacement),
+// certify the result, and on the device either keep it or route the batch
+// again by the update from zero prices.  No host synchronisation: the
+// fallback pass is always enqueued and every one of its kernels exits at
+// once when the learned routing was kept.
+namespace {
+
+__global__ void judge_init(int32_t* state, int E, const float* __restrict__ p_hat,
+                           float* __restrict__ price, int mode, float gamma) {
+  const int tid = threadIdx.x;
+  if (tid < ST_LEN) state[tid] = 0;
+  for (int e = tid; e < E; e += blockDim.x)
+    price[e] = mode == MOE_PRICE_WARM ? gamma * p_hat[e] : p_hat[e];
+}
+
+// Keep the learned routing if it is valid and its relative certificate gap
+// is at most gap_tol; otherwise reset the state words and prices for the
+// update from p = 0.  A non-finite logit is kept as it is (a second pass
+// would meet the same logits).
+__global__ void judge_decide(const double* __restrict__ cert, int32_t* state,
+                             float* __restrict__ price, int E, int N, float gap_tol,
+                             double* __restrict__ verdict) {
+  __shared__ int keep_s;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    const int status = state[ST_STATUS];
+    const double gap = cert[2];
+    const bool ok = status == MOE_OK && gap <= (double)gap_tol;
+    const bool keep = ok || status == MOE_ENAN;
+    verdict[0] = (double)state[ST_OVERFLOW] / (double)(N > 0 ? N : 1);
+    verdict[1] = status == MOE_OK ? gap : __builtin_nan("");
+    verdict[2] = ok ? 1.0 : 0.0;
+    verdict[4] = (double)state[ST_ITERS];
+    if (keep) {
+      state[ST_DONE] = 1;
+      state[ST_NEED_REPAIR] = 0;
+      state[ST_SKIP_WEIGHTS] = 1;
+    } else {
+      state[ST_DONE] = 0;
+      state[ST_CONVERGED] = 0;
+      state[ST_ITERS] = 0;
+      state[ST_OVERFLOW] = 0;
+      state[ST_STATUS] = MOE_OK;
+      state[ST_ROUNDS] = 0;
+      state[ST_NEED_REPAIR] = 0;
+      state[ST_REPAIRED] = 0;
+      state[ST_SKIP_WEIGHTS] = 0;
+    }
+    keep_s = keep;
+  }
+  __syncthreads();
+  if (!keep_s)
+    for (int e = tid; e < E; e += blockDim.x) price[e] = 0.0f;
+}
+
+__global__ void judge_final(const double* __restrict__ cert, const int32_t* state,
+                            double* __restrict__ verdict, int empty) {
+  if (threadIdx.x != 0) return;
+  if (empty) {
+    verdict[0] = 0.0;
+    verdict[1] = 0.0;
+    verdict[2] = 1.0;
+    verdict[3] = 0.0;
+    verdict[4] = 0.0;
+    return;
+  }
+  verdict[3] = state[ST_STATUS] == MOE_OK ? cert[2] : __builtin_nan("");
+}
+
+struct JudgeScratch {
+  double* part;
+  double* cert;
+};
+
+JudgeScratch carve_judge_scratch(const moe_cfg& c, void* base, size_t* total) {
+  const size_t head = route_ws_bytes(c);
+  WsCarve wc{base ? (char*)base + head : nullptr, 0};
+  JudgeScratch r;
+  r.part = wc.take<double>(2 * (((size_t)c.T + 255) / 256 + 1));
+  r.cert = wc.take<double>(4);
+  if (total) *total = head + align_up(wc.off, 256);
+  return r;
+}
+
+}  // namespace
+
+size_t judged_ws_bytes(const moe_cfg& c) {
+  size_t total = 0;
+  carve_judge_scratch(c, nullptr, &total);
+  return total;
+}
+
+extern "C" moe_status moe_route_judged(const moe_cfg* cfg, const float* logits,
+                                       const float* price_hat, float gap_tol, float* price,
+                                       int32_t* topk_idx, float* topk_w, int32_t* load,
+                                       int32_t* info, double* verdict, void* ws, size_t ws_bytes,
+                                       void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.price_mode != MOE_PRICE_WARM && c.price_mode != MOE_PRICE_GIVEN) return MOE_EINVAL;
+  if (!price_hat || !verdict || !aligned(price_hat, 4) || !aligned(verdict, 8))
+    return MOE_EINVAL;
+  if (!(gap_tol >= 0.0f) || !(gap_tol < INFINITY)) return MOE_EINVAL;
+  if (ws_bytes < judged_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  stc = route_check(cfg, logits, price, topk_idx, topk_w, load, info, ws, ws_bytes);
+  if (stc != MOE_OK) return stc;
+  hipStream_t st = (hipStream_t)stream;
+  RouteWs w = carve_route(c, ws, nullptr);
+  JudgeScratch js = carve_judge_scratch(c, ws, nullptr);
+  hipLaunchKernelGGL(judge_init, dim3(1), dim3(256), 0, st, w.state, c.E, price_hat, price,
+                     c.price_mode, c.warm_gamma);
+  if (c.T == 0) {
+    hipLaunchKernelGGL(route_finalize, dim3(1), dim3(256), 0, st, w.state, info, load, c.T, c.E,
+                       c.k, 1);
+    hipLaunchKernelGGL(judge_final, dim3(1), dim3(64), 0, st, js.cert, w.state, verdict, 1);
+    MOE_LAUNCH_CHECK();
+    return MOE_OK;
+  }
+  hipLaunchKernelGGL(logits_transpose, dim3((c.T + 63) / 64, (c.E + 63) / 64), dim3(256), 0, st,
+                     logits, c.T, c.E, w.sT);
+  // 1) the learned pass: warm-started update, or p_hat alone plus repair
+  stc = route_from_scores(c, w, logits, price, topk_idx, topk_w, load, info, st);
+  if (stc != MOE_OK) return stc;
+  launch_certify(c, logits, price, topk_idx, js.part, js.cert, st);
+  hipLaunchKernelGGL(judge_decide, dim3(1), dim3(256), 0, st, js.cert, w.state, price, c.E,
+                     c.T * c.k, gap_tol, verdict);
+  // 2) the fallback: the update from p = 0 (nothing runs if the learned
+  //    routing was kept)
+  moe_cfg c0 = c;
+  c0.price_mode = MOE_PRICE_ACP;
+  launch_loop(c0, w, logits, price, topk_idx, topk_w, load, c.max_iters, st);
+  hipLaunchKernelGGL(route_finalize, dim3(1), dim3(64), 0, st, w.state, info, load, c.T, c.E,
+                     c.k, 0);
+  launch_certify(c, logits, price, topk_idx, js.part, js.cert, st);
+  hipLaunchKernelGGL(judge_final, dim3(1), dim3(64), 0, st, js.cert, w.state, verdict, 0);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
 }

@@ -3,9 +3,9 @@ training, and routing that starts from (or replaces) the clearing-price
 update with the exact update as fallback and judge.
 
 Every computation runs in libmoe's kernels; this module allocates device
-tensors, passes pointers and streams, and makes the one host-side decision
-of the judge (fall back to the exact update or not), which needs the
-certificate's value on the host.
+tensors and passes pointers and streams.  The judge's decision (keep the
+learned routing or route again from zero prices) is made on the device by
+moe_route_judged.
 """
 from __future__ import annotations
 
@@ -209,38 +209,55 @@ def predict(cfg, logits, params):
     return phat
 
 
-def learned_route(cfg, logits, params, mode="warm", gamma=0.9):
-    """Route one batch with learned prices.
+VERDICT_V, VERDICT_GAP, VERDICT_KEPT, VERDICT_GAP_FINAL, VERDICT_ITERS = range(5)
+
+
+def judged_route(cfg, logits, phat, mode="warm", gamma=0.9, gap_tol=GAP_TOL, ws=None):
+    """moe_route_judged: the routing from learned prices p_hat, kept when the
+    certificate's relative gap is <= gap_tol, else the exact update from
+    p = 0 (decided on the device).  Returns the routing dict plus the
+    verdict tensor [5] f64 (V, learned gap, kept, final gap, learned-pass
+    updates)."""
+    T, E, k = cfg.T, cfg.E, cfg.k
+    _need(logits, "logits", torch.float32, (T, E))
+    _need(phat, "price_hat", torch.float32, (E,))
+    if mode not in ("warm", "replace"):
+        raise ValueError(f"unknown mode {mode!r}")
+    pm = L.MOE_PRICE_WARM if mode == "warm" else L.MOE_PRICE_GIVEN
+    c = L.make_cfg(T, cfg.d, E, k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act, cfg.w, pm, gamma)
+    dev = logits.device
+    out = dict(price=torch.empty(E, dtype=torch.float32, device=dev),
+               idx=torch.empty(T, k, dtype=torch.int32, device=dev),
+               w=torch.empty(T, k, dtype=torch.float32, device=dev),
+               load=torch.empty(E, dtype=torch.int32, device=dev),
+               info=torch.empty(L.INFO_LEN, dtype=torch.int32, device=dev),
+               verdict=torch.empty(5, dtype=torch.float64, device=dev))
+    ws = _WS.get(c, dev) if ws is None else ws
+    L.moe_route_judged(c, _p(logits), _p(phat), gap_tol, _p(out["price"]), _p(out["idx"]),
+                       _p(out["w"]), _p(out["load"]), _p(out["info"]), _p(out["verdict"]), _p(ws),
+                       ws.numel(), _stream())
+    return out
+
+
+def learned_route(cfg, logits, params, mode="warm", gamma=0.9, gap_tol=GAP_TOL):
+    """Route one batch with learned prices (statistics, network, then
+    moe_route_judged; no host synchronisation).
 
     warm:    p0 = gamma * p_hat, then the exact clearing-price update.
-    replace: route under p_hat alone (no update; the capacity repair runs
-             if an expert overflows); the violation V = overflow / N is
-             reported; the judge accepts the result when V = 0 and the
-             certificate's relative gap is <= GAP_TOL, else the batch is
-             routed again by the exact update from p = 0.
-    Returns the routing dict plus p_hat, and for replace: V, gap, fallback."""
+    replace: route under p_hat alone (the capacity repair places any
+             overflow).
+    Either routing is kept when its certificate gap is <= gap_tol, else the
+    batch is routed again by the exact update from p = 0.  Returns the
+    routing dict plus p_hat and the verdict tensor."""
     phat = predict(cfg, logits, params)
-    if mode == "warm":
-        c = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act,
-                       cfg.w, L.MOE_PRICE_WARM, gamma)
-        r = route_logits(c, logits, phat.clone())
-        r["p_hat"] = phat
-        return r
-    if mode != "replace":
-        raise ValueError(f"unknown mode {mode!r}")
-    c = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act,
-                   cfg.w, L.MOE_PRICE_GIVEN)
-    r = route_logits(c, logits, phat.clone())
-    info = r["info"].cpu()
-    overflow = int(info[L.INFO_OVERFLOW])
-    V = overflow / float(cfg.T * cfg.k)
-    gap = float("nan")
-    if overflow == 0:
-        gap = float(certify(c, logits, r["price"], r["idx"])[2].item())
-    accept = overflow == 0 and gap <= GAP_TOL
-    if not accept:
-        c0 = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity, cfg.max_iters,
-                        cfg.act, cfg.w, L.MOE_PRICE_ACP)
-        r = route_logits(c0, logits)
-    r.update(p_hat=phat, V=V, gap=gap, fallback=not accept)
+    r = judged_route(cfg, logits, phat, mode, gamma, gap_tol)
+    r["p_hat"] = phat
     return r
+
+
+def verdict_dict(r):
+    """Host copy of a judged routing's verdict (waits for the stream)."""
+    v = r["verdict"].cpu().numpy()
+    return {"V": float(v[VERDICT_V]), "gap_learned": float(v[VERDICT_GAP]),
+            "kept": bool(v[VERDICT_KEPT] == 1.0), "gap": float(v[VERDICT_GAP_FINAL]),
+            "learned_iters": int(v[VERDICT_ITERS])}

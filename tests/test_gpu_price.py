@@ -323,7 +323,68 @@ def _small_dataset(n, E, k, seed0):
     return out
 
 
+def _assert_judged(cfg, r, s, phat, mode, tol, gamma=0.9):
+    """The judged routing against the oracle's: the keep-or-fallback
+    decision, the routing returned (bit-exact against the FP32 replica of
+    the pass that produced it) and the verdict."""
+    ref = R.judged_route(s, cfg.k, cfg.capacity, phat, mode, gamma, tol, cfg.max_iters)
+    v = P.verdict_dict(r)
+    assert v["kept"] == ref["kept"], (v, ref["gap_learned"])
+    if ref["kept"]:
+        pm = L.MOE_PRICE_WARM if mode == "warm" else L.MOE_PRICE_GIVEN
+        c = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity,
+                       cfg.max_iters if mode == "warm" else 0, cfg.act, cfg.w, pm, gamma)
+        assert_route_matches(c, r, replica_route(c, s, phat))
+    else:
+        c = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act,
+                       cfg.w, L.MOE_PRICE_ACP)
+        assert_route_matches(c, r, replica_route(c, s))
+    assert v["V"] == ref["V"]
+    assert v["learned_iters"] == ref["learned_iters"]
+    assert abs(v["gap_learned"] - ref["gap_learned"]) <= 1e-12
+    assert abs(v["gap"] - ref["gap"]) <= 1e-12
+    return v, ref
+
+
+# learned prices: the exact clearing prices and a 10 % under-estimate of
+# them; tolerances that keep (1.0), judge (5e-3) and reject (0.0)
+@pytest.mark.parametrize("tol", [1.0, 5e-3, 0.0])
+@pytest.mark.parametrize("scale", [1.0, 0.9])
+@pytest.mark.parametrize("mode", ["warm", "replace"])
+def test_judged_route_matches_oracle(mode, scale, tol):
+    T, E, k = 3001, 48, 6
+    s, sd = _logits(T, E, 93)
+    cfg = _cfg(T, E, k)
+    pstar = R.route(s, k, cfg.capacity, 50)["p"]
+    phat = (pstar * F32(scale)).astype(F32)
+    r = P.judged_route(cfg, sd, torch.from_numpy(phat).cuda(), mode, gap_tol=tol)
+    torch.cuda.synchronize()
+    v, ref = _assert_judged(cfg, r, s, phat, mode, tol)
+    if tol == 1.0:
+        assert v["kept"]
+    if tol == 0.0:
+        assert not v["kept"]
+
+
+def test_judged_route_empty_batch_and_bad_mode():
+    cfg = _cfg(0, 8, 2, 0)
+    r = P.judged_route(cfg, torch.empty(0, 8, device="cuda"), torch.zeros(8, device="cuda"))
+    torch.cuda.synchronize()
+    assert int(r["info"][L.INFO_STATUS]) == 0 and P.verdict_dict(r)["kept"]
+    s, sd = _logits(100, 8, 94)
+    c = _cfg(100, 8, 2, mode=L.MOE_PRICE_ACP)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    with pytest.raises(L.MoEError) as e:
+        L.moe_route_judged(c, sd.data_ptr(), sd.data_ptr(), 5e-3, sd.data_ptr(), sd.data_ptr(),
+                           sd.data_ptr(), sd.data_ptr(), sd.data_ptr(), sd.data_ptr(),
+                           ws.data_ptr(), ws.numel(), 0)
+    assert e.value.status == L.MOE_EINVAL
+
+
 def test_learned_prices_train_and_route_bit_exact():
+    """Train on small batches, then route a fresh batch from the network's
+    prices: warm start and replacement, each judged on the device and
+    checked against the oracle's judged routing."""
     E, k = 64, 8
     ds = P.build_dataset(_small_dataset(24, E, k, 900), E, k)
     params, hist = P.train(ds, steps=300, batches_per_step=8, lr=1e-3, seed=3, log_every=50)
@@ -333,23 +394,10 @@ def test_learned_prices_train_and_route_bit_exact():
     s = synth.make_logits(T, E, 1.25, 12345)
     sd = torch.from_numpy(s).cuda()
     cfg = _cfg(T, E, k)
-    # warm start: bit-exact against the replica started from gamma * p_hat
-    rw = P.learned_route(cfg, sd, params, mode="warm")
-    torch.cuda.synchronize()
-    phat = rw["p_hat"].cpu().numpy()
-    cw = _cfg(T, E, k, mode=L.MOE_PRICE_WARM)
-    assert_route_matches(cw, rw, replica_route(cw, s, phat))
-    cold = replica_route(_cfg(T, E, k), s)
-    # replace: either accepted with no violation and a small gap, or the
-    # exact update from zero prices
-    rr = P.learned_route(cfg, sd, params, mode="replace")
-    torch.cuda.synchronize()
-    if rr["fallback"]:
-        assert_route_matches(cfg, rr, cold)
-    else:
-        assert rr["V"] == 0.0 and rr["gap"] <= P.GAP_TOL
-        cg = _cfg(T, E, k, mode=L.MOE_PRICE_GIVEN)
-        assert_route_matches(cg, rr, replica_route(cg, s, phat))
+    for mode in ("warm", "replace"):
+        r = P.learned_route(cfg, sd, params, mode=mode)
+        torch.cuda.synchronize()
+        _assert_judged(cfg, r, s, r["p_hat"].cpu().numpy(), mode, P.GAP_TOL)
 
 
 def test_learned_price_path_at_full_size():
@@ -375,8 +423,7 @@ def test_learned_price_path_at_full_size():
     params = torch.from_numpy(M.init_params(21)).cuda()
     rw = P.learned_route(cfg, logits, params, mode="warm")
     torch.cuda.synchronize()
-    cw = _cfg(T, E, k, mode=L.MOE_PRICE_WARM)
-    assert_route_matches(cw, rw, replica_route(cw, s, rw["p_hat"].cpu().numpy()))
+    _assert_judged(cfg, rw, s, rw["p_hat"].cpu().numpy(), "warm", P.GAP_TOL)
     cert = P.certify(cfg, logits, rw["price"], rw["idx"]).cpu().numpy()
     sel = rw["idx"].cpu().numpy()
     prim = R.primal_objective(s, sel)
