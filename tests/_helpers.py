@@ -76,16 +76,17 @@ def row_rel_max(a, b) -> float:
     return float((np.linalg.norm(a - b, axis=1) / np.maximum(nb, floor)).max())
 
 
-def assert_close(got, ref, tol, what="", row_tol=None):
-    """Relative Frobenius error <= tol, max |diff| / max |ref| <= tol and, for
-    matrices of at least 64 columns, every row's relative error <= row_tol
-    (2 * tol unless given)."""
+def assert_close(got, ref, tol, what="", row_tol=None, max_tol=None):
+    """Relative Frobenius error <= tol, max |diff| / max |ref| <= max_tol
+    (tol unless given) and, for matrices of at least 64 columns, every row's
+    relative error <= row_tol (2 * tol unless given)."""
     fro, mx = rel_fro(got, ref), max_abs_rel(got, ref)
     row = 0.0
     if np.ndim(ref) == 2 and np.shape(ref)[1] >= 64:
         row = row_rel_max(got, ref)
     row_tol = 2.0 * tol if row_tol is None else row_tol
-    assert fro <= tol and mx <= tol and row <= row_tol, (what, fro, mx, row)
+    max_tol = tol if max_tol is None else max_tol
+    assert fro <= tol and mx <= max_tol and row <= row_tol, (what, fro, mx, row)
     return fro, mx, row
 
 

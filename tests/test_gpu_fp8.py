@@ -5,15 +5,19 @@ Bars:
   quantisation (tokens 1 x 128 in the dispatch, weights 128 x 128, h):
       codes and scales bit-identical to the oracle's quantiser run on the
       same FP32 / BF16 values;
-  expert outputs Y and layer output: rel. Frobenius and max |diff| /
-      max |ref| <= 1e-2 against the FP8-emulating FP64 oracle (its h is
-      rounded to BF16 and re-quantised like the GPU's; a BF16 rounding of h
-      on either side can move an FP8 code by one step, up to an eighth of
-      that element), worst row <= 1e-1 (one moved code of a large h element
-      shifts a row of Y by a few 1e-2 at d_ff = 128; a wrong or zeroed row
-      gives about 1); rel. Frobenius <= 8e-2 against the FP64 layer on the
-      same BF16 tokens and unquantised weights (the FP8 rounding itself,
-      about 6.4e-2 in an FP64 emulation at these shapes).
+  expert outputs Y and layer output: rel. Frobenius <= 1e-2 against the
+      FP8-emulating FP64 oracle (its h is rounded to BF16 and re-quantised
+      like the GPU's; a BF16 rounding of h on either side can move an FP8
+      code by one step, up to an eighth of that element), worst row <= 1e-1
+      (one moved code of a large h element shifts a row of Y by a few 1e-2
+      at d_ff = 128; a wrong or zeroed row gives about 1), max |diff| /
+      max |ref| <= 3e-2: when the BF16 rounding of a block's largest h
+      element differs, that block's scale differs and every one of its 128
+      codes can move by a step at once (1.3-1.5e-2 of max |Y| measured at
+      these shapes, with GEMM 2 on the GPU's own h codes agreeing to 2.3e-3,
+      the BF16 rounding of Y); rel. Frobenius <= 8e-2 against the FP64 layer
+      on the same BF16 tokens and unquantised weights (the FP8 rounding
+      itself, about 6.4e-2 in an FP64 emulation at these shapes).
 """
 import numpy as np
 import pytest
@@ -129,10 +133,11 @@ def test_fp8_layer_matches_emulating_oracle(shape, config):
     np.testing.assert_array_equal(r["X_perm"].cpu().numpy(), ref["Xq"][row_map])
     np.testing.assert_array_equal(r["X_perm_scale"].cpu().numpy(), ref["Xs"][row_map])
     Y = r["Y"].float().cpu().numpy()
-    assert_close(Y, ref["Y"], 1e-2, "Y", row_tol=1e-1)
+    assert_close(Y, ref["Y"], 1e-2, "Y", row_tol=1e-1, max_tol=3e-2)
     w = r["w"].cpu().numpy()
     out_ref = ffn.combine(ref["Y"], inv_map, w)
-    assert_close(r["out"].float().cpu().numpy(), out_ref, 1e-2, "out", row_tol=1e-1)
+    assert_close(r["out"].float().cpu().numpy(), out_ref, 1e-2, "out", row_tol=1e-1,
+                 max_tol=3e-2)
     # against the unquantised FP64 layer on the same BF16 tokens and weights
     _, _, Y64 = ffn.slots_forward(h["X"], row_map, offsets, W13v, W2v)
     assert rel_fro(Y, Y64) <= 8e-2
@@ -195,4 +200,5 @@ def test_fp8_experts_config_sampled():
             hq, hs = fp8.quantize_blocks(h.astype(np.float32), 1, 128)
             y = fp8.dequantize_blocks(hq, hs, 1, 128) @ fp8.dequantize_blocks(w2q, w2s, 128, 128).T
             got = Y[int(inv[t, j])].float().cpu().numpy()
-            assert_close(got[None], y, 1e-2, f"Y of token {t}, choice {j}", row_tol=1e-1)
+            assert_close(got[None], y, 1e-2, f"Y of token {t}, choice {j}", row_tol=1e-1,
+                         max_tol=3e-2)
