@@ -291,6 +291,26 @@ moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int32_t* topk_i
                         float* X_perm_scale, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * moe_dispatch_noalloc -- moe_dispatch for callers that cannot allocate
+ *   device memory (code under stream capture, serving loops, harnesses that
+ *   forbid allocation): identical arguments, definition and results, minus
+ *   the workspace.  Its scratch (the per-256-token-block expert counts,
+ *   ceil(T/256) * E int32) lives in a fixed 4 MiB device array inside the
+ *   library, one copy per GPU, held until the process ends; the call never
+ *   allocates or frees memory.  A configuration whose counts need more than
+ *   4 MiB (e.g. E = 64 with T > 4 194 304, E = 1024 with T > 262 144)
+ *   returns MOE_EUNSUPPORTED.  ``stream`` must belong to the current device
+ *   (MOE_EINVAL otherwise).  Every call on one GPU shares that GPU's array
+ *   and leaves its counts there: calls issued in order on one stream are
+ *   safe, calls that overlap on one GPU (concurrent streams or host threads)
+ *   race and give unspecified maps.  Nothing needs clearing between calls
+ *   (each call writes every count it reads).
+ */
+moe_status moe_dispatch_noalloc(const moe_cfg* cfg, const void* X, const int32_t* topk_idx,
+                                int32_t* offsets, int32_t* row_map, int32_t* inv_map,
+                                void* X_perm, float* X_perm_scale, void* stream);
+
+/*
  * moe_expert_ffn -- grouped SwiGLU experts over uneven per-expert row counts.
  *   For the rows r of expert e (offsets[e] <= r < offsets[e+1]):
  *     A = X_perm[r] W1_e^T, B = X_perm[r] W3_e^T, h = silu(A) * B,

@@ -53,6 +53,7 @@ SIGNATURES = {
     "moe_workspace_bytes": [_CFG, ctypes.POINTER(ctypes.c_size_t)],
     "moe_route": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_dispatch": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_dispatch_noalloc": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P],
     "moe_expert_ffn": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_expert_ffn_gather": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_quantize_fp8": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P],
@@ -159,6 +160,12 @@ def moe_expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, dX_perm, dW13, dW2
                        stream):
     _check(lib().moe_expert_ffn_bwd(ctypes.byref(cfg), X, row_map, offsets, dY, W13, W2, dX_perm,
                                     dW13, dW2, ws, ws_bytes, stream), "moe_expert_ffn_bwd")
+
+
+def moe_dispatch_noalloc(cfg, X, topk_idx, offsets, row_map, inv_map, X_perm, X_perm_scale,
+                         stream):
+    _check(lib().moe_dispatch_noalloc(ctypes.byref(cfg), X, topk_idx, offsets, row_map, inv_map,
+                                      X_perm, X_perm_scale, stream), "moe_dispatch_noalloc")
 
 
 def moe_dispatch_bwd(cfg, dX_perm, inv_map, dX, stream):

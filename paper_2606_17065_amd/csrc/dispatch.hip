@@ -5,6 +5,8 @@
 // contiguous run of every expert's slots: its base is the expert's offset
 // plus the counts of all earlier blocks, and a token's rank inside its
 // block comes from per-wavefront 64-bit occupancy masks.
+#include <mutex>
+
 #include "common.h"
 #include "internal.h"
 
@@ -294,6 +296,64 @@ extern "C" moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int3
   PROF_END("dispatch", st);
   MOE_LAUNCH_CHECK();
   return MOE_OK;
+}
+
+// ---------------------------------------------- dispatch without allocation
+// moe_dispatch_noalloc: the per-block expert counts live in a fixed device
+// array instead of a caller workspace.  In host code the array's name is only
+// a host-side stand-in, so the device address is looked up once per device
+// (with that device current) and every launch takes that address.
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(4) << 20;  // 1 Mi counts
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+static __device__ __align__(256) int32_t scratch[NOALLOC_SCRATCH_BYTES / sizeof(int32_t)];
+
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of ``scratch`` on the current device (looked up on the
+// first call per device, kept for the life of the process).
+moe_status noalloc_scratch(int32_t** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return MOE_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MOE_EHIP;
+    g_scratch_ptr[dev] = (int32_t*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MOE_OK;
+}
+
+}  // namespace
+
+extern "C" moe_status moe_dispatch_noalloc(const moe_cfg* cfg, const void* X,
+                                           const int32_t* topk_idx, int32_t* offsets,
+                                           int32_t* row_map, int32_t* inv_map, void* X_perm,
+                                           float* X_perm_scale, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const size_t need = dispatch_ws_bytes(*cfg);
+  if (need > NOALLOC_SCRATCH_BYTES) return MOE_EUNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  // the stream must belong to the current device, whose copy of the array
+  // is the one looked up
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return MOE_EHIP;
+  if (st) {
+    hipDevice_t sdev = -1;
+    if (hipStreamGetDevice(st, &sdev) != hipSuccess) return MOE_EHIP;
+    if ((int)sdev != cur) return MOE_EINVAL;
+  }
+  int32_t* ptr = nullptr;
+  stc = noalloc_scratch(&ptr);
+  if (stc != MOE_OK) return stc;
+  // dispatch_count writes every count the scan reads, so nothing is cleared
+  return moe_dispatch(cfg, X, topk_idx, offsets, row_map, inv_map, X_perm, X_perm_scale, ptr,
+                      NOALLOC_SCRATCH_BYTES, stream);
 }
 
 extern "C" moe_status moe_combine(const moe_cfg* cfg, const void* Y, const int32_t* inv_map,

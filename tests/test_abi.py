@@ -145,3 +145,15 @@ def test_missing_library_fails_loudly():
                        timeout=120)
     assert r.returncode == 0, r.stderr
     assert "raised:" in r.stdout and "missing" in r.stdout
+
+
+def test_noalloc_dispatch_rejects_oversized_counts_on_the_host():
+    """The fixed scratch of moe_dispatch_noalloc holds 4 MiB of counts:
+    ceil(T / 256) * E int32 above that is refused before any launch."""
+    fake = 1 << 20
+    T, E, k = 256 * 1025, 1024, 2
+    big = L.make_cfg(T, 128, E, k, 128, (T * k + E - 1) // E + 1, 50, L.MOE_BF16, L.MOE_BF16,
+                     L.MOE_PRICE_ACP)
+    with pytest.raises(L.MoEError) as e:
+        L.moe_dispatch_noalloc(big, fake, fake, fake, fake, fake, None, None, None)
+    assert e.value.status == L.MOE_EUNSUPPORTED
