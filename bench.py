@@ -345,8 +345,11 @@ def learned_prices(args, dev, torch, L, price, layer, synth):
         def warm():
             return price.learned_route(cfg, logits, params, mode="warm")
 
+        def replace():
+            return price.learned_route(cfg, logits, params, mode="replace")
+
         res = {}
-        for name, fn in (("cold", cold), ("warm", warm)):
+        for name, fn in (("cold", cold), ("warm", warm), ("replace", replace)):
             for _ in range(2):
                 fn()
             torch.cuda.synchronize()
@@ -361,8 +364,8 @@ def learned_prices(args, dev, torch, L, price, layer, synth):
             res[name] = {"ms": e0.elapsed_time(e1) / reps,
                          "iters": int(r["info"][L.INFO_ITERS]),
                          "converged": bool(r["info"][L.INFO_CONVERGED])}
-        rr = price.learned_route(cfg, logits, params, mode="replace")
-        res["replace"] = {"violation": rr["V"], "gap_rel": rr["gap"], "fallback": rr["fallback"]}
+            if name != "cold":
+                res[name].update(price.verdict_dict(r))
         evals.append({"T": T, **res})
     return {"workload": "moe-learned-price", "E": E, "d_model": d, "top_k": k,
             "train_batches": args.price_batches, "train_steps": args.price_steps,
