@@ -76,6 +76,7 @@ typedef struct {
   int32_t w;          /* moe_dtype of expert weights */
   int32_t price_mode; /* moe_price_mode */
   float warm_gamma;   /* MOE_PRICE_WARM scale of the given prices */
+  int32_t price_stages; /* epsilon-scaled restarts after the update (0..8; 0 = none) */
 } moe_cfg;
 
 /* info[] layout written by moe_route (device int32[8]). */
@@ -107,6 +108,14 @@ moe_status moe_workspace_bytes(const moe_cfg* cfg /* host */, size_t* bytes /* h
  *       overloaded e, q = (C+1)-th largest of the margins
  *       m_t = s_te - (e in S_t ? kappa2_t : kappa1_t) and
  *       p_e = max(p_e, nextafter(q, +inf) + eps).
+ *   epsilon-scaled restarts (price-rule variant, cfg.price_stages = R > 0,
+ *     with max_iters > 0): after the update, while it ended converged with
+ *     some expert priced above zero and loaded below C (a nonzero
+ *     certificate gap) and fewer than R restarts have run: p_e =
+ *     max(+0, fl32(p_e - fl32(4 eps))) for every e, eps = fl32(eps / 8), and
+ *     the update runs again from those prices (at most max_iters updates per
+ *     run).  info reports the updates summed over the runs and the eps of
+ *     the last run.  R = 0 is the plain update.
  *   routing: topk_idx[t, 0..k-1] = S_t in rank order (best first);
  *     topk_w[t, j] = softmax over the k chosen experts of the raw logits.
  *   If the final ranking still overloads an expert, a capacity repair runs:

@@ -356,7 +356,8 @@ def route(s32, k, C, max_iters=50, p0=None, mode="acp", stages=0):
     return res
 
 
-def judged_route(s32, k, C, p_hat, mode="warm", gamma=0.9, gap_tol=5e-3, max_iters=50):
+def judged_route(s32, k, C, p_hat, mode="warm", gamma=0.9, gap_tol=5e-3, max_iters=50,
+                 stages=0):
     """Routing from learned prices, judged by the duality certificate, with
     the update from zero prices as fallback (reading stated here).
 
@@ -368,6 +369,7 @@ def judged_route(s32, k, C, p_hat, mode="warm", gamma=0.9, gap_tol=5e-3, max_ite
     duality makes this a valid bound for any routing within capacity,
     repaired ones included).  Otherwise the batch is routed by the update
     from p = 0.  A non-finite logit is reported as such, with no fallback.
+    stages > 0 adds that many epsilon-scaled restarts to both updates.
 
     Returns the dict of ``route`` for the routing kept, plus V (overflow of
     the learned ranking before any repair, divided by N = T k), gap_learned,
@@ -376,7 +378,7 @@ def judged_route(s32, k, C, p_hat, mode="warm", gamma=0.9, gap_tol=5e-3, max_ite
     T, E = s32.shape
     ph = np.asarray(p_hat, dtype=F32)
     if mode == "warm":
-        r = route(s32, k, C, max_iters, (F32(gamma) * ph).astype(F32), "acp")
+        r = route(s32, k, C, max_iters, (F32(gamma) * ph).astype(F32), "acp", stages)
     elif mode == "replace":
         r = route(s32, k, C, 0, ph, "given")
     else:
@@ -399,7 +401,7 @@ def judged_route(s32, k, C, p_hat, mode="warm", gamma=0.9, gap_tol=5e-3, max_ite
         extra["gap_learned"] = rel_gap(r)
         extra["kept"] = extra["gap_learned"] <= gap_tol
     if not extra["kept"]:
-        r = route(s32, k, C, max_iters, None, "acp")
+        r = route(s32, k, C, max_iters, None, "acp", stages)
     if r["status"] == OK:
         extra["gap"] = rel_gap(r)
     return {**r, **extra}

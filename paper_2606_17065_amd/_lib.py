@@ -35,6 +35,7 @@ class MoeCfg(ctypes.Structure):
         ("k", ctypes.c_int32), ("d_ff", ctypes.c_int32), ("capacity", ctypes.c_int32),
         ("max_iters", ctypes.c_int32), ("act", ctypes.c_int32), ("w", ctypes.c_int32),
         ("price_mode", ctypes.c_int32), ("warm_gamma", ctypes.c_float),
+        ("price_stages", ctypes.c_int32),
     ]
 
 
@@ -110,8 +111,9 @@ def _check(status: int, where: str) -> None:
 
 
 def make_cfg(T, d, E, k, d_ff, capacity, max_iters=50, act=MOE_BF16, w=MOE_BF16,
-             price_mode=MOE_PRICE_ACP, warm_gamma=0.9) -> MoeCfg:
-    return MoeCfg(T, d, E, k, d_ff, capacity, max_iters, act, w, price_mode, warm_gamma)
+             price_mode=MOE_PRICE_ACP, warm_gamma=0.9, price_stages=0) -> MoeCfg:
+    return MoeCfg(T, d, E, k, d_ff, capacity, max_iters, act, w, price_mode, warm_gamma,
+                  price_stages)
 
 
 def moe_workspace_bytes(cfg: MoeCfg) -> int:

@@ -24,6 +24,7 @@ moe_status check_cfg_shape(const moe_cfg* c) {
     return MOE_EINVAL;
   if (c->act != MOE_F32 && c->act != MOE_BF16) return MOE_EINVAL;
   if (c->w != MOE_F32 && c->w != MOE_BF16 && c->w != MOE_FP8E4M3) return MOE_EINVAL;
+  if (c->price_stages < 0 || c->price_stages > 8) return MOE_EINVAL;
   if (c->k > c->E) return MOE_EINFEASIBLE;
   if ((int64_t)c->E * (int64_t)c->capacity < (int64_t)c->T * (int64_t)c->k) return MOE_EINFEASIBLE;
   if (c->E > 1024 || c->k > 16) return MOE_EUNSUPPORTED;

@@ -29,6 +29,9 @@ enum {
   ST_NEED_REPAIR = 8,
   ST_REPAIRED = 9,
   ST_SKIP_WEIGHTS = 10,  // the final routing is already in place (judged routing kept)
+  ST_ITERS_PREV = 11,    // updates of the finished runs (epsilon-scaled restarts)
+  ST_STAGE_STOP = 12,    // no further epsilon-scaled restart runs
+  ST_EPS0 = 13,          // float bits: the first run's increment
   ST_LEN = 16
 };
 

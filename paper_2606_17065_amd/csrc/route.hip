@@ -310,6 +310,7 @@ __global__ __launch_bounds__(SIG_BLOCK) void score_sigma(const double* part, int
     float eps = 1.0e-3f * sigma;
     state[ST_SIGMA] = __float_as_int(sigma);
     state[ST_EPS] = __float_as_int(eps);
+    state[ST_EPS0] = __float_as_int(eps);
   }
 }
 
@@ -812,6 +813,53 @@ __global__ __launch_bounds__(SEL_THREADS) void acp_select(
   select_update(col, kk, cached, T, C, e, price, __int_as_float(state[ST_EPS]), sc, red);
 }
 
+// --------------------------------------------- epsilon-scaled restarts
+// Between two runs of the price update.  When the previous run converged
+// and some expert is priced above zero yet below capacity (a nonzero
+// certificate gap), every price is lowered by four increments (a result
+// that is not positive becomes +0), the increment is divided by eight and
+// the update runs again from those prices; otherwise every later run is
+// skipped.  The updates of finished runs are summed in ST_ITERS_PREV.
+__global__ __launch_bounds__(256) void scaled_restart(int32_t* __restrict__ state,
+                                                      float* __restrict__ price,
+                                                      const int32_t* __restrict__ load, int E,
+                                                      int C) {
+  __shared__ int slack, go;
+  __shared__ float eps_s;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    slack = 0;
+    eps_s = __int_as_float(state[ST_EPS]);
+  }
+  __syncthreads();
+  const bool active =
+      !state[ST_STAGE_STOP] && state[ST_STATUS] == MOE_OK && state[ST_CONVERGED] != 0;
+  if (active)
+    for (int e = tid; e < E; e += blockDim.x)
+      if (price[e] != 0.0f && load[e] != C) slack = 1;
+  __syncthreads();
+  if (tid == 0) go = active && slack;
+  __syncthreads();
+  if (!go) {
+    if (tid == 0) state[ST_STAGE_STOP] = 1;
+    return;
+  }
+  const float back = 4.0f * eps_s;
+  for (int e = tid; e < E; e += blockDim.x) {
+    const float lowered = price[e] - back;
+    price[e] = lowered > 0.0f ? lowered : 0.0f;
+  }
+  if (tid == 0) {
+    state[ST_ITERS_PREV] += state[ST_ITERS];
+    state[ST_ITERS] = 0;
+    state[ST_CONVERGED] = 0;
+    state[ST_OVERFLOW] = 0;
+    state[ST_NEED_REPAIR] = 0;
+    state[ST_EPS] = __float_as_int(eps_s / 8.0f);
+    state[ST_DONE] = 0;
+  }
+}
+
 // ----------------------------------------------------- capacity repair
 // Single block; runs only when the price loop ended with an overloaded
 // expert.  Bitmasks of W = ceil(E/32) words per token live in the workspace.
@@ -1027,7 +1075,7 @@ __global__ void route_finalize(const int32_t* state, int32_t* info, int32_t* loa
   else if (state[ST_STATUS] == MOE_ENAN)
     for (int e = tid; e < E; e += blockDim.x) load_out[e] = e < k ? T : 0;
   if (tid == 0) {
-    info[MOE_INFO_ITERS] = state[ST_ITERS];
+    info[MOE_INFO_ITERS] = state[ST_ITERS] + state[ST_ITERS_PREV];
     info[MOE_INFO_CONVERGED] = empty ? 1 : state[ST_CONVERGED];
     info[MOE_INFO_OVERFLOW] = state[ST_OVERFLOW];
     info[MOE_INFO_STATUS] = state[ST_STATUS];
@@ -1083,7 +1131,11 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
   constexpr int RW = L <= 9 ? 8 : 4;
   const int per = (E + RW - 1) / RW;
   // one ranking and one update kernel per iteration, each exiting at once
-  // after the loop has stopped
+  // after the loop has stopped; epsilon-scaled restarts repeat the loop
+  const int stages = max_iters > 0 ? c.price_stages : 0;
+  for (int stage = 0; stage <= stages; ++stage) {
+  if (stage > 0)
+    hipLaunchKernelGGL(scaled_restart, dim3(1), dim3(256), 0, st, ws.state, price, load, E, C);
   for (int it = 0; it <= max_iters; ++it) {
     const dim3 rb(64 * RW * TG);
     if (per <= 4)
@@ -1103,6 +1155,7 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
                          price, T, E, k, ws.state, ws.mT, idx, ws.cnt);
     hipLaunchKernelGGL(acp_select, dim3(E), dim3(SEL_THREADS), 0, st, ws.mT, price, T, E, C, it,
                        max_iters, nblk, ws.cnt, ws.state, load);
+  }
   }
   hipLaunchKernelGGL(route_weights, dim3((T + 255) / 256), dim3(256), 0, st, logits, idx, T, E, k,
                      ws.state, w);
@@ -1309,11 +1362,12 @@ __global__ void judge_decide(const double* __restrict__ cert, int32_t* state,
     verdict[0] = (double)state[ST_OVERFLOW] / (double)(N > 0 ? N : 1);
     verdict[1] = status == MOE_OK ? gap : __builtin_nan("");
     verdict[2] = ok ? 1.0 : 0.0;
-    verdict[4] = (double)state[ST_ITERS];
+    verdict[4] = (double)(state[ST_ITERS] + state[ST_ITERS_PREV]);
     if (keep) {
       state[ST_DONE] = 1;
       state[ST_NEED_REPAIR] = 0;
       state[ST_SKIP_WEIGHTS] = 1;
+      state[ST_STAGE_STOP] = 1;
     } else {
       state[ST_DONE] = 0;
       state[ST_CONVERGED] = 0;
@@ -1324,6 +1378,9 @@ __global__ void judge_decide(const double* __restrict__ cert, int32_t* state,
       state[ST_NEED_REPAIR] = 0;
       state[ST_REPAIRED] = 0;
       state[ST_SKIP_WEIGHTS] = 0;
+      state[ST_ITERS_PREV] = 0;
+      state[ST_STAGE_STOP] = 0;
+      state[ST_EPS] = state[ST_EPS0];
     }
     keep_s = keep;
   }

@@ -224,7 +224,8 @@ def judged_route(cfg, logits, phat, mode="warm", gamma=0.9, gap_tol=GAP_TOL, ws=
     if mode not in ("warm", "replace"):
         raise ValueError(f"unknown mode {mode!r}")
     pm = L.MOE_PRICE_WARM if mode == "warm" else L.MOE_PRICE_GIVEN
-    c = L.make_cfg(T, cfg.d, E, k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act, cfg.w, pm, gamma)
+    c = L.make_cfg(T, cfg.d, E, k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act, cfg.w, pm, gamma,
+                   cfg.price_stages)
     dev = logits.device
     out = dict(price=torch.empty(E, dtype=torch.float32, device=dev),
                idx=torch.empty(T, k, dtype=torch.int32, device=dev),

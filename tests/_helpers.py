@@ -99,7 +99,7 @@ def replica_route(cfg, logits32, price_in=None):
     elif mode == L.MOE_PRICE_WARM:
         p0 = (F32(cfg.warm_gamma) * np.asarray(price_in, F32)).astype(F32)
     iters = cfg.max_iters if mode in (L.MOE_PRICE_ACP, L.MOE_PRICE_WARM) else 0
-    return R.route(logits32, cfg.k, cfg.capacity, iters, p0, MODE_NAME[mode])
+    return R.route(logits32, cfg.k, cfg.capacity, iters, p0, MODE_NAME[mode], cfg.price_stages)
 
 
 def assert_route_matches(cfg, r_gpu, ref):

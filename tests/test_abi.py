@@ -157,3 +157,12 @@ def test_noalloc_dispatch_rejects_oversized_counts_on_the_host():
     with pytest.raises(L.MoEError) as e:
         L.moe_dispatch_noalloc(big, fake, fake, fake, fake, fake, None, None, None)
     assert e.value.status == L.MOE_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("stages", [-1, 9])
+def test_price_stages_out_of_range_rejected(stages):
+    cfg = _cfg()
+    cfg.price_stages = stages
+    with pytest.raises(L.MoEError) as e:
+        L.moe_workspace_bytes(cfg)
+    assert e.value.status == L.MOE_EINVAL

@@ -327,17 +327,19 @@ def _assert_judged(cfg, r, s, phat, mode, tol, gamma=0.9):
     """The judged routing against the oracle's: the keep-or-fallback
     decision, the routing returned (bit-exact against the FP32 replica of
     the pass that produced it) and the verdict."""
-    ref = R.judged_route(s, cfg.k, cfg.capacity, phat, mode, gamma, tol, cfg.max_iters)
+    ref = R.judged_route(s, cfg.k, cfg.capacity, phat, mode, gamma, tol, cfg.max_iters,
+                         cfg.price_stages)
     v = P.verdict_dict(r)
     assert v["kept"] == ref["kept"], (v, ref["gap_learned"])
     if ref["kept"]:
         pm = L.MOE_PRICE_WARM if mode == "warm" else L.MOE_PRICE_GIVEN
         c = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity,
-                       cfg.max_iters if mode == "warm" else 0, cfg.act, cfg.w, pm, gamma)
+                       cfg.max_iters if mode == "warm" else 0, cfg.act, cfg.w, pm, gamma,
+                       cfg.price_stages)
         assert_route_matches(c, r, replica_route(c, s, phat))
     else:
         c = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act,
-                       cfg.w, L.MOE_PRICE_ACP)
+                       cfg.w, L.MOE_PRICE_ACP, 0.9, cfg.price_stages)
         assert_route_matches(c, r, replica_route(c, s))
     assert v["V"] == ref["V"]
     assert v["learned_iters"] == ref["learned_iters"]
