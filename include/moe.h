@@ -292,8 +292,9 @@ moe_status moe_adam_step(int n, float* params, const float* grads, float* m, flo
  *   FP8 experts (cfg.w == MOE_FP8E4M3, d % 128 == 0): every token row is
  *   quantised per 1 x 128 block as moe_quantize_fp8 does and X_perm [N,d]
  *   u8 receives the codes, X_perm_scale [N, d/128] f32 the scales (NULL
- *   otherwise).  Other dtypes: X_perm may be NULL, in which case only the
- *   maps are written (for moe_expert_ffn_gather, which gathers itself).
+ *   otherwise).  X_perm may be NULL (any dtype), in which case only the
+ *   maps are written (for moe_expert_ffn_gather and
+ *   moe_expert_ffn_gather_fp8, which gather the token rows themselves).
  */
 moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int32_t* topk_idx,
                         int32_t* offsets, int32_t* row_map, int32_t* inv_map, void* X_perm,
@@ -355,6 +356,25 @@ moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm, const float* X
 moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X, const int32_t* row_map,
                                  const int32_t* offsets, const void* W13, const void* W2, void* Y,
                                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * moe_expert_ffn_gather_fp8 -- the FP8-expert moe_expert_ffn with the permute
+ *   fused into the first product: slot row r reads token row row_map[r] of
+ *   the per-token codes X_codes [T,d] u8 and scales X_scale [T, d/128] f32
+ *   (X quantised once per token, as moe_quantize_fp8 with block_rows = 1
+ *   writes it), so no slot-ordered copy of the codes is made.  Same
+ *   definition and results, bit for bit, as moe_dispatch (FP8) followed by
+ *   moe_expert_ffn.  Requires cfg.act = MOE_BF16, cfg.w = MOE_FP8E4M3,
+ *   d % 128 == 0 and d_ff % 128 == 0 (else MOE_EUNSUPPORTED).  row_map [N]
+ *   and offsets [E+1] as moe_dispatch writes them; weights and Y as in
+ *   moe_expert_ffn.
+ */
+moe_status moe_expert_ffn_gather_fp8(const moe_cfg* cfg, const uint8_t* X_codes,
+                                     const float* X_scale, const int32_t* row_map,
+                                     const int32_t* offsets, const uint8_t* W13,
+                                     const float* W13_scale, const uint8_t* W2,
+                                     const float* W2_scale, void* Y, void* ws, size_t ws_bytes,
+                                     void* stream);
 
 /*
  * moe_quantize_fp8 -- OCP FP8 e4m3 block quantisation of src [rows, cols]

@@ -57,6 +57,7 @@ SIGNATURES = {
     "moe_dispatch_noalloc": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P],
     "moe_expert_ffn": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_expert_ffn_gather": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_expert_ffn_gather_fp8": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_quantize_fp8": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P],
     "moe_combine": [_CFG, _P, _P, _P, _P, _P],
     "moe_combine_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P],
@@ -137,6 +138,13 @@ def moe_expert_ffn(cfg, X_perm, X_perm_scale, offsets, W13, W13_scale, W2, W2_sc
                    ws_bytes, stream):
     _check(lib().moe_expert_ffn(ctypes.byref(cfg), X_perm, X_perm_scale, offsets, W13, W13_scale,
                                 W2, W2_scale, Y, ws, ws_bytes, stream), "moe_expert_ffn")
+
+
+def moe_expert_ffn_gather_fp8(cfg, X_codes, X_scale, row_map, offsets, W13, W13_scale, W2,
+                              W2_scale, Y, ws, ws_bytes, stream):
+    _check(lib().moe_expert_ffn_gather_fp8(ctypes.byref(cfg), X_codes, X_scale, row_map, offsets,
+                                           W13, W13_scale, W2, W2_scale, Y, ws, ws_bytes, stream),
+           "moe_expert_ffn_gather_fp8")
 
 
 def moe_expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, Y, ws, ws_bytes, stream):

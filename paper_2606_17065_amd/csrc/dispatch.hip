@@ -256,10 +256,9 @@ extern "C" moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int3
   const bool fp8 = c.w == MOE_FP8E4M3;
   if (!offsets) return MOE_EINVAL;
   if (c.T > 0 && (!topk_idx || !row_map || !inv_map)) return MOE_EINVAL;
-  if (c.T > 0 && (fp8 || X_perm) && !X) return MOE_EINVAL;
-  if (c.T > 0 && fp8 && !X_perm) return MOE_EINVAL;
-  if (fp8 && c.d % 128 != 0) return MOE_EUNSUPPORTED;
-  if (fp8 && c.T > 0 && !X_perm_scale) return MOE_EINVAL;
+  if (c.T > 0 && X_perm && !X) return MOE_EINVAL;
+  if (fp8 && X_perm && c.d % 128 != 0) return MOE_EUNSUPPORTED;
+  if (fp8 && c.T > 0 && X_perm && !X_perm_scale) return MOE_EINVAL;
   if (!aligned(X_perm_scale, 4)) return MOE_EINVAL;
   if (!aligned(X, 16) || !aligned(X_perm, 16) || !aligned(topk_idx, 4) || !aligned(offsets, 4) ||
       !aligned(row_map, 4) || !aligned(inv_map, 4))
@@ -283,6 +282,8 @@ extern "C" moe_status moe_dispatch(const moe_cfg* cfg, const void* X, const int3
         hipLaunchKernelGGL(dispatch_gather, dim3((c.T + 3) / 4), dim3(256), 0, st,
                            (const u32x4*)X, c.T, row_vec, c.k, inv_map, (u32x4*)X_perm);
       }
+    } else if (!X_perm) {
+      // maps only (moe_expert_ffn_gather_fp8 reads the per-token codes)
     } else if (c.act == MOE_BF16) {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_gather_fp8<bf16_t>), dim3((c.T + 3) / 4),
                          dim3(256), 0, st, (const bf16_t*)X, c.T, c.d, c.k, inv_map,

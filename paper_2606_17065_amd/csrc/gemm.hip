@@ -623,16 +623,19 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 // v_mfma_f32_32x32x64_f8f6f4 accumulate the block on its own, which is then
 // promoted into the FP32 result: acc += partial * (sa * sb).  A lane holds
 // one token row of each tile, so sa is one value per row tile and sb one
-// value per column tile (wavefront-uniform).
+// value per column tile (wavefront-uniform).  GATHER: token row r of the A
+// operand (codes and scales) is row row_map[r] of the per-token arrays
+// (the permute fused into the operand DMA).
 constexpr int F8_STAGE_A = GBM * 128, F8_STAGE_B = GBN * 128;
 constexpr int F8_STAGE = F8_STAGE_A + F8_STAGE_B;
 constexpr int F8_NSTAGE = 3;
 constexpr int F8_LDS = F8_NSTAGE * F8_STAGE > EPI_BYTES ? F8_NSTAGE * F8_STAGE : EPI_BYTES;
 constexpr int F8_A_INS = GBM * 128 / 1024 / 4, F8_B_INS = GBN * 128 / 1024 / 4;
 
-template <int EPI>
+template <int EPI, bool GATHER>
 __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
-    const fp8_t* __restrict__ A, const float* __restrict__ As, const fp8_t* __restrict__ B,
+    const fp8_t* __restrict__ A, const float* __restrict__ As,
+    const int32_t* __restrict__ row_map, int T, const fp8_t* __restrict__ B,
     const float* __restrict__ Bs, bf16_t* __restrict__ C, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ tile_start, int E, int N, int K, int f, int Ncols, int n_tiles,
     int grid_total) {
@@ -658,7 +661,9 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   for (int i = 0; i < F8_A_INS; ++i) {
     const int R = wv * (GBM / 4) + i * 8 + (lane >> 3);
     const int c = (lane & 7) ^ ((R >> 1) & 7);
-    asrc[i] = A + (size_t)(row0 + min(R, rows - 1)) * K + c * 16;
+    const int r = row0 + min(R, rows - 1);
+    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
+    asrc[i] = A + arow * K + c * 16;
   }
 #pragma unroll
   for (int i = 0; i < F8_B_INS; ++i) {
@@ -685,8 +690,11 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   // of the wavefront's two column tiles
   const float* sa_row[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    sa_row[i] = As + (size_t)(row0 + min(wm * 128 + i * 32 + fr, rows - 1)) * nkb;
+  for (int i = 0; i < 4; ++i) {
+    const int r = row0 + min(wm * 128 + i * 32 + fr, rows - 1);
+    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
+    sa_row[i] = As + arow * nkb;
+  }
   const int wr0 = PAIRED ? n0 + wn * 32 : n0 + wn * 64;
   const int wr1 = PAIRED ? f + n0 + wn * 32 : n0 + wn * 64 + 32;
   const float* sb_row0 = Bs + ((size_t)e * (Brows_e / 128) + wr0 / 128) * nkb;
@@ -820,13 +828,15 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   }
 }
 
-#define MOE_INST_F8(EPI)                                                                     \
-  template __global__ void gemm_fp8_big<EPI>(                                                \
-      const fp8_t* __restrict__, const float* __restrict__, const fp8_t* __restrict__,       \
-      const float* __restrict__, bf16_t* __restrict__, const int32_t* __restrict__,          \
-      const int32_t* __restrict__, int, int, int, int, int, int, int);
-MOE_INST_F8(EPI_SWIGLU)
-MOE_INST_F8(EPI_PLAIN)
+#define MOE_INST_F8(EPI, GATHER)                                                             \
+  template __global__ void gemm_fp8_big<EPI, GATHER>(                                        \
+      const fp8_t* __restrict__, const float* __restrict__, const int32_t* __restrict__, int, \
+      const fp8_t* __restrict__, const float* __restrict__, bf16_t* __restrict__,            \
+      const int32_t* __restrict__, const int32_t* __restrict__, int, int, int, int, int, int, \
+      int);
+MOE_INST_F8(EPI_SWIGLU, false)
+MOE_INST_F8(EPI_SWIGLU, true)
+MOE_INST_F8(EPI_PLAIN, false)
 #undef MOE_INST_F8
 
 // ------------------------------------------------------------- backward
@@ -1198,6 +1208,44 @@ size_t ffn_ws_bytes(const moe_cfg& c) {
   return total;
 }
 
+namespace moe_gemm {
+
+// The FP8 expert products: GEMM 1 + SwiGLU (token rows gathered through
+// row_map when it is given), the 1 x 128 quantisation of h, GEMM 2.
+void launch_fp8_ffn(const moe_cfg& c, const FfnWs& w, const fp8_t* Aq, const float* As,
+                    const int32_t* row_map, const int32_t* offsets, const fp8_t* W13,
+                    const float* W13_scale, const fp8_t* W2, const float* W2_scale, bf16_t* Y,
+                    hipStream_t st) {
+  const int N = c.T * c.k;
+  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
+  const int mt_big = (N + GBM - 1) / GBM + c.E;
+  const int nt1 = c.d_ff / 64;
+  const int G1 = (mt_big * nt1 + 7) / 8 * 8;
+  PROF_BEGIN("gemm1_swiglu", st);
+  if (row_map)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_SWIGLU, true>), dim3(G1), dim3(256), 0,
+                       st, Aq, As, row_map, c.T, W13, W13_scale, (bf16_t*)w.h, offsets,
+                       w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt1, G1);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_SWIGLU, false>), dim3(G1), dim3(256), 0,
+                       st, Aq, As, nullptr, 0, W13, W13_scale, (bf16_t*)w.h, offsets,
+                       w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt1, G1);
+  PROF_END("gemm1_swiglu", st);
+  PROF_BEGIN("quant_h", st);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_rows<bf16_t>), dim3((N + 3) / 4), dim3(256), 0, st,
+                     (const bf16_t*)w.h, N, c.d_ff, w.hq, w.hs);
+  PROF_END("quant_h", st);
+  const int nt2 = c.d / 128;
+  const int G2 = (mt_big * nt2 + 7) / 8 * 8;
+  PROF_BEGIN("gemm2", st);
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_PLAIN, false>), dim3(G2), dim3(256), 0, st,
+                     (const fp8_t*)w.hq, (const float*)w.hs, nullptr, 0, W2, W2_scale, Y, offsets,
+                     w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt2, G2);
+  PROF_END("gemm2", st);
+}
+
+}  // namespace moe_gemm
+
 extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
                                      const float* X_perm_scale, const int32_t* offsets,
                                      const void* W13, const float* W13_scale, const void* W2,
@@ -1225,28 +1273,8 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
   FfnWs w = carve_ffn(c, ws, nullptr);
   const int N = c.T * c.k;
   if (fp8path) {
-    hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
-    const int mt_big = (N + GBM - 1) / GBM + c.E;
-    const int nt1 = c.d_ff / 64;
-    const int G1 = (mt_big * nt1 + 7) / 8 * 8;
-    PROF_BEGIN("gemm1_swiglu", st);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_SWIGLU>), dim3(G1), dim3(256), 0, st,
-                       (const fp8_t*)X_perm, X_perm_scale, (const fp8_t*)W13, W13_scale,
-                       (bf16_t*)w.h, offsets, w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt1,
-                       G1);
-    PROF_END("gemm1_swiglu", st);
-    PROF_BEGIN("quant_h", st);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_rows<bf16_t>), dim3((N + 3) / 4), dim3(256), 0,
-                       st, (const bf16_t*)w.h, N, c.d_ff, w.hq, w.hs);
-    PROF_END("quant_h", st);
-    const int nt2 = c.d / 128;
-    const int G2 = (mt_big * nt2 + 7) / 8 * 8;
-    PROF_BEGIN("gemm2", st);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_PLAIN>), dim3(G2), dim3(256), 0, st,
-                       (const fp8_t*)w.hq, (const float*)w.hs, (const fp8_t*)W2, W2_scale,
-                       (bf16_t*)Y, offsets, w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt2,
-                       G2);
-    PROF_END("gemm2", st);
+    launch_fp8_ffn(c, w, (const fp8_t*)X_perm, X_perm_scale, nullptr, offsets, (const fp8_t*)W13,
+                   W13_scale, (const fp8_t*)W2, W2_scale, (bf16_t*)Y, st);
   } else if (bf16path) {
     // 256-row tiles (d_ff % 64 == 0 and d % 128 == 0 were checked above):
     // 256 x 256 where d_ff % 128 (GEMM 1) or d % 256 (GEMM 2) allows it,
@@ -1434,12 +1462,14 @@ extern "C" moe_status moe_quantize_fp8(int rows, int cols, int block_rows, int s
   if (!aligned(src, 16) || !aligned(codes, 8) || !aligned(scales, 4)) return MOE_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   if (block_rows == 1) {
+    PROF_BEGIN("quant_rows", st);
     if (src_dtype == MOE_BF16)
       hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_rows<bf16_t>), dim3((rows + 3) / 4), dim3(256),
                          0, st, (const bf16_t*)src, rows, cols, codes, scales);
     else
       hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_rows<float>), dim3((rows + 3) / 4), dim3(256),
                          0, st, (const float*)src, rows, cols, codes, scales);
+    PROF_END("quant_rows", st);
   } else {
     const dim3 g(cols / 128, (rows + 127) / 128);
     if (src_dtype == MOE_BF16)
@@ -1492,6 +1522,33 @@ extern "C" moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X,
                        offsets, w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt, G);
     PROF_END("gemm2", st);
   }
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_expert_ffn_gather_fp8(const moe_cfg* cfg, const uint8_t* X_codes,
+                                                const float* X_scale, const int32_t* row_map,
+                                                const int32_t* offsets, const uint8_t* W13,
+                                                const float* W13_scale, const uint8_t* W2,
+                                                const float* W2_scale, void* Y, void* ws,
+                                                size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.act != MOE_BF16 || c.w != MOE_FP8E4M3) return MOE_EUNSUPPORTED;
+  if (c.d_ff % 128 != 0 || c.d % 128 != 0) return MOE_EUNSUPPORTED;
+  if (!offsets || !W13 || !W2 || !W13_scale || !W2_scale) return MOE_EINVAL;
+  if (c.T > 0 && (!X_codes || !X_scale || !row_map || !Y)) return MOE_EINVAL;
+  if (!aligned(X_codes, 16) || !aligned(X_scale, 4) || !aligned(W13, 16) || !aligned(W2, 16) ||
+      !aligned(Y, 16) || !aligned(offsets, 4) || !aligned(row_map, 4) ||
+      !aligned(W13_scale, 4) || !aligned(W2_scale, 4))
+    return MOE_EINVAL;
+  if (ws_bytes < ffn_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  if (c.T == 0) return MOE_OK;
+  hipStream_t st = (hipStream_t)stream;
+  FfnWs w = carve_ffn(c, ws, nullptr);
+  launch_fp8_ffn(c, w, (const fp8_t*)X_codes, X_scale, row_map, offsets, (const fp8_t*)W13,
+                 W13_scale, (const fp8_t*)W2, W2_scale, (bf16_t*)Y, st);
   MOE_LAUNCH_CHECK();
   return MOE_OK;
 }

@@ -87,7 +87,6 @@ def dispatch(cfg, X, idx, ws=None, permute=True):
     _need(idx, "topk_idx", torch.int32, (T, k))
     dev = X.device
     fp8 = cfg.w == L.MOE_FP8E4M3
-    permute = permute or fp8
     out = dict(offsets=torch.empty(E + 1, dtype=torch.int32, device=dev),
                row_map=torch.empty(T * k, dtype=torch.int32, device=dev),
                inv_map=torch.empty(T, k, dtype=torch.int32, device=dev),
@@ -176,6 +175,32 @@ def expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, ws=None):
     return Y
 
 
+def gather_fused_fp8(cfg) -> bool:
+    """True when the FP8 expert products can read per-token codes through
+    row_map."""
+    return (cfg.act == L.MOE_BF16 and cfg.w == L.MOE_FP8E4M3 and cfg.d_ff % 128 == 0
+            and cfg.d % 128 == 0)
+
+
+def expert_ffn_gather_fp8(cfg, X_codes, X_scale, row_map, offsets, W13, W2, W13_scale, W2_scale,
+                          ws=None):
+    N, d, E, f = cfg.T * cfg.k, cfg.d, cfg.E, cfg.d_ff
+    _need(X_codes, "X_codes", torch.uint8, (cfg.T, d))
+    _need(X_scale, "X_scale", torch.float32, (cfg.T, d // 128))
+    _need(row_map, "row_map", torch.int32, (N,))
+    _need(offsets, "offsets", torch.int32, (E + 1,))
+    _need(W13, "W13", torch.uint8, (E, 2 * f, d))
+    _need(W2, "W2", torch.uint8, (E, d, f))
+    _need(W13_scale, "W13_scale", torch.float32, (E, 2 * f // 128, d // 128))
+    _need(W2_scale, "W2_scale", torch.float32, (E, d // 128, f // 128))
+    Y = torch.empty(N, d, dtype=torch.bfloat16, device=X_codes.device)
+    ws = _WS.get(cfg, X_codes.device) if ws is None else ws
+    L.moe_expert_ffn_gather_fp8(cfg, _p(X_codes), _p(X_scale), _p(row_map), _p(offsets), _p(W13),
+                                _p(W13_scale), _p(W2), _p(W2_scale), _p(Y), _p(ws), ws.numel(),
+                                _stream())
+    return Y
+
+
 def check_status(info, where="moe_route"):
     """Raise MoEError if a routing's device status (info[MOE_INFO_STATUS]) is
     not MOE_OK.  Reads the value on the host, so it waits for the stream."""
@@ -198,6 +223,13 @@ def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None, 
     if fuse and gather_fused(cfg):
         dsp = dispatch(cfg, X, r["idx"], permute=False)
         Y = expert_ffn_gather(cfg, X, dsp["row_map"], dsp["offsets"], W13, W2)
+    elif fuse and gather_fused_fp8(cfg):
+        # tokens quantised once (1 x 128 blocks), gathered by the first product
+        Xq, Xs = quantize_fp8(X, 1)
+        dsp = dispatch(cfg, X, r["idx"], permute=False)
+        Y = expert_ffn_gather_fp8(cfg, Xq, Xs, dsp["row_map"], dsp["offsets"], W13, W2,
+                                  W13_scale, W2_scale)
+        r["X_codes"], r["X_scale"] = Xq, Xs
     else:
         dsp = dispatch(cfg, X, r["idx"])
         Y = expert_ffn(cfg, dsp["X_perm"], dsp["offsets"], W13, W2, W13_scale, W2_scale,

@@ -129,10 +129,21 @@ def test_fp8_layer_matches_emulating_oracle(shape, config):
     np.testing.assert_array_equal(q13.cpu().numpy(), oq13)
     np.testing.assert_array_equal(s2.cpu().numpy(), os2)
     ref = fp8.slots_forward_fp8(h["X"], row_map, offsets, oq13, os13, oq2, os2)
-    # token codes and scales in slot order: bit-exact
-    np.testing.assert_array_equal(r["X_perm"].cpu().numpy(), ref["Xq"][row_map])
-    np.testing.assert_array_equal(r["X_perm_scale"].cpu().numpy(), ref["Xs"][row_map])
+    # token codes and scales (quantised once per token, gathered by GEMM 1):
+    # bit-exact
+    assert r["X_perm"] is None
+    np.testing.assert_array_equal(r["X_codes"].cpu().numpy(), ref["Xq"])
+    np.testing.assert_array_equal(r["X_scale"].cpu().numpy(), ref["Xs"])
     Y = r["Y"].float().cpu().numpy()
+    # the unfused path (slot-ordered codes written by the dispatch, then
+    # the expert products) gives the same codes and the same Y bit for bit
+    u = layer.forward(cfg, d["X"], d["Wr"], d["br"], q13, q2, W13_scale=s13, W2_scale=s2,
+                      fuse=False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u["X_perm"].cpu().numpy(), ref["Xq"][row_map])
+    np.testing.assert_array_equal(u["X_perm_scale"].cpu().numpy(), ref["Xs"][row_map])
+    np.testing.assert_array_equal(u["Y"].view(torch.int16).cpu().numpy(),
+                                  r["Y"].view(torch.int16).cpu().numpy())
     assert_close(Y, ref["Y"], 1e-2, "Y", row_tol=1e-1, max_tol=3e-2)
     w = r["w"].cpu().numpy()
     out_ref = ffn.combine(ref["Y"], inv_map, w)
@@ -141,6 +152,23 @@ def test_fp8_layer_matches_emulating_oracle(shape, config):
     # against the unquantised FP64 layer on the same BF16 tokens and weights
     _, _, Y64 = ffn.slots_forward(h["X"], row_map, offsets, W13v, W2v)
     assert rel_fro(Y, Y64) <= 8e-2
+
+
+def test_fp8_gather_ffn_rejects_bad_arguments():
+    shape = synth.MoEShape("fp8-bad", T=64, d=192, E=4, k=2, f=256, zipf=1.0, act="bf16", w="fp8")
+    x = torch.zeros(128, 256, dtype=torch.uint8, device="cuda")
+    p = x.data_ptr()
+    with pytest.raises(L.MoEError) as e:  # d % 128 != 0
+        L.moe_expert_ffn_gather_fp8(cfg_for(shape), p, p, p, p, p, p, p, p, p, p, 1 << 30, 0)
+    assert e.value.status == L.MOE_EUNSUPPORTED
+    ok = synth.MoEShape("fp8-ok", T=64, d=256, E=4, k=2, f=256, zipf=1.0, act="bf16", w="fp8")
+    with pytest.raises(L.MoEError) as e:  # no scales for the token codes
+        L.moe_expert_ffn_gather_fp8(cfg_for(ok), p, None, p, p, p, p, p, p, p, p, 1 << 30, 0)
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:  # BF16 experts take moe_expert_ffn_gather
+        L.moe_expert_ffn_gather_fp8(cfg_for(dataclass_bf16(ok)), p, p, p, p, p, p, p, p, p, p,
+                                    1 << 30, 0)
+    assert e.value.status == L.MOE_EUNSUPPORTED
 
 
 def test_fp8_ffn_rejects_unaligned_widths():
@@ -184,9 +212,8 @@ def test_fp8_experts_config_sampled():
     for t in (0, shape.T - 1):
         xt = X[t:t + 1].float().cpu().numpy()
         xq, xs = fp8.quantize_blocks(xt, 1, 128)
-        slot = int(inv[t, 0])
-        np.testing.assert_array_equal(r["X_perm"][slot].cpu().numpy(), xq[0])
-        np.testing.assert_array_equal(r["X_perm_scale"][slot].cpu().numpy(), xs[0])
+        np.testing.assert_array_equal(r["X_codes"][t].cpu().numpy(), xq[0])
+        np.testing.assert_array_equal(r["X_scale"][t].cpu().numpy(), xs[0])
         xd = fp8.dequantize_blocks(xq, xs, 1, 128)
         for j in (0, shape.k - 1):
             e = int(sel[t, j])
