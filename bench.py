@@ -52,9 +52,13 @@ def parse():
     ap.add_argument("--cpu-tokens", type=int, default=-1,
                     help="tokens in the oracle's timed sample (-1 = the whole batch, 0 = skip)")
     ap.add_argument("--fp8", type=int, default=1, help="also time the FP8-expert workload")
-    ap.add_argument("--price-batches", type=int, default=2000,
+    ap.add_argument("--forms", type=int, default=1,
+                    help="compare every precision form (tokens/s, error vs FP64) at one shape")
+    ap.add_argument("--mx", type=int, default=1,
+                    help="also time the MX-expert forms (e4m3, e2m3, e2m1) at the FP8 shape")
+    ap.add_argument("--price-batches", type=int, default=10000,
                     help="training batches of the price network (0 = skip that part)")
-    ap.add_argument("--price-steps", type=int, default=2000)
+    ap.add_argument("--price-steps", type=int, default=4000)
     ap.add_argument("--profile-only", choices=["fwd", "copy", "fp8"], default=None)
     return ap.parse_args()
 
@@ -199,6 +203,8 @@ def main():
     if args.bwd_config:
         fb = fwd_bwd(args.bwd_config, args, dev, torch, L, layer, synth)
     f8 = fp8_forward(args, dev, torch, L, layer, synth) if args.fp8 else None
+    mxr = mx_forward(args, dev, torch, L, layer, synth) if args.mx else None
+    forms = forms_comparison(args, dev, torch, L, layer, synth) if args.forms else None
     lp = None
     if args.price_batches:
         from paper_2606_17065_amd import price
@@ -222,7 +228,8 @@ def main():
                    "parallelism": "single-gpu"},
         "price_iters": int(info[0]), "converged": bool(info[1]),
         "slots_per_s": value * shape.k, "wall_s": wall,
-        "roofline": roof, "stages": stages, "fwd_bwd": fb, "fp8": f8, "learned_price": lp,
+        "roofline": roof, "stages": stages, "fwd_bwd": fb, "fp8": f8, "mx": mxr, "forms": forms,
+        "learned_price": lp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))
@@ -256,6 +263,127 @@ def fwd_bwd(config, args, dev, torch, L, layer, synth):
     return {"workload": f"moe-{shape.name}", "T": shape.T, "d_model": d, "E": shape.E,
             "top_k": shape.k, "d_ff": f, "steps": steps, "ms_per_step": ms,
             "tokens_per_s": shape.T / (ms / 1e3), "stages": st}
+
+
+MX_PEAK_TFLOPS = {"e4m3": 5000.0, "e2m3": 10100.0, "e2m1": 10100.0}
+
+
+def forms_comparison(args, dev, torch, L, layer, synth):
+    """Every precision form of the layer forward on the BF16 workload's shape
+    (T=16384, d=1024, E=64, top-8, d_ff=2048, same FP32 inputs): tokens/s
+    and the error of each form against the FP64 layer on the FP32 inputs
+    (router logits of all tokens; Y and out of 64 sampled tokens on the
+    routing each form chose, with FP64 gate weights)."""
+    from oracle import ffn, routing as R
+    shape = synth.SHAPES[2]
+    inp = synth.make_inputs(shape, 2)
+    T, d, E, k, f = shape.T, shape.d, shape.E, shape.k, shape.f
+    sample = np.linspace(0, T - 1, 64).astype(np.int64)
+    X64 = inp["X"].astype(np.float64)
+    s64 = R.logits_fp64(X64, inp["Wr"], inp["br"])
+    W13_64 = inp["W13"].astype(np.float64)
+    W2_64 = inp["W2"].astype(np.float64)
+    Wr = torch.from_numpy(inp["Wr"]).to(dev)
+    br = torch.from_numpy(inp["br"]).to(dev)
+    res = {"workload": "moe-bf16-scale shape, every form", "T": T, "d_model": d, "E": E,
+           "top_k": k, "d_ff": f, "error_sample_tokens": len(sample), "forms": {}}
+    forms = [("f32", L.MOE_F32, L.MOE_F32), ("bf16", L.MOE_BF16, L.MOE_BF16),
+             ("fp8-e4m3 (1x128 / 128x128 FP32 scales)", L.MOE_BF16, L.MOE_FP8E4M3),
+             ("mx-e4m3", L.MOE_BF16, L.MOE_MXFP8E4M3), ("mx-e2m3", L.MOE_BF16, L.MOE_MXFP6E2M3),
+             ("mx-e2m1", L.MOE_BF16, L.MOE_MXFP4E2M1)]
+    for name, act, w in forms:
+        adt = torch.float32 if act == L.MOE_F32 else torch.bfloat16
+        X = torch.from_numpy(inp["X"]).to(adt).to(dev)
+        W13 = torch.from_numpy(inp["W13"]).to(dev)
+        W2 = torch.from_numpy(inp["W2"]).to(dev)
+        s13 = s2 = None
+        if w == L.MOE_BF16:
+            W13, W2 = W13.to(torch.bfloat16), W2.to(torch.bfloat16)
+        elif w == L.MOE_FP8E4M3:
+            (W13, s13), (W2, s2) = layer.quantize_fp8(W13, 128), layer.quantize_fp8(W2, 128)
+        elif w != L.MOE_F32:
+            (W13, s13), (W2, s2) = layer.quantize_mx(W13, w), layer.quantize_mx(W2, w)
+        cfg = L.make_cfg(T, d, E, k, f, shape.capacity, shape.max_iters, act, w, L.MOE_PRICE_ACP)
+
+        def fwd():
+            return layer.forward(cfg, X, Wr, br, W13, W2, W13_scale=s13, W2_scale=s2,
+                                 check=False)
+
+        steps = 5
+        gpu_ms, _ = timed(fwd, steps, 2, torch, L)
+        r = fwd()
+        torch.cuda.synchronize()
+        sel = r["idx"].cpu().numpy()
+        inv = r["inv_map"].cpu().numpy()
+        Yg = r["Y"].float()
+        s_gpu = r["logits"].cpu().numpy().astype(np.float64)
+        errs = {"logits": float(np.abs(s_gpu - s64).max() / np.abs(s64).max())}
+        w64 = R.gate_weights(s64[sample], sel[sample])
+        y_ref = np.zeros((len(sample), k, d))
+        y_got = np.zeros((len(sample), k, d))
+        for a, t in enumerate(sample):
+            for j in range(k):
+                e = int(sel[t, j])
+                x = X64[t]
+                A = W13_64[e, :f] @ x
+                B = W13_64[e, f:] @ x
+                y_ref[a, j] = W2_64[e] @ (A / (1.0 + np.exp(-A)) * B)
+                y_got[a, j] = Yg[int(inv[t, j])].cpu().numpy()
+        o_ref = np.einsum("tj,tjd->td", w64, y_ref)
+        o_got = r["out"][torch.from_numpy(sample).to(dev)].float().cpu().numpy()
+        for key, got, ref in (("Y", y_got, y_ref), ("out", o_got, o_ref)):
+            errs[key] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            errs[key + "_max_abs"] = float(np.abs(got - ref).max() / np.abs(ref).max())
+        res["forms"][name] = {"ms_per_step": gpu_ms / steps,
+                              "tokens_per_s": T / (gpu_ms / steps / 1e3),
+                              "rel_err_vs_fp64": errs, "price_iters": int(r["info"][0])}
+        del X, W13, W2, s13, s2, r, Yg
+    return res
+
+
+def mx_forward(args, dev, torch, L, layer, synth):
+    """Forward of the FP8-expert workload's shape with OCP MX experts (e4m3,
+    e2m3 and e2m1 codes, E8M0 scales per 32 along K; weights quantised once
+    outside the timed region, tokens and h inside the layer)."""
+    shape = synth.SHAPES[3]
+    inp = synth.make_inputs(shape, 3)
+    X = torch.from_numpy(inp["X"]).to(torch.bfloat16).to(dev)
+    Wr = torch.from_numpy(inp["Wr"]).to(dev)
+    br = torch.from_numpy(inp["br"]).to(dev)
+    W13 = torch.from_numpy(inp["W13"]).to(torch.bfloat16).to(dev)
+    W2 = torch.from_numpy(inp["W2"]).to(torch.bfloat16).to(dev)
+    del inp
+    N, d, f = shape.N, shape.d, shape.f
+    res = {"workload": f"moe-{shape.name}-mx", "T": shape.T, "d_model": d, "E": shape.E,
+           "top_k": shape.k, "d_ff": f, "formats": {}}
+    for fmt, name in ((L.MOE_MXFP8E4M3, "e4m3"), (L.MOE_MXFP6E2M3, "e2m3"),
+                      (L.MOE_MXFP4E2M1, "e2m1")):
+        q13, s13 = layer.quantize_mx(W13, fmt)
+        q2, s2 = layer.quantize_mx(W2, fmt)
+        cfg = L.make_cfg(shape.T, d, shape.E, shape.k, f, shape.capacity, shape.max_iters,
+                         L.MOE_BF16, fmt, L.MOE_PRICE_ACP)
+
+        def fwd():
+            return layer.forward(cfg, X, Wr, br, q13, q2, W13_scale=s13, W2_scale=s2, check=False)
+
+        steps = max(2, args.steps // 4)
+        gpu_ms, wall = timed(fwd, steps, max(1, args.warmup // 2), torch, L)
+        ms = gpu_ms / steps
+        st = stage_times(L, ("router_logits", "price_loop", "quant_mx", "dispatch", "gemm1_swiglu",
+                             "gemm2", "combine"))
+        st["gemm1_swiglu"].update(flop=4.0 * N * d * f,
+                                  tflops=4.0 * N * d * f / (st["gemm1_swiglu"]["ms"] * 1e9))
+        st["gemm2"].update(flop=2.0 * N * d * f,
+                           tflops=2.0 * N * d * f / (st["gemm2"]["ms"] * 1e9))
+        ach = st["gemm1_swiglu"]["tflops"]
+        res["formats"][name] = {
+            "steps": steps, "ms_per_step": ms, "tokens_per_s": shape.T / (ms / 1e3),
+            "roofline": {"kernel": f"gemm1_swiglu (mx {name})", "bound": "mfma", "achieved": ach,
+                         "peak": MX_PEAK_TFLOPS[name], "unit": "TFLOP/s",
+                         "frac": ach / MX_PEAK_TFLOPS[name]},
+            "stages": st}
+        del q13, s13, q2, s2
+    return res
 
 
 def fp8_forward(args, dev, torch, L, layer, synth):
@@ -331,14 +459,23 @@ def learned_prices(args, dev, torch, L, price, layer, synth):
     t_train = time.perf_counter() - t0
     it_train = ds.iters.float()
     evals = []
-    for T in (4096, 16384, 65536):
+    # expert weights of the layer timings: N(0, 0.02^2) drawn on the device
+    # from a seeded generator (only their shape matters for the timing)
+    f = synth.SHAPES[5].f
+    wg = torch.Generator(device=dev)
+    wg.manual_seed(5_000_002)
+    W13 = (0.02 * torch.randn(E, 2 * f, d, generator=wg, device=dev)).to(torch.bfloat16)
+    W2 = (0.02 * torch.randn(E, d, f, generator=wg, device=dev)).to(torch.bfloat16)
+    # uneven batch lengths over the training range (none a multiple of a tile)
+    for T in (4133, 11587, 30011, 65521):
         shape = synth.SHAPES[5].with_tokens(T)
         inp = synth.make_inputs(shape, 5, rep=1, experts=False)
         X = torch.from_numpy(inp["X"]).to(torch.bfloat16).to(dev)
+        Wr_d = torch.from_numpy(inp["Wr"]).to(dev)
+        br_d = torch.from_numpy(inp["br"]).to(dev)
         cfg = L.make_cfg(T, d, E, k, shape.f, shape.capacity, 50, L.MOE_BF16, L.MOE_BF16,
                          L.MOE_PRICE_ACP)
-        logits = layer.route(cfg, X, torch.from_numpy(inp["Wr"]).to(dev),
-                             torch.from_numpy(inp["br"]).to(dev))["logits"]
+        logits = layer.router_logits(cfg, X, Wr_d, br_d)
 
         def cold():
             return price.route_logits(cfg, logits)
@@ -367,6 +504,26 @@ def learned_prices(args, dev, torch, L, price, layer, synth):
                          "converged": bool(r["info"][L.INFO_CONVERGED])}
             if name != "cold":
                 res[name].update(price.verdict_dict(r))
+
+        def layer_cold():
+            return layer.forward(cfg, X, Wr_d, br_d, W13, W2, check=False)
+
+        def layer_warm():
+            return price.learned_layer_forward(cfg, X, Wr_d, br_d, W13, W2, params, mode="warm")
+
+        for name, fn in (("layer_cold", layer_cold), ("layer_learned_warm", layer_warm)):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            res[name] = {"ms": ms, "tokens_per_s": T / (ms / 1e3)}
         evals.append({"T": T, **res})
     return {"workload": "moe-learned-price", "E": E, "d_model": d, "top_k": k,
             "train_batches": args.price_batches, "train_steps": args.price_steps,

@@ -59,7 +59,14 @@ typedef enum {
   MOE_ECAPACITY = -7     /* (device, info[3]) capacity repair placed no slot */
 } moe_status;
 
-typedef enum { MOE_F32 = 0, MOE_BF16 = 1, MOE_FP8E4M3 = 2 } moe_dtype;
+typedef enum {
+  MOE_F32 = 0,
+  MOE_BF16 = 1,
+  MOE_FP8E4M3 = 2,   /* e4m3 codes with FP32 scales per 1x128 / 128x128 block */
+  MOE_MXFP8E4M3 = 3, /* OCP MX: e4m3 codes, E8M0 scale per 32 along K        */
+  MOE_MXFP6E2M3 = 4, /* OCP MX: e2m3 codes, E8M0 scale per 32 along K        */
+  MOE_MXFP4E2M1 = 5  /* OCP MX: e2m1 codes, E8M0 scale per 32 along K        */
+} moe_dtype;
 
 typedef enum {
   MOE_PRICE_NONE = 0,  /* p = 0: plain top-k (then capacity repair)        */
@@ -133,6 +140,16 @@ moe_status moe_workspace_bytes(const moe_cfg* cfg /* host */, size_t* bytes /* h
 moe_status moe_route(const moe_cfg* cfg, const void* X, const float* Wr, const float* br,
                      float* logits, float* price, int32_t* topk_idx, float* topk_w,
                      int32_t* load, int32_t* info, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * moe_router_logits -- the router alone: logits [T,E] f32 out = X W_r^T +
+ *   b_r, computed exactly as moe_route computes them (same kernels, same
+ *   bits).  For callers that route from these logits themselves (learned
+ *   prices: moe_logit_stats, the price network, moe_route_judged).  X, Wr,
+ *   br as in moe_route; ws at least moe_workspace_bytes(cfg).
+ */
+moe_status moe_router_logits(const moe_cfg* cfg, const void* X, const float* Wr, const float* br,
+                             float* logits, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * moe_route_logits -- moe_route for caller-supplied logits: the same
@@ -389,6 +406,54 @@ moe_status moe_expert_ffn_gather_fp8(const moe_cfg* cfg, const uint8_t* X_codes,
  */
 moe_status moe_quantize_fp8(int rows, int cols, int block_rows, int src_dtype, const void* src,
                             uint8_t* codes, float* scales, void* stream);
+
+/*
+ * OCP Microscaling (MX) experts (cfg.w = MOE_MXFP8E4M3, MOE_MXFP6E2M3 or
+ * MOE_MXFP4E2M1; the published OCP Microscaling Formats v1.0 block format).
+ * A matrix [R, K] (K % 32 == 0) is quantised along K in blocks of 32: amax
+ * = max |x| of the block; s = floor(log2 amax) - emax (emax 8 for e4m3, 2
+ * for e2m3 and e2m1), clamped to [-127, 127], s = 0 for an all-zero block;
+ * scale byte = s + 127 (E8M0); code_i = the element value nearest to
+ * x_i / 2^s, ties to the even mantissa, magnitudes above the largest
+ * normal (448, 7.5, 6) saturated, sign kept.  Inputs must be finite.
+ * Code layout of a row of K elements: e4m3 one byte per code (K bytes);
+ * e2m3 per block the 32 codes 6 bits apart (code i at bits 6i of the
+ * block's little-endian bit string) in 24 bytes followed by 8 zero bytes
+ * (K bytes); e2m1 two codes per byte, lower index in the low nibble (K/2
+ * bytes).  Scales [R, K/32] u8.
+ */
+
+/*
+ * moe_quantize_mx -- MX quantisation of src [rows, cols] (src_dtype MOE_F32
+ *   or MOE_BF16; cols % 32 == 0, rows * cols < 2^40) as stated above.
+ *   fmt: MOE_MXFP8E4M3, MOE_MXFP6E2M3 or MOE_MXFP4E2M1.  codes [rows, row
+ *   bytes] u8 out (16-byte aligned), scales [rows, cols/32] u8 out (4-byte
+ *   aligned).  Expert weights [E, R, C] quantise as rows = E * R.
+ */
+moe_status moe_quantize_mx(int rows, int cols, int fmt, int src_dtype, const void* src,
+                           uint8_t* codes, uint8_t* scales, void* stream);
+
+/*
+ * moe_expert_ffn_mx -- grouped SwiGLU experts with MX operands, the permute
+ *   fused into the first product:
+ *     for the slots r of expert e: x = MX-dequantised token row row_map[r];
+ *     A = x W1_e^T, B = x W3_e^T with MX-dequantised weights (block products
+ *     accumulated in FP32 by the scaled matrix instructions); h = silu(A) *
+ *     B rounded to BF16, then MX-quantised along f (1 x 32 blocks); Y[r] =
+ *     h W2_e^T (FP32 accumulation) stored as BF16.
+ *   cfg.act = MOE_BF16, cfg.w one of the MX formats; d % 256 == 0 and
+ *   d_ff % 128 == 0 (else MOE_EUNSUPPORTED).  X_codes [T, row bytes of d],
+ *   X_scale [T, d/32] (moe_quantize_mx of the tokens); W13 [E*2f, row
+ *   bytes of d] with W13_scale [E*2f, d/32] (rows 0..f-1 of expert e =
+ *   W1_e, f..2f-1 = W3_e); W2 [E*d, row bytes of f] with W2_scale
+ *   [E*d, f/32]; row_map [N], offsets [E+1] as moe_dispatch writes them;
+ *   Y [N,d] bf16 out.  ws: moe_workspace_bytes(cfg).
+ */
+moe_status moe_expert_ffn_mx(const moe_cfg* cfg, const uint8_t* X_codes, const uint8_t* X_scale,
+                             const int32_t* row_map, const int32_t* offsets, const uint8_t* W13,
+                             const uint8_t* W13_scale, const uint8_t* W2,
+                             const uint8_t* W2_scale, void* Y, void* ws, size_t ws_bytes,
+                             void* stream);
 
 /*
  * moe_combine -- out[t] = sum_j topk_w[t,j] * Y[inv_map[t,j]], accumulated

@@ -22,6 +22,7 @@ MOE_ENAN = -6
 MOE_ECAPACITY = -7
 
 MOE_F32, MOE_BF16, MOE_FP8E4M3 = 0, 1, 2
+MOE_MXFP8E4M3, MOE_MXFP6E2M3, MOE_MXFP4E2M1 = 3, 4, 5
 MOE_PRICE_NONE, MOE_PRICE_ACP, MOE_PRICE_GIVEN, MOE_PRICE_WARM = 0, 1, 2, 3
 
 INFO_ITERS, INFO_CONVERGED, INFO_OVERFLOW, INFO_STATUS = 0, 1, 2, 3
@@ -53,11 +54,14 @@ _CFG = ctypes.POINTER(MoeCfg)
 SIGNATURES = {
     "moe_workspace_bytes": [_CFG, ctypes.POINTER(ctypes.c_size_t)],
     "moe_route": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_router_logits": [_CFG, _P, _P, _P, _P, _P, _S, _P],
     "moe_dispatch": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_dispatch_noalloc": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P],
     "moe_expert_ffn": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_expert_ffn_gather": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_expert_ffn_gather_fp8": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_quantize_mx": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P],
+    "moe_expert_ffn_mx": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_quantize_fp8": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P],
     "moe_combine": [_CFG, _P, _P, _P, _P, _P],
     "moe_combine_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P],
@@ -128,6 +132,11 @@ def moe_route(cfg, X, Wr, br, logits, price, topk_idx, topk_w, load, info, ws, w
                            info, ws, ws_bytes, stream), "moe_route")
 
 
+def moe_router_logits(cfg, X, Wr, br, logits, ws, ws_bytes, stream):
+    _check(lib().moe_router_logits(ctypes.byref(cfg), X, Wr, br, logits, ws, ws_bytes, stream),
+           "moe_router_logits")
+
+
 def moe_dispatch(cfg, X, topk_idx, offsets, row_map, inv_map, X_perm, X_perm_scale, ws, ws_bytes,
                  stream):
     _check(lib().moe_dispatch(ctypes.byref(cfg), X, topk_idx, offsets, row_map, inv_map, X_perm,
@@ -145,6 +154,18 @@ def moe_expert_ffn_gather_fp8(cfg, X_codes, X_scale, row_map, offsets, W13, W13_
     _check(lib().moe_expert_ffn_gather_fp8(ctypes.byref(cfg), X_codes, X_scale, row_map, offsets,
                                            W13, W13_scale, W2, W2_scale, Y, ws, ws_bytes, stream),
            "moe_expert_ffn_gather_fp8")
+
+
+def moe_quantize_mx(rows, cols, fmt, src_dtype, src, codes, scales, stream):
+    _check(lib().moe_quantize_mx(rows, cols, fmt, src_dtype, src, codes, scales, stream),
+           "moe_quantize_mx")
+
+
+def moe_expert_ffn_mx(cfg, X_codes, X_scale, row_map, offsets, W13, W13_scale, W2, W2_scale, Y,
+                      ws, ws_bytes, stream):
+    _check(lib().moe_expert_ffn_mx(ctypes.byref(cfg), X_codes, X_scale, row_map, offsets, W13,
+                                   W13_scale, W2, W2_scale, Y, ws, ws_bytes, stream),
+           "moe_expert_ffn_mx")
 
 
 def moe_expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, Y, ws, ws_bytes, stream):

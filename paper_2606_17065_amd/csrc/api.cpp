@@ -23,7 +23,7 @@ moe_status check_cfg_shape(const moe_cfg* c) {
   if (c->T < 0 || c->d < 1 || c->E < 1 || c->k < 1 || c->d_ff < 1 || c->capacity < 0)
     return MOE_EINVAL;
   if (c->act != MOE_F32 && c->act != MOE_BF16) return MOE_EINVAL;
-  if (c->w != MOE_F32 && c->w != MOE_BF16 && c->w != MOE_FP8E4M3) return MOE_EINVAL;
+  if (c->w < MOE_F32 || c->w > MOE_MXFP4E2M1) return MOE_EINVAL;
   if (c->price_stages < 0 || c->price_stages > 8) return MOE_EINVAL;
   if (c->k > c->E) return MOE_EINFEASIBLE;
   if ((int64_t)c->E * (int64_t)c->capacity < (int64_t)c->T * (int64_t)c->k) return MOE_EINFEASIBLE;

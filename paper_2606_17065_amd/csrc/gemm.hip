@@ -839,6 +839,388 @@ MOE_INST_F8(EPI_SWIGLU, true)
 MOE_INST_F8(EPI_PLAIN, false)
 #undef MOE_INST_F8
 
+// ============================================================ MX formats
+// OCP Microscaling blocks: 32 consecutive elements along K share an E8M0
+// scale byte (2^(byte - 127)); elements are e4m3 (MX-FP8), e2m3 (MX-FP6)
+// or e2m1 (MX-FP4) codes.  Memory layout of a code row of K elements:
+//   e4m3  one code per byte                            (K bytes)
+//   e2m3  each block's 32 codes packed 6 bits apart (code i at bits 6i of
+//         the block's little-endian bit string) in 24 bytes, then 8 zero
+//         bytes of padding                             (K bytes)
+//   e2m1  two codes per byte, lower index in the low nibble  (K/2 bytes)
+// Template parameter FMT is the matrix instruction's format selector
+// (0 e4m3, 2 e2m3, 4 e2m1).
+
+template <int FMT> struct MxFmt;
+template <> struct MxFmt<0> {
+  static constexpr int EB = 4, MB = 3, BIAS = 7, EMAX = 8;
+  static constexpr uint32_t MAXCODE = 0x7E;
+  static constexpr float MAXV = 448.0f;
+};
+template <> struct MxFmt<2> {
+  static constexpr int EB = 2, MB = 3, BIAS = 1, EMAX = 2;
+  static constexpr uint32_t MAXCODE = 0x1F;
+  static constexpr float MAXV = 7.5f;
+};
+template <> struct MxFmt<4> {
+  static constexpr int EB = 2, MB = 1, BIAS = 1, EMAX = 2;
+  static constexpr uint32_t MAXCODE = 0x7;
+  static constexpr float MAXV = 6.0f;
+};
+
+// Bytes of a code row of K elements.
+__host__ __device__ constexpr size_t mx_row_bytes(int fmt, size_t K) {
+  return fmt == 4 ? K / 2 : K;
+}
+
+// Shared exponent of a block: floor(log2 amax) - emax, clamped to the E8M0
+// range; 0 for an all-zero block.
+template <int FMT>
+__device__ __forceinline__ int mx_block_exp(float amax) {
+  if (!(amax > 0.0f)) return 0;
+  const int s = ilogbf(amax) - MxFmt<FMT>::EMAX;
+  return s < -127 ? -127 : (s > 127 ? 127 : s);
+}
+
+// Code of y (already divided by the block scale): nearest element value,
+// ties to the even mantissa, magnitudes above the largest normal saturated;
+// the sign is kept (so -0 and negatives rounding to zero are negative zero).
+template <int FMT>
+__device__ __forceinline__ uint32_t mx_encode(float y) {
+  using F = MxFmt<FMT>;
+  const uint32_t sign = (__float_as_uint(y) >> 31) << (F::EB + F::MB);
+  const float v = fabsf(y);
+  uint32_t mag;
+  if (v >= F::MAXV) {
+    mag = F::MAXCODE;
+  } else {
+    int e = v > 0.0f ? ilogbf(v) : 1 - F::BIAS;
+    if (e < 1 - F::BIAS) e = 1 - F::BIAS;
+    const int n = (int)rintf(ldexpf(v, F::MB - e));  // exact scaling, then RNE
+    if (n < (1 << F::MB)) {
+      mag = (uint32_t)n;  // subnormal (only reachable at the smallest exponent) or zero
+    } else if (n == (2 << F::MB)) {
+      mag = (uint32_t)((e + 1 + F::BIAS) << F::MB);
+    } else {
+      mag = (uint32_t)(((e + F::BIAS) << F::MB) | (n - (1 << F::MB)));
+    }
+  }
+  return sign | mag;
+}
+
+// Codes of one 32-element block (values already divided by the scale) in
+// the memory layout above: 8 words (e4m3, e2m3 with 2 words of padding) or
+// 4 words (e2m1).
+template <int FMT>
+__device__ __forceinline__ void mx_pack_block(const float (&y)[32], uint32_t (&w)[8]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) w[q] = 0u;
+  if (FMT == 0) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) w[i >> 2] |= mx_encode<FMT>(y[i]) << (8 * (i & 3));
+  } else if (FMT == 4) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) w[i >> 3] |= mx_encode<FMT>(y[i]) << (4 * (i & 7));
+  } else {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const uint64_t v = (uint64_t)mx_encode<FMT>(y[i]) << ((6 * i) & 31);
+      w[(6 * i) >> 5] |= (uint32_t)v;
+      if (((6 * i) & 31) > 26) w[((6 * i) >> 5) + 1] |= (uint32_t)(v >> 32);
+    }
+  }
+}
+
+// Quantise a block of 32 values: writes its codes at dst (32 or 16 bytes,
+// 16-byte aligned) and returns the scale byte.
+template <int FMT>
+__device__ __forceinline__ uint8_t mx_quant_block(float (&x)[32], uint8_t* dst) {
+  float amax = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) amax = fmaxf(amax, fabsf(x[i]));
+  const int s = mx_block_exp<FMT>(amax);
+#pragma unroll
+  for (int i = 0; i < 32; ++i) x[i] = ldexpf(x[i], -s);
+  uint32_t w[8];
+  mx_pack_block<FMT>(x, w);
+  u32x4* d = (u32x4*)dst;
+  d[0] = (u32x4){w[0], w[1], w[2], w[3]};
+  if (FMT != 4) d[1] = (u32x4){w[4], w[5], w[6], w[7]};
+  return (uint8_t)(s + 127);
+}
+
+// One thread per 32-element block of the rows of src [rows, K].
+template <int FMT, typename TIN>
+__global__ __launch_bounds__(256) void mx_quant_rows(const TIN* __restrict__ src, int rows,
+                                                     int K, uint8_t* __restrict__ codes,
+                                                     uint8_t* __restrict__ scales) {
+  const int nb = K / 32;
+  const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (size_t)rows * nb) return;
+  const size_t r = g / nb;
+  const int b = (int)(g - r * nb);
+  float x[32];
+  const TIN* p = src + r * K + (size_t)b * 32;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) x[i] = (float)p[i];
+  scales[g] = mx_quant_block<FMT>(x, codes + r * mx_row_bytes(FMT, K) + mx_row_bytes(FMT, 32) * b);
+}
+
+// ------------------------------------------- MX grouped GEMM, 256 x 256
+// The 8-wavefront 256 x 256 tile of gemm_bf16_wide (same tile order, DMA,
+// swizzled 128-byte LDS rows, SwiGLU pairing), reading one 128-byte row
+// segment per stage: 128 K (e4m3, padded e2m3) or 256 K (e2m1).  Per stage
+// and 32x32 tile, v_mfma_scale_f32_32x32x64_f8f6f4 steps through K in
+// 64-element slices with the two operands' E8M0 block scales as its scale
+// operands, so the block scaling costs nothing beyond loading the scale
+// bytes.  Lane (row r, half h) of a slice holds: e4m3 bytes 16h..16h+15 of
+// each of the slice's two blocks; e2m3 / e2m1 all of block h; it supplies
+// the scale of block h of its row (the instruction takes each block's
+// scale from the lane of that row and half).  For e2m1, K % 256 == 128
+// leaves a last stage of 128 K: its upper row halves are never loaded nor
+// used.  SwiGLU epilogue: h = silu(A) * B rounded to BF16 in the LDS tile,
+// then quantised per 32-column block straight to h codes and scale bytes.
+template <int FMT, int EPI, bool GATHER>
+__global__ __launch_bounds__(64 * XW, 1) void gemm_mx_wide(
+    const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
+    const int32_t* __restrict__ row_map, int T, const uint8_t* __restrict__ B,
+    const uint8_t* __restrict__ Bs, void* __restrict__ Cv, uint8_t* __restrict__ Cscale,
+    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start, int E, int N,
+    int K, int f, int Ncols, int n_tiles, int grid_total) {
+  typedef __attribute__((address_space(3))) void lds_void;
+  constexpr bool PAIRED = EPI == EPI_SWIGLU;
+  constexpr int KPS = FMT == 4 ? 256 : 128;  // K elements per stage
+  constexpr int KK = KPS / 64;               // 64-K slices per stage
+  constexpr int BPS = KPS / 32;              // scale blocks per stage
+  __shared__ __attribute__((aligned(1024))) char lds[XLDS];
+  const int b = blockIdx.x;
+  const int per = grid_total >> 3;
+  const int Lt = (b & 7) * per + (b >> 3);
+  int e, row0, rows, nt;
+  if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 2, wn = wv & 3;
+  const int n0 = nt * (PAIRED ? 128 : 256);
+  const size_t Brows_e = PAIRED ? (size_t)2 * f : (size_t)Ncols;
+  const size_t RB = mx_row_bytes(FMT, K);  // bytes of an operand row
+  const int nbk = K / 32;                  // scale bytes of an operand row
+  const uint8_t* asrc[XA_INS];
+  const uint8_t* bsrc[XB_INS];
+  bool a_lo[XA_INS], b_lo[XB_INS];  // the lane's chunk lies in the first 64 bytes
+#pragma unroll
+  for (int i = 0; i < XA_INS; ++i) {
+    const int R = wv * (GBM / XW) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
+    const int r = row0 + min(R, rows - 1);
+    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
+    asrc[i] = A + arow * RB + c * 16;
+    a_lo[i] = c < 4;
+  }
+#pragma unroll
+  for (int i = 0; i < XB_INS; ++i) {
+    const int R = wv * (XBN / XW) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
+    const int wrow = PAIRED ? (R < 128 ? n0 + R : f + n0 + (R - 128)) : n0 + R;
+    bsrc[i] = B + ((size_t)e * Brows_e + wrow) * RB + c * 16;
+    b_lo[i] = c < 4;
+  }
+  const int fr = lane & 31, fh = lane >> 5;
+  int aoff[4], asw[4], boff[2], bsw[2];
+  const uint8_t* sarow[4];
+  const uint8_t* sbrow[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int R = wm * 128 + i * 32 + fr;
+    aoff[i] = R * 128;
+    asw[i] = (R >> 1) & 7;
+    const int r = row0 + min(R, rows - 1);
+    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
+    sarow[i] = As + arow * nbk;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int R = (PAIRED ? (j == 0 ? wn * 32 : 128 + wn * 32) : wn * 64 + j * 32) + fr;
+    boff[j] = XSTAGE_A + R * 128;
+    bsw[j] = (R >> 1) & 7;
+    const int wrow = PAIRED ? (R < 128 ? n0 + R : f + n0 + (R - 128)) : n0 + R;
+    sbrow[j] = Bs + ((size_t)e * Brows_e + wrow) * nbk;
+  }
+  f32x16 acc[4][2];
+  zero_acc(acc);
+  const int nk = (K + KPS - 1) / KPS;
+  const bool tail = K % KPS != 0;  // e2m1 only: last stage of 128 K
+#define MX_ISSUE(kstep)                                                                        \
+  {                                                                                            \
+    char* st_ = lds + ((kstep) & 1) * XSTAGE;                                                  \
+    const size_t k0_ = (size_t)(kstep) * 128;                                                  \
+    const bool half_ = tail && (kstep) == nk - 1;                                              \
+    _Pragma("unroll") for (int i = 0; i < XA_INS; ++i) if (!half_ || a_lo[i])                  \
+        __builtin_amdgcn_global_load_lds(asrc[i] + k0_,                                        \
+                                         (lds_void*)(st_ + (wv * (GBM / XW) + i * 8) * 128),   \
+                                         16, 0, 0);                                            \
+    _Pragma("unroll") for (int i = 0; i < XB_INS; ++i) if (!half_ || b_lo[i])                  \
+        __builtin_amdgcn_global_load_lds(                                                      \
+            bsrc[i] + k0_, (lds_void*)(st_ + XSTAGE_A + (wv * (XBN / XW) + i * 8) * 128), 16,  \
+            0, 0);                                                                             \
+  }
+  // scale words of a stage: bytes [kstep * BPS, +BPS) of each row, loaded
+  // one stage ahead into san / sbn
+  uint32_t sa[4][BPS / 4], sb[2][BPS / 4], san[4][BPS / 4], sbn[2][BPS / 4];
+#define MX_SCALES(SA, SB, kstep)                                                   \
+  {                                                                                \
+    const int o_ = (kstep) * BPS;                                                  \
+    const bool half_ = tail && (kstep) == nk - 1;                                  \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) _Pragma("unroll") for (          \
+        int w = 0; w < BPS / 4; ++w) SA[i][w] =                                    \
+        (w == 0 || !half_) ? *(const uint32_t*)(sarow[i] + o_ + 4 * w) : 0u;       \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) _Pragma("unroll") for (          \
+        int w = 0; w < BPS / 4; ++w) SB[j][w] =                                    \
+        (w == 0 || !half_) ? *(const uint32_t*)(sbrow[j] + o_ + 4 * w) : 0u;       \
+  }
+  // fragment of slice kk for a row at LDS offset off with swizzle sw
+#define MX_FRAG(out, off, sw, kk)                                                  \
+  {                                                                                \
+    const char* st_ = lds + (kt & 1) * XSTAGE;                                     \
+    if (FMT == 0) {                                                                \
+      const u32x4 lo_ = *(const u32x4*)(st_ + (off) + (((4 * (kk) + fh) ^ (sw)) << 4));     \
+      const u32x4 hi_ = *(const u32x4*)(st_ + (off) + (((4 * (kk) + 2 + fh) ^ (sw)) << 4)); \
+      out = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],            \
+                    (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};           \
+    } else if (FMT == 2) {                                                         \
+      const u32x4 lo_ = *(const u32x4*)(st_ + (off) + (((4 * (kk) + 2 * fh) ^ (sw)) << 4));     \
+      const u32x4 hi_ = *(const u32x4*)(st_ + (off) + (((4 * (kk) + 2 * fh + 1) ^ (sw)) << 4)); \
+      out = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],            \
+                    (int)hi_[0], (int)hi_[1], 0, 0};                               \
+    } else {                                                                       \
+      const u32x4 lo_ = *(const u32x4*)(st_ + (off) + (((2 * (kk) + fh) ^ (sw)) << 4)); \
+      out = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3], 0, 0, 0, 0}; \
+    }                                                                              \
+  }
+  MX_ISSUE(0);
+  if (nk > 1) {
+    MX_ISSUE(1);
+    WAIT_VM_LGKM0(XA_INS + XB_INS);
+  } else {
+    WAIT_VM_LGKM0(0);
+  }
+  MX_SCALES(sa, sb, 0);
+  stage_barrier();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) MX_SCALES(san, sbn, kt + 1);
+    const int kkn = (tail && kt == nk - 1) ? KK / 2 : KK;
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+      if (kk < kkn) {
+        i32x8 af[4], bfr[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) MX_FRAG(af[i], aoff[i], asw[i], kk);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) MX_FRAG(bfr[j], boff[j], bsw[j], kk);
+        const int blk = 2 * kk + fh, wsel = blk >> 2, sh = 8 * (blk & 3);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int sca = (int)((sa[i][wsel] >> sh) & 0xFFu);
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int scb = (int)((sb[j][wsel] >> sh) & 0xFFu);
+            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                bfr[j], af[i], acc[i][j], FMT, FMT, 0, scb, 0, sca);
+          }
+        }
+      }
+    }
+    if (kt + 1 < nk) {
+      WAIT_VM_LGKM0(0);
+      stage_barrier();
+      if (kt + 2 < nk) MX_ISSUE(kt + 2);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int w = 0; w < BPS / 4; ++w) sa[i][w] = san[i][w];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int w = 0; w < BPS / 4; ++w) sb[j][w] = sbn[j][w];
+    }
+  }
+#undef MX_ISSUE
+#undef MX_SCALES
+#undef MX_FRAG
+  WAIT_VM_LGKM0(0);
+  stage_barrier();
+
+  constexpr int CS = EPI == EPI_SWIGLU ? 128 : 256;
+  constexpr int CLD = CS + 8;
+  bf16_t* Cs = (bf16_t*)lds;
+  const int cbase = fh * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rl = wm * 128 + i * 32 + fr;
+#pragma unroll
+    for (int j = 0; j < (EPI == EPI_SWIGLU ? 1 : 2); ++j) {
+      const int col0 = EPI == EPI_SWIGLU ? wn * 32 : wn * 64 + j * 32;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        bf16x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float x = acc[i][j][g * 4 + q];
+          if (EPI == EPI_SWIGLU) v[q] = (bf16_t)(silu(x) * acc[i][1][g * 4 + q]);
+          else v[q] = (bf16_t)x;
+        }
+        *(bf16x4*)(Cs + rl * CLD + col0 + g * 8 + cbase) = v;
+      }
+    }
+  }
+  __syncthreads();
+  if (EPI == EPI_SWIGLU) {
+    // h codes [N, row bytes of f] and scale bytes [N, f/32]
+    uint8_t* hc = (uint8_t*)Cv;
+    const size_t RBf = mx_row_bytes(FMT, f);
+    for (int c = tid; c < GBM * 4; c += 64 * XW) {
+      const int rr = c >> 2, qb = c & 3;
+      if (rr >= rows) continue;
+      float x[32];
+      const bf16_t* src = Cs + rr * CLD + qb * 32;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bf16x8 v = *(const bf16x8*)(src + 8 * q);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[8 * q + u] = (float)v[u];
+      }
+      const size_t row = (size_t)(row0 + rr);
+      const int blk = nt * 4 + qb;
+      Cscale[row * (f / 32) + blk] =
+          mx_quant_block<FMT>(x, hc + row * RBf + mx_row_bytes(FMT, 32) * blk);
+    }
+  } else {
+    bf16_t* C = (bf16_t*)Cv;
+    constexpr int CPR = CS / 8;
+    for (int c = tid; c < GBM * CPR; c += 64 * XW) {
+      const int rr = c / CPR, cc = (c - rr * CPR) * 8;
+      if (rr >= rows) continue;
+      *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + (size_t)nt * CS + cc) =
+          *(const u32x4*)(Cs + rr * CLD + cc);
+    }
+  }
+}
+
+#define MOE_INST_MX(FMT)                                                                      \
+  template __global__ void gemm_mx_wide<FMT, EPI_SWIGLU, true>(                              \
+      const uint8_t* __restrict__, const uint8_t* __restrict__, const int32_t* __restrict__, \
+      int, const uint8_t* __restrict__, const uint8_t* __restrict__, void* __restrict__,     \
+      uint8_t* __restrict__, const int32_t* __restrict__, const int32_t* __restrict__, int,  \
+      int, int, int, int, int, int);                                                         \
+  template __global__ void gemm_mx_wide<FMT, EPI_PLAIN, false>(                              \
+      const uint8_t* __restrict__, const uint8_t* __restrict__, const int32_t* __restrict__, \
+      int, const uint8_t* __restrict__, const uint8_t* __restrict__, void* __restrict__,     \
+      uint8_t* __restrict__, const int32_t* __restrict__, const int32_t* __restrict__, int,  \
+      int, int, int, int, int, int);
+MOE_INST_MX(0)
+MOE_INST_MX(2)
+MOE_INST_MX(4)
+#undef MOE_INST_MX
+
 // ------------------------------------------------------------- backward
 // Recompute-based backward of the expert FFN for the rows of each expert
 // (dY = w * dOut in slot order, supplied by the combine backward):
@@ -1177,10 +1559,21 @@ __global__ __launch_bounds__(256) void gemm_f32(const float* __restrict__ A,
 struct FfnWs {
   int32_t* tile_start;
   int32_t* tile_start_big;
-  void* h;
-  fp8_t* hq;   // FP8 path: codes of h [N, f]
-  float* hs;   // FP8 path: scales of h [N, f/128]
+  void* h;      // h [N, f] in cfg.act; MX experts: h codes [N, row bytes of f]
+  fp8_t* hq;    // FP8 path: codes of h [N, f]
+  float* hs;    // FP8 path: scales of h [N, f/128]
+  uint8_t* hx;  // MX experts: scale bytes of h [N, f/32]
 };
+
+// Matrix-instruction format selector of an MX dtype, -1 otherwise.
+int mx_format(int dtype) {
+  switch (dtype) {
+    case MOE_MXFP8E4M3: return 0;
+    case MOE_MXFP6E2M3: return 2;
+    case MOE_MXFP4E2M1: return 4;
+    default: return -1;
+  }
+}
 
 FfnWs carve_ffn(const moe_cfg& c, void* base, size_t* total) {
   WsCarve wc{(char*)base, 0};
@@ -1188,9 +1581,12 @@ FfnWs carve_ffn(const moe_cfg& c, void* base, size_t* total) {
   r.tile_start = wc.take<int32_t>((size_t)c.E + 1);
   r.tile_start_big = wc.take<int32_t>((size_t)c.E + 1);
   const size_t N = (size_t)c.T * c.k;
-  r.h = wc.take<char>(N * (size_t)c.d_ff * act_bytes(c.act));
+  const int mxf = mx_format(c.w);
+  r.h = wc.take<char>(mxf >= 0 ? N * mx_row_bytes(mxf, (size_t)c.d_ff)
+                               : N * (size_t)c.d_ff * act_bytes(c.act));
   r.hq = nullptr;
   r.hs = nullptr;
+  r.hx = mxf >= 0 ? wc.take<uint8_t>(N * (size_t)(c.d_ff / 32)) : nullptr;
   if (c.w == MOE_FP8E4M3) {
     r.hq = wc.take<fp8_t>(N * (size_t)c.d_ff);
     r.hs = wc.take<float>(N * (size_t)(c.d_ff / 128));
@@ -1549,6 +1945,86 @@ extern "C" moe_status moe_expert_ffn_gather_fp8(const moe_cfg* cfg, const uint8_
   FfnWs w = carve_ffn(c, ws, nullptr);
   launch_fp8_ffn(c, w, (const fp8_t*)X_codes, X_scale, row_map, offsets, (const fp8_t*)W13,
                  W13_scale, (const fp8_t*)W2, W2_scale, (bf16_t*)Y, st);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_quantize_mx(int rows, int cols, int fmt, int src_dtype, const void* src,
+                                      uint8_t* codes, uint8_t* scales, void* stream) {
+  const int hw = mx_format(fmt);
+  if (hw < 0) return MOE_EINVAL;
+  if (rows < 0 || cols < 0 || cols % 32 != 0) return MOE_EINVAL;
+  if (src_dtype != MOE_F32 && src_dtype != MOE_BF16) return MOE_EINVAL;
+  if ((int64_t)rows * cols >= ((int64_t)1 << 40)) return MOE_EUNSUPPORTED;
+  if (rows == 0 || cols == 0) return MOE_OK;
+  if (!src || !codes || !scales) return MOE_EINVAL;
+  if (!aligned(src, 16) || !aligned(codes, 16) || !aligned(scales, 4)) return MOE_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nblk = (size_t)rows * (cols / 32);
+  const dim3 g((unsigned)((nblk + 255) / 256));
+  PROF_BEGIN("quant_mx", st);
+#define MX_Q(F)                                                                               \
+  if (src_dtype == MOE_BF16)                                                                  \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(mx_quant_rows<F, bf16_t>), g, dim3(256), 0, st,        \
+                       (const bf16_t*)src, rows, cols, codes, scales);                        \
+  else                                                                                        \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(mx_quant_rows<F, float>), g, dim3(256), 0, st,         \
+                       (const float*)src, rows, cols, codes, scales);
+  if (hw == 0) { MX_Q(0) }
+  else if (hw == 2) { MX_Q(2) }
+  else { MX_Q(4) }
+#undef MX_Q
+  PROF_END("quant_mx", st);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
+
+extern "C" moe_status moe_expert_ffn_mx(const moe_cfg* cfg, const uint8_t* X_codes,
+                                        const uint8_t* X_scale, const int32_t* row_map,
+                                        const int32_t* offsets, const uint8_t* W13,
+                                        const uint8_t* W13_scale, const uint8_t* W2,
+                                        const uint8_t* W2_scale, void* Y, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  const int hw = mx_format(c.w);
+  if (c.act != MOE_BF16 || hw < 0) return MOE_EUNSUPPORTED;
+  if (c.d % 256 != 0 || c.d_ff % 128 != 0) return MOE_EUNSUPPORTED;
+  if (!offsets || !W13 || !W2 || !W13_scale || !W2_scale) return MOE_EINVAL;
+  if (c.T > 0 && (!X_codes || !X_scale || !row_map || !Y)) return MOE_EINVAL;
+  if (!aligned(X_codes, 16) || !aligned(X_scale, 4) || !aligned(W13, 16) || !aligned(W2, 16) ||
+      !aligned(W13_scale, 4) || !aligned(W2_scale, 4) || !aligned(Y, 16) ||
+      !aligned(offsets, 4) || !aligned(row_map, 4))
+    return MOE_EINVAL;
+  if (ws_bytes < ffn_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  if (c.T == 0) return MOE_OK;
+  hipStream_t st = (hipStream_t)stream;
+  FfnWs w = carve_ffn(c, ws, nullptr);
+  const int N = c.T * c.k;
+  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
+  const int mt_big = (N + GBM - 1) / GBM + c.E;
+  const int nt1 = c.d_ff / 128, G1 = (mt_big * nt1 + 7) / 8 * 8;
+  const int nt2 = c.d / 256, G2 = (mt_big * nt2 + 7) / 8 * 8;
+#define MX_FFN(F)                                                                              \
+  {                                                                                            \
+    PROF_BEGIN("gemm1_swiglu", st);                                                            \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_mx_wide<F, EPI_SWIGLU, true>), dim3(G1),           \
+                       dim3(64 * XW), 0, st, X_codes, X_scale, row_map, c.T, W13, W13_scale,   \
+                       w.h, w.hx, offsets, w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt1, \
+                       G1);                                                                    \
+    PROF_END("gemm1_swiglu", st);                                                              \
+    PROF_BEGIN("gemm2", st);                                                                   \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_mx_wide<F, EPI_PLAIN, false>), dim3(G2),           \
+                       dim3(64 * XW), 0, st, (const uint8_t*)w.h, (const uint8_t*)w.hx,        \
+                       nullptr, 0, W2, W2_scale, Y, nullptr, offsets, w.tile_start_big, c.E, N, \
+                       c.d_ff, c.d_ff, c.d, nt2, G2);                                          \
+    PROF_END("gemm2", st);                                                                     \
+  }
+  if (hw == 0) MX_FFN(0)
+  else if (hw == 2) MX_FFN(2)
+  else MX_FFN(4)
+#undef MX_FFN
   MOE_LAUNCH_CHECK();
   return MOE_OK;
 }

@@ -1168,6 +1168,32 @@ moe_status route_from_scores(const moe_cfg& c, const RouteWs& w, const float* lo
                              float* price, int32_t* topk_idx, float* topk_w, int32_t* load,
                              int32_t* info, hipStream_t st);
 
+// s = X W_r^T + b_r and its transpose sT in the workspace.
+void launch_router(const moe_cfg& c, const RouteWs& w, const void* X, const float* Wr,
+                   const float* br, float* logits, hipStream_t st) {
+  dim3 g((c.T + 63) / 64, (c.E + 63) / 64);
+  PROF_BEGIN("router_logits", st);
+  if (c.act == MOE_F32)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits<float>), g, dim3(256), 0, st,
+                       (const float*)X, Wr, br, logits, w.sT, c.T, c.d, c.E);
+  else if (c.d % 32 != 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits<bf16_t>), g, dim3(256), 0, st,
+                       (const bf16_t*)X, Wr, br, logits, w.sT, c.T, c.d, c.E);
+  else {
+    const int n = c.E * c.d;
+    hipLaunchKernelGGL(router_split, dim3((n + 255) / 256), dim3(256), 0, st, Wr, n, w.W3);
+    const dim3 g((c.T + 127) / 128, (c.E + 63) / 64);
+    if (c.d % 128 == 0)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<128>), g, dim3(256), 0, st,
+                         (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<32>), g, dim3(256), 0, st,
+                         (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+  }
+  PROF_END("router_logits", st);
+}
+
+
 moe_status route_check(const moe_cfg* cfg, const float* logits, float* price, int32_t* topk_idx,
                        float* topk_w, int32_t* load, int32_t* info, void* ws, size_t ws_bytes) {
   moe_status stc = check_cfg_shape(cfg);
@@ -1211,27 +1237,26 @@ extern "C" moe_status moe_route(const moe_cfg* cfg, const void* X, const float* 
     MOE_LAUNCH_CHECK();
     return MOE_OK;
   }
-  dim3 g((c.T + 63) / 64, (c.E + 63) / 64);
-  PROF_BEGIN("router_logits", st);
-  if (c.act == MOE_F32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits<float>), g, dim3(256), 0, st,
-                       (const float*)X, Wr, br, logits, w.sT, c.T, c.d, c.E);
-  else if (c.d % 32 != 0)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits<bf16_t>), g, dim3(256), 0, st,
-                       (const bf16_t*)X, Wr, br, logits, w.sT, c.T, c.d, c.E);
-  else {
-    const int n = c.E * c.d;
-    hipLaunchKernelGGL(router_split, dim3((n + 255) / 256), dim3(256), 0, st, Wr, n, w.W3);
-    const dim3 g((c.T + 127) / 128, (c.E + 63) / 64);
-    if (c.d % 128 == 0)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<128>), g, dim3(256), 0, st,
-                         (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<32>), g, dim3(256), 0, st,
-                         (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
-  }
-  PROF_END("router_logits", st);
+  launch_router(c, w, X, Wr, br, logits, st);
   return route_from_scores(c, w, logits, price, topk_idx, topk_w, load, info, st);
+}
+
+extern "C" moe_status moe_router_logits(const moe_cfg* cfg, const void* X, const float* Wr,
+                                        const float* br, float* logits, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  moe_status stc = check_cfg_shape(cfg);
+  if (stc != MOE_OK) return stc;
+  const moe_cfg& c = *cfg;
+  if (c.T == 0) return MOE_OK;
+  if (!X || !Wr || !br || !logits) return MOE_EINVAL;
+  if (!aligned(X, 16) || !aligned(Wr, 4) || !aligned(br, 4) || !aligned(logits, 4))
+    return MOE_EINVAL;
+  if (ws_bytes < route_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  RouteWs w = carve_route(c, ws, nullptr);
+  launch_router(c, w, X, Wr, br, logits, st);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
 }
 
 namespace {

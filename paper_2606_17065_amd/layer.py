@@ -78,6 +78,18 @@ def route(cfg, X, Wr, br, price=None, ws=None):
     return out
 
 
+def router_logits(cfg, X, Wr, br, ws=None):
+    """logits [T,E] f32 = X W_r^T + b_r (the router of moe_route alone)."""
+    T, d, E = cfg.T, cfg.d, cfg.E
+    _need(X, "X", _DT[cfg.act], (T, d))
+    _need(Wr, "Wr", torch.float32, (E, d))
+    _need(br, "br", torch.float32, (E,))
+    logits = torch.empty(T, E, dtype=torch.float32, device=X.device)
+    ws = _WS.get(cfg, X.device) if ws is None else ws
+    L.moe_router_logits(cfg, _p(X), _p(Wr), _p(br), _p(logits), _p(ws), ws.numel(), _stream())
+    return logits
+
+
 def dispatch(cfg, X, idx, ws=None, permute=True):
     """Slot maps and permuted tokens; with FP8 experts X_perm holds e4m3
     codes (uint8) and X_perm_scale the per-1x128-block scales.  With
@@ -143,6 +155,53 @@ def quantize_fp8(x, block_rows):
     L.moe_quantize_fp8(rows, cols, block_rows, L.MOE_BF16 if x.dtype == torch.bfloat16 else L.MOE_F32,
                        _p(x), _p(codes), _p(scales), _stream())
     return codes, scales
+
+
+MX_DTYPES = (L.MOE_MXFP8E4M3, L.MOE_MXFP6E2M3, L.MOE_MXFP4E2M1)
+
+
+def mx_row_bytes(fmt, K):
+    """Bytes of an MX code row of K elements (e2m1: two codes per byte;
+    e4m3 and the padded e2m3 layout: one byte per element)."""
+    return K // 2 if fmt == L.MOE_MXFP4E2M1 else K
+
+
+def quantize_mx(x, fmt):
+    """(codes uint8 [..., row bytes], scale bytes uint8 [..., K/32]) of a
+    contiguous f32/bf16 device tensor, quantised along its last dimension
+    in OCP MX blocks of 32."""
+    if x.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("quantize_mx takes float32 or bfloat16")
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("quantize_mx takes a contiguous device tensor")
+    if fmt not in MX_DTYPES:
+        raise ValueError(f"not an MX format: {fmt}")
+    K = x.shape[-1]
+    rows = x.numel() // max(K, 1)
+    codes = torch.empty(tuple(x.shape[:-1]) + (mx_row_bytes(fmt, K),), dtype=torch.uint8,
+                        device=x.device)
+    scales = torch.empty(tuple(x.shape[:-1]) + (K // 32,), dtype=torch.uint8, device=x.device)
+    L.moe_quantize_mx(rows, K, fmt, L.MOE_BF16 if x.dtype == torch.bfloat16 else L.MOE_F32,
+                      _p(x), _p(codes), _p(scales), _stream())
+    return codes, scales
+
+
+def expert_ffn_mx(cfg, X_codes, X_scale, row_map, offsets, W13, W13_scale, W2, W2_scale, ws=None):
+    N, d, E, f = cfg.T * cfg.k, cfg.d, cfg.E, cfg.d_ff
+    fmt = cfg.w
+    _need(X_codes, "X_codes", torch.uint8, (cfg.T, mx_row_bytes(fmt, d)))
+    _need(X_scale, "X_scale", torch.uint8, (cfg.T, d // 32))
+    _need(row_map, "row_map", torch.int32, (N,))
+    _need(offsets, "offsets", torch.int32, (E + 1,))
+    _need(W13, "W13", torch.uint8, (E, 2 * f, mx_row_bytes(fmt, d)))
+    _need(W13_scale, "W13_scale", torch.uint8, (E, 2 * f, d // 32))
+    _need(W2, "W2", torch.uint8, (E, d, mx_row_bytes(fmt, f)))
+    _need(W2_scale, "W2_scale", torch.uint8, (E, d, f // 32))
+    Y = torch.empty(N, d, dtype=torch.bfloat16, device=X_codes.device)
+    ws = _WS.get(cfg, X_codes.device) if ws is None else ws
+    L.moe_expert_ffn_mx(cfg, _p(X_codes), _p(X_scale), _p(row_map), _p(offsets), _p(W13),
+                        _p(W13_scale), _p(W2), _p(W2_scale), _p(Y), _p(ws), ws.numel(), _stream())
+    return Y
 
 
 def combine(cfg, Y, inv_map, w):
@@ -223,6 +282,13 @@ def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None, 
     if fuse and gather_fused(cfg):
         dsp = dispatch(cfg, X, r["idx"], permute=False)
         Y = expert_ffn_gather(cfg, X, dsp["row_map"], dsp["offsets"], W13, W2)
+    elif cfg.w in MX_DTYPES:
+        # tokens MX-quantised once, gathered by the first product
+        Xq, Xs = quantize_mx(X, cfg.w)
+        dsp = dispatch(cfg, X, r["idx"], permute=False)
+        Y = expert_ffn_mx(cfg, Xq, Xs, dsp["row_map"], dsp["offsets"], W13, W13_scale, W2,
+                          W2_scale)
+        r["X_codes"], r["X_scale"] = Xq, Xs
     elif fuse and gather_fused_fp8(cfg):
         # tokens quantised once (1 x 128 blocks), gathered by the first product
         Xq, Xs = quantize_fp8(X, 1)

@@ -262,3 +262,22 @@ def verdict_dict(r):
     return {"V": float(v[VERDICT_V]), "gap_learned": float(v[VERDICT_GAP]),
             "kept": bool(v[VERDICT_KEPT] == 1.0), "gap": float(v[VERDICT_GAP_FINAL]),
             "learned_iters": int(v[VERDICT_ITERS])}
+
+
+def learned_layer_forward(cfg, X, Wr, br, W13, W2, params, mode="warm", gamma=0.9,
+                          gap_tol=GAP_TOL):
+    """The layer forward with learned prices (BF16 experts): router logits,
+    statistics and the price network, the judged routing (warm start or
+    replacement, the exact update as judge and fallback), dispatch maps, the
+    gather-fused expert products and the combine.  No host synchronisation.
+    Returns the routing dict plus Y and out."""
+    from . import layer
+    logits = layer.router_logits(cfg, X, Wr, br)
+    r = learned_route(cfg, logits, params, mode, gamma, gap_tol)
+    dsp = layer.dispatch(cfg, X, r["idx"], permute=False)
+    Y = layer.expert_ffn_gather(cfg, X, dsp["row_map"], dsp["offsets"], W13, W2)
+    r.update(dsp)
+    r["logits"] = logits
+    r["Y"] = Y
+    r["out"] = layer.combine(cfg, Y, dsp["inv_map"], r["w"])
+    return r
