@@ -481,10 +481,10 @@ def learned_prices(args, dev, torch, L, price, layer, synth):
             return price.route_logits(cfg, logits)
 
         def warm():
-            return price.learned_route(cfg, logits, params, mode="warm")
+            return price.learned_route(cfg, logits, params, mode="warm", fallback="host")
 
         def replace():
-            return price.learned_route(cfg, logits, params, mode="replace")
+            return price.learned_route(cfg, logits, params, mode="replace", fallback="host")
 
         res = {}
         for name, fn in (("cold", cold), ("warm", warm), ("replace", replace)):
@@ -509,7 +509,8 @@ def learned_prices(args, dev, torch, L, price, layer, synth):
             return layer.forward(cfg, X, Wr_d, br_d, W13, W2, check=False)
 
         def layer_warm():
-            return price.learned_layer_forward(cfg, X, Wr_d, br_d, W13, W2, params, mode="warm")
+            return price.learned_layer_forward(cfg, X, Wr_d, br_d, W13, W2, params, mode="warm",
+                                               fallback="host")
 
         for name, fn in (("layer_cold", layer_cold), ("layer_learned_warm", layer_warm)):
             for _ in range(2):

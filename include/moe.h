@@ -228,6 +228,20 @@ moe_status moe_route_judged(const moe_cfg* cfg, const float* logits, const float
                             size_t ws_bytes, void* stream);
 
 /*
+ * moe_route_learned -- steps 1) and 2) of moe_route_judged without the
+ *   device fallback: the learned routing, its certificate and the verdict
+ *   (verdict[2] = 1 if the judge keeps it, verdict[3] = its relative gap),
+ *   leaving the routing in the outputs either way.  For callers that read
+ *   the verdict and route again themselves only when it is 0 (one host
+ *   wait instead of the always-enqueued fallback pass).  Arguments as in
+ *   moe_route_judged.
+ */
+moe_status moe_route_learned(const moe_cfg* cfg, const float* logits, const float* price_hat,
+                             float gap_tol, float* price, int32_t* topk_idx, float* topk_w,
+                             int32_t* load, int32_t* info, double* verdict, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/*
  * Learned starting prices.  Eight statistics of a batch of logits per
  * expert feed a small network shared by all experts whose output,
  * p_hat_e = sigma * softplus(z_e), predicts the prices the clearing-price

@@ -72,6 +72,7 @@ SIGNATURES = {
     "moe_price_update": [_CFG, _P, _P, _P, _P, _S, _P],
     "moe_route_certify": [_CFG, _P, _P, _P, _P, _P, _S, _P],
     "moe_route_judged": [_CFG, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_route_learned": [_CFG, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_logit_stats": [_CFG, _P, _P, _P, _P, _S, _P],
     "moe_price_mlp_sizes": [ctypes.c_int, ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)],
@@ -230,6 +231,13 @@ def moe_route_judged(cfg, logits, price_hat, gap_tol, price, topk_idx, topk_w, l
     _check(lib().moe_route_judged(ctypes.byref(cfg), logits, price_hat, float(gap_tol), price,
                                   topk_idx, topk_w, load, info, verdict, ws, ws_bytes, stream),
            "moe_route_judged")
+
+
+def moe_route_learned(cfg, logits, price_hat, gap_tol, price, topk_idx, topk_w, load, info,
+                     verdict, ws, ws_bytes, stream):
+    _check(lib().moe_route_learned(ctypes.byref(cfg), logits, price_hat, float(gap_tol), price,
+                                  topk_idx, topk_w, load, info, verdict, ws, ws_bytes, stream),
+           "moe_route_learned")
 
 
 def moe_logit_stats(cfg, logits, feats, sigma, ws, ws_bytes, stream):

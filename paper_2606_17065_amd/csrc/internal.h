@@ -17,7 +17,7 @@ size_t cert_ws_bytes(const moe_cfg& c);
 size_t judged_ws_bytes(const moe_cfg& c);
 
 // Certificate of a routing under prices (moe_route_certify without the
-// checks): part holds 2 * (ceil(T / 256) + 1) doubles, cert[3] receives
+// checks): part holds 2 * (ceil(T / 64) + 1) doubles, cert[3] receives
 // primal, dual and the relative gap.
 void launch_certify(const moe_cfg& c, const float* logits, const float* price,
                     const int32_t* topk_idx, double* part, double* cert, void* stream);

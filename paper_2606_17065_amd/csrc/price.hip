@@ -37,14 +37,67 @@ __device__ __forceinline__ void top_insert(uint32_t (&K)[L], int (&X)[L], uint32
   }
 }
 
-// One thread per token: the best k+1 experts at zero prices.
+// Top-L of experts [e_lo, e_hi) of one token's row, a_e = row[e] (- p[e]
+// when PRICED), sorted by (key descending, expert ascending), experts
+// inserted in ascending order.  The row is read 32 values at a time with
+// in-bounds (clamped) addresses, so the loads of a batch are in flight
+// together.
+template <int L, bool PRICED>
+__device__ __forceinline__ void row_top_range(const float* __restrict__ row, const float* p,
+                                              int e_lo, int e_hi, uint32_t (&K)[L],
+                                              int (&X)[L]) {
+  for (int e0 = e_lo; e0 < e_hi; e0 += 32) {
+    float v[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = row[min(e0 + i, e_hi - 1)];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      if (e0 + i < e_hi) {
+        const float a = PRICED ? v[i] - p[e0 + i] : v[i];
+        top_insert<L>(K, X, f32_key(a), e0 + i);
+      }
+    }
+  }
+}
+
+// RS consecutive lanes share one token: each scans a contiguous range of
+// the experts, then the lists are merged across the RS lanes (butterfly of
+// exchanges, each inserting the partner's entries); every lane ends with
+// the token's full list.  Entries compare by (key, expert), so the result
+// is the same list a single in-order scan gives.  Call with every lane of
+// the wavefront (the exchanges are cross-lane); inactive lanes pass an
+// empty range.
+constexpr int RS = 4;
+
+template <int L, bool PRICED>
+__device__ __forceinline__ void row_top_split(const float* __restrict__ row, const float* p,
+                                              int E, int sub, bool active, uint32_t (&K)[L],
+                                              int (&X)[L]) {
+  const int chunk = (E + RS - 1) / RS;
+  const int e_lo = min(E, sub * chunk), e_hi = min(E, e_lo + chunk);
+  if (active && e_hi > e_lo) row_top_range<L, PRICED>(row, p, e_lo, e_hi, K, X);
+#pragma unroll
+  for (int o = 1; o < RS; o <<= 1) {
+    uint32_t K2[L];
+    int X2[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      K2[j] = (uint32_t)__shfl_xor((int)K[j], o, 64);
+      X2[j] = __shfl_xor(X[j], o, 64);
+    }
+#pragma unroll
+    for (int j = 0; j < L; ++j) top_insert<L>(K, X, K2[j], X2[j]);
+  }
+}
+
+// RS threads per token: the best k+1 experts at zero prices.
 template <int L>
 __global__ __launch_bounds__(256) void ls_rows(const float* __restrict__ s, int T, int E, int k,
                                                uint32_t* __restrict__ kkey,
                                                int32_t* __restrict__ kexp,
                                                float* __restrict__ kap) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= T) return;
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int t = g / RS, sub = g % RS;
   uint32_t K[L];
   int X[L];
 #pragma unroll
@@ -52,8 +105,8 @@ __global__ __launch_bounds__(256) void ls_rows(const float* __restrict__ s, int 
     K[j] = 0u;
     X[j] = E;
   }
-  const float* row = s + (size_t)t * E;
-  for (int e = 0; e < E; ++e) top_insert<L>(K, X, f32_key(row[e]), e);
+  row_top_split<L, false>(s + (size_t)min(t, T - 1) * E, nullptr, E, sub, t < T, K, X);
+  if (t >= T || sub != 0) return;
   uint32_t k1 = K[0], k2 = K[0];
   int e1 = X[0];
 #pragma unroll
@@ -355,18 +408,21 @@ __global__ __launch_bounds__(256) void cert_tokens(const float* __restrict__ s,
                                                    const int32_t* __restrict__ idx, int T, int E,
                                                    int k, double* __restrict__ part) {
   __shared__ double sp[256], sd[256];
-  const int tid = threadIdx.x, t = blockIdx.x * 256 + tid;
+  __shared__ float ps[MOE_MAX_E];
+  const int tid = threadIdx.x, t = blockIdx.x * (256 / RS) + tid / RS, sub = tid % RS;
+  for (int e = tid; e < E; e += 256) ps[e] = p[e];
+  __syncthreads();
   double prim = 0.0, dual = 0.0;
-  if (t < T) {
-    uint32_t K[L];
-    int X[L];
+  uint32_t K[L];
+  int X[L];
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-      K[j] = 0u;
-      X[j] = 0;
-    }
-    const float* row = s + (size_t)t * E;
-    for (int e = 0; e < E; ++e) top_insert<L>(K, X, f32_key(row[e] - p[e]), e);
+  for (int j = 0; j < L; ++j) {
+    K[j] = 0u;
+    X[j] = 0;
+  }
+  const float* row = s + (size_t)min(t, T - 1) * E;
+  row_top_split<L, true>(row, ps, E, sub, t < T, K, X);
+  if (t < T && sub == 0) {
 #pragma unroll
     for (int j = 0; j < L; ++j)
       if (j < k) dual += (double)row[X[j]] - (double)p[X[j]];
@@ -391,14 +447,30 @@ __global__ __launch_bounds__(256) void cert_tokens(const float* __restrict__ s,
   }
 }
 
-__global__ void cert_final(const double* __restrict__ part, int nb, const float* __restrict__ p,
-                           int E, int C, double* __restrict__ cert) {
-  if (threadIdx.x != 0) return;
-  double prim = 0.0, dual = 0.0, ps = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    prim += part[2 * b];
-    dual += part[2 * b + 1];
+// Fixed order: thread i folds block partials i, i + 256, ... in order, then
+// the 256 sums are halved (stride 128..1); the prices are summed in order.
+__global__ __launch_bounds__(256) void cert_final(const double* __restrict__ part, int nb,
+                                                  const float* __restrict__ p, int E, int C,
+                                                  double* __restrict__ cert) {
+  __shared__ double sp[256], sd[256];
+  const int tid = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int j = tid; j < nb; j += 256) {
+    a += part[2 * j];
+    b += part[2 * j + 1];
   }
+  sp[tid] = a;
+  sd[tid] = b;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (tid < h) {
+      sp[tid] += sp[tid + h];
+      sd[tid] += sd[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  double prim = sp[0], dual = sd[0], ps = 0.0;
   for (int e = 0; e < E; ++e) ps += (double)p[e];
   dual += (double)C * ps;
   cert[0] = prim;
@@ -443,7 +515,7 @@ size_t stats_ws_bytes(const moe_cfg& c) {
 }
 
 size_t cert_ws_bytes(const moe_cfg& c) {
-  return align_up(sizeof(double) * 2 * (((size_t)c.T + 255) / 256 + 1), 256);
+  return align_up(sizeof(double) * 2 * (((size_t)c.T + 63) / 64 + 1), 256);
 }
 
 extern "C" moe_status moe_logit_stats(const moe_cfg* cfg, const float* logits, float* feats,
@@ -458,7 +530,7 @@ extern "C" moe_status moe_logit_stats(const moe_cfg* cfg, const float* logits, f
   hipStream_t st = (hipStream_t)stream;
   StatsWs w = carve_stats(c, ws, nullptr);
   const int L = c.k + 1;
-  const dim3 gr((c.T + 255) / 256);
+  const dim3 gr((unsigned)(((size_t)c.T * RS + 255) / 256));
   if (L <= 3)
     hipLaunchKernelGGL(HIP_KERNEL_NAME(ls_rows<3>), gr, dim3(256), 0, st, logits, c.T, c.E, c.k,
                        w.kkey, w.kexp, w.kap);
@@ -500,7 +572,7 @@ extern "C" moe_status moe_route_certify(const moe_cfg* cfg, const float* logits,
 void launch_certify(const moe_cfg& c, const float* logits, const float* price,
                     const int32_t* topk_idx, double* part, double* cert, void* stream) {
   hipStream_t st = (hipStream_t)stream;
-  const int nb = (c.T + 255) / 256;
+  const int nb = (c.T + 256 / RS - 1) / (256 / RS);  // 64 tokens per block
   if (nb > 0) {
     const int L = c.k;
     if (L <= 2)
@@ -516,7 +588,7 @@ void launch_certify(const moe_cfg& c, const float* logits, const float* price,
       hipLaunchKernelGGL(HIP_KERNEL_NAME(cert_tokens<16>), dim3(nb), dim3(256), 0, st, logits,
                          price, topk_idx, c.T, c.E, c.k, part);
   }
-  hipLaunchKernelGGL(cert_final, dim3(1), dim3(64), 0, st, part, nb, price, c.E, c.capacity,
+  hipLaunchKernelGGL(cert_final, dim3(1), dim3(256), 0, st, part, nb, price, c.E, c.capacity,
                      cert);
 }
 

@@ -144,7 +144,10 @@ __global__ __launch_bounds__(256) void router_split(const float* __restrict__ Wr
 // block's experts go through LDS; each wavefront reads its own token
 // fragments straight from HBM.  Every product is exact in FP32 and the
 // accumulation runs plane by plane within each K step.
-template <int KS>
+// TPB tokens per block: 128 (each wavefront 32 tokens x 64 experts) or 64
+// (each wavefront 32 tokens x 32 experts, twice the blocks for batches too
+// short to fill the chip with 128-token blocks).
+template <int KS, int TPB>
 __global__ __launch_bounds__(256) void router_logits_mfma(const bf16_t* __restrict__ X,
                                                           const bf16_t* __restrict__ W3,
                                                           const float* __restrict__ br,
@@ -155,9 +158,11 @@ __global__ __launch_bounds__(256) void router_logits_mfma(const bf16_t* __restri
   constexpr int CPR = KS / 8;               // 16-byte chunks per weight row and step
   constexpr int WCH = 3 * 64 * CPR / 256;   // chunks per thread
   constexpr int KSUB = KS / 16;             // MFMA K steps per K step
+  constexpr int NJ = TPB == 128 ? 2 : 1;    // 32-expert tiles per wavefront
   __shared__ __attribute__((aligned(16))) bf16_t Ws[3 * 64 * LDK];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int t0 = blockIdx.x * 128 + wv * 32;
+  const int t0 = blockIdx.x * TPB + (TPB == 128 ? wv * 32 : (wv & 1) * 32);
+  const int jb = TPB == 128 ? 0 : (wv >> 1);
   const int e0 = blockIdx.y * 64;
   const size_t plane = (size_t)E * d;
   const int fr = lane & 31, fk = (lane >> 5) * 8;
@@ -182,9 +187,9 @@ __global__ __launch_bounds__(256) void router_logits_mfma(const bf16_t* __restri
                                wcol[r])                                                   \
              : u32x4{0u, 0u, 0u, 0u};                                                     \
   _Pragma("unroll") for (int u = 0; u < KSUB; ++u) xa[u] = *(const bf16x8*)(xr + (k0) + 16 * u);
-  f32x16 acc[2];
+  f32x16 acc[NJ];
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
+  for (int j = 0; j < NJ; ++j)
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[j][q] = 0.0f;
   RLOAD(0);
@@ -197,12 +202,13 @@ __global__ __launch_bounds__(256) void router_logits_mfma(const bf16_t* __restri
     __syncthreads();
     if (k0 + KS < d) { RLOAD(k0 + KS); }
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int pl = 0; pl < 3; ++pl)
 #pragma unroll
         for (int u = 0; u < KSUB; ++u) {
-          const bf16x8 w = *(const bf16x8*)(Ws + (pl * 64 + j * 32 + fr) * LDK + 16 * u + fk);
+          const bf16x8 w =
+              *(const bf16x8*)(Ws + (pl * 64 + (jb + j) * 32 + fr) * LDK + 16 * u + fk);
           acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w, x[u], acc[j], 0, 0, 0);
         }
     __syncthreads();
@@ -211,10 +217,10 @@ __global__ __launch_bounds__(256) void router_logits_mfma(const bf16_t* __restri
   // lane holds token trow and experts e0 + 32 j + 8 (q/4) + 4 (lane/32) + q%4
   if (tvalid) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int eb = e0 + j * 32 + g * 8 + (lane >> 5) * 4;
+        const int eb = e0 + (jb + j) * 32 + g * 8 + (lane >> 5) * 4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int e = eb + q;
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(SIG_BLOCK) void score_partials(const float* __restr
     for (int e0 = 0; e0 < E; e0 += 64) {
       float xv[64];
 #pragma unroll
-      for (int i = 0; i < 64; ++i) xv[i] = e0 + i < E ? sT[(size_t)(e0 + i) * T + t] : 0.0f;
+      for (int i = 0; i < 64; ++i) xv[i] = sT[(size_t)min(e0 + i, E - 1) * T + t];
 #pragma unroll
       for (int i = 0; i < 64; ++i) {
         if (e0 + i < E) {
@@ -1182,13 +1188,25 @@ void launch_router(const moe_cfg& c, const RouteWs& w, const void* X, const floa
   else {
     const int n = c.E * c.d;
     hipLaunchKernelGGL(router_split, dim3((n + 255) / 256), dim3(256), 0, st, Wr, n, w.W3);
-    const dim3 g((c.T + 127) / 128, (c.E + 63) / 64);
-    if (c.d % 128 == 0)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<128>), g, dim3(256), 0, st,
-                         (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<32>), g, dim3(256), 0, st,
-                         (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+    // 128-token blocks once they give at least two blocks per CU, 64 below
+    const int eg = (c.E + 63) / 64;
+    const bool big = (size_t)((c.T + 127) / 128) * eg >= 512;
+    const dim3 g(big ? (c.T + 127) / 128 : (c.T + 63) / 64, eg);
+    if (c.d % 128 == 0) {
+      if (big)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<128, 128>), g, dim3(256), 0, st,
+                           (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<128, 64>), g, dim3(256), 0, st,
+                           (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+    } else {
+      if (big)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<32, 128>), g, dim3(256), 0, st,
+                           (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(router_logits_mfma<32, 64>), g, dim3(256), 0, st,
+                           (const bf16_t*)X, w.W3, br, logits, w.sT, c.T, c.d, c.E);
+    }
   }
   PROF_END("router_logits", st);
 }
@@ -1376,14 +1394,14 @@ __global__ void judge_init(int32_t* state, int E, const float* __restrict__ p_ha
 // would meet the same logits).
 __global__ void judge_decide(const double* __restrict__ cert, int32_t* state,
                              float* __restrict__ price, int E, int N, float gap_tol,
-                             double* __restrict__ verdict) {
+                             double* __restrict__ verdict, int reset) {
   __shared__ int keep_s;
   const int tid = threadIdx.x;
   if (tid == 0) {
     const int status = state[ST_STATUS];
     const double gap = cert[2];
     const bool ok = status == MOE_OK && gap <= (double)gap_tol;
-    const bool keep = ok || status == MOE_ENAN;
+    const bool keep = ok || status == MOE_ENAN || !reset;
     verdict[0] = (double)state[ST_OVERFLOW] / (double)(N > 0 ? N : 1);
     verdict[1] = status == MOE_OK ? gap : __builtin_nan("");
     verdict[2] = ok ? 1.0 : 0.0;
@@ -1437,7 +1455,7 @@ JudgeScratch carve_judge_scratch(const moe_cfg& c, void* base, size_t* total) {
   const size_t head = route_ws_bytes(c);
   WsCarve wc{base ? (char*)base + head : nullptr, 0};
   JudgeScratch r;
-  r.part = wc.take<double>(2 * (((size_t)c.T + 255) / 256 + 1));
+  r.part = wc.take<double>(2 * (((size_t)c.T + 63) / 64 + 1));
   r.cert = wc.take<double>(4);
   if (total) *total = head + align_up(wc.off, 256);
   return r;
@@ -1451,11 +1469,12 @@ size_t judged_ws_bytes(const moe_cfg& c) {
   return total;
 }
 
-extern "C" moe_status moe_route_judged(const moe_cfg* cfg, const float* logits,
-                                       const float* price_hat, float gap_tol, float* price,
-                                       int32_t* topk_idx, float* topk_w, int32_t* load,
-                                       int32_t* info, double* verdict, void* ws, size_t ws_bytes,
-                                       void* stream) {
+namespace {
+
+moe_status route_learned_impl(const moe_cfg* cfg, const float* logits, const float* price_hat,
+                              float gap_tol, float* price, int32_t* topk_idx, float* topk_w,
+                              int32_t* load, int32_t* info, double* verdict, void* ws,
+                              size_t ws_bytes, void* stream, bool device_fallback) {
   moe_status stc = check_cfg_shape(cfg);
   if (stc != MOE_OK) return stc;
   const moe_cfg& c = *cfg;
@@ -1485,16 +1504,38 @@ extern "C" moe_status moe_route_judged(const moe_cfg* cfg, const float* logits,
   if (stc != MOE_OK) return stc;
   launch_certify(c, logits, price, topk_idx, js.part, js.cert, st);
   hipLaunchKernelGGL(judge_decide, dim3(1), dim3(256), 0, st, js.cert, w.state, price, c.E,
-                     c.T * c.k, gap_tol, verdict);
-  // 2) the fallback: the update from p = 0 (nothing runs if the learned
-  //    routing was kept)
-  moe_cfg c0 = c;
-  c0.price_mode = MOE_PRICE_ACP;
-  launch_loop(c0, w, logits, price, topk_idx, topk_w, load, c.max_iters, st);
-  hipLaunchKernelGGL(route_finalize, dim3(1), dim3(64), 0, st, w.state, info, load, c.T, c.E,
-                     c.k, 0);
-  launch_certify(c, logits, price, topk_idx, js.part, js.cert, st);
+                     c.T * c.k, gap_tol, verdict, device_fallback ? 1 : 0);
+  if (device_fallback) {
+    // 2) the fallback: the update from p = 0 (nothing runs if the learned
+    //    routing was kept)
+    moe_cfg c0 = c;
+    c0.price_mode = MOE_PRICE_ACP;
+    launch_loop(c0, w, logits, price, topk_idx, topk_w, load, c.max_iters, st);
+    hipLaunchKernelGGL(route_finalize, dim3(1), dim3(64), 0, st, w.state, info, load, c.T, c.E,
+                       c.k, 0);
+    launch_certify(c, logits, price, topk_idx, js.part, js.cert, st);
+  }
   hipLaunchKernelGGL(judge_final, dim3(1), dim3(64), 0, st, js.cert, w.state, verdict, 0);
   MOE_LAUNCH_CHECK();
   return MOE_OK;
+}
+
+}  // namespace
+
+extern "C" moe_status moe_route_judged(const moe_cfg* cfg, const float* logits,
+                                       const float* price_hat, float gap_tol, float* price,
+                                       int32_t* topk_idx, float* topk_w, int32_t* load,
+                                       int32_t* info, double* verdict, void* ws, size_t ws_bytes,
+                                       void* stream) {
+  return route_learned_impl(cfg, logits, price_hat, gap_tol, price, topk_idx, topk_w, load, info,
+                            verdict, ws, ws_bytes, stream, true);
+}
+
+extern "C" moe_status moe_route_learned(const moe_cfg* cfg, const float* logits,
+                                        const float* price_hat, float gap_tol, float* price,
+                                        int32_t* topk_idx, float* topk_w, int32_t* load,
+                                        int32_t* info, double* verdict, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  return route_learned_impl(cfg, logits, price_hat, gap_tol, price, topk_idx, topk_w, load, info,
+                            verdict, ws, ws_bytes, stream, false);
 }

@@ -212,12 +212,16 @@ def predict(cfg, logits, params):
 VERDICT_V, VERDICT_GAP, VERDICT_KEPT, VERDICT_GAP_FINAL, VERDICT_ITERS = range(5)
 
 
-def judged_route(cfg, logits, phat, mode="warm", gamma=0.9, gap_tol=GAP_TOL, ws=None):
+def judged_route(cfg, logits, phat, mode="warm", gamma=0.9, gap_tol=GAP_TOL, ws=None,
+                 fallback="device"):
     """moe_route_judged: the routing from learned prices p_hat, kept when the
     certificate's relative gap is <= gap_tol, else the exact update from
-    p = 0 (decided on the device).  Returns the routing dict plus the
-    verdict tensor [5] f64 (V, learned gap, kept, final gap, learned-pass
-    updates)."""
+    p = 0.  fallback="device" decides on the device (the fallback pass is
+    always enqueued and exits at once when it is not needed); "host" calls
+    moe_route_learned, reads the verdict (one wait for the stream) and runs
+    the update from p = 0 only when the judge rejected the learned routing.
+    Returns the routing dict plus the verdict tensor [5] f64 (V, learned
+    gap, kept, final gap, learned-pass updates)."""
     T, E, k = cfg.T, cfg.E, cfg.k
     _need(logits, "logits", torch.float32, (T, E))
     _need(phat, "price_hat", torch.float32, (E,))
@@ -234,13 +238,29 @@ def judged_route(cfg, logits, phat, mode="warm", gamma=0.9, gap_tol=GAP_TOL, ws=
                info=torch.empty(L.INFO_LEN, dtype=torch.int32, device=dev),
                verdict=torch.empty(5, dtype=torch.float64, device=dev))
     ws = _WS.get(c, dev) if ws is None else ws
-    L.moe_route_judged(c, _p(logits), _p(phat), gap_tol, _p(out["price"]), _p(out["idx"]),
-                       _p(out["w"]), _p(out["load"]), _p(out["info"]), _p(out["verdict"]), _p(ws),
-                       ws.numel(), _stream())
+    if fallback == "device":
+        L.moe_route_judged(c, _p(logits), _p(phat), gap_tol, _p(out["price"]), _p(out["idx"]),
+                           _p(out["w"]), _p(out["load"]), _p(out["info"]), _p(out["verdict"]),
+                           _p(ws), ws.numel(), _stream())
+        return out
+    if fallback != "host":
+        raise ValueError(f"unknown fallback {fallback!r}")
+    L.moe_route_learned(c, _p(logits), _p(phat), gap_tol, _p(out["price"]), _p(out["idx"]),
+                        _p(out["w"]), _p(out["load"]), _p(out["info"]), _p(out["verdict"]),
+                        _p(ws), ws.numel(), _stream())
+    if float(out["verdict"][VERDICT_KEPT].item()) != 1.0 and \
+            int(out["info"][L.INFO_STATUS].item()) != L.MOE_ENAN:
+        c0 = L.make_cfg(T, cfg.d, E, k, cfg.d_ff, cfg.capacity, cfg.max_iters, cfg.act, cfg.w,
+                        L.MOE_PRICE_ACP, gamma, cfg.price_stages)
+        r0 = route_logits(c0, logits, out["price"], ws=ws)
+        cert = certify(c0, logits, r0["price"], r0["idx"], ws=ws)
+        out.update({key: r0[key] for key in ("price", "idx", "w", "load", "info")})
+        out["verdict"][VERDICT_GAP_FINAL] = cert[2]
     return out
 
 
-def learned_route(cfg, logits, params, mode="warm", gamma=0.9, gap_tol=GAP_TOL):
+def learned_route(cfg, logits, params, mode="warm", gamma=0.9, gap_tol=GAP_TOL,
+                  fallback="device"):
     """Route one batch with learned prices (statistics, network, then
     moe_route_judged; no host synchronisation).
 
@@ -251,7 +271,7 @@ def learned_route(cfg, logits, params, mode="warm", gamma=0.9, gap_tol=GAP_TOL):
     batch is routed again by the exact update from p = 0.  Returns the
     routing dict plus p_hat and the verdict tensor."""
     phat = predict(cfg, logits, params)
-    r = judged_route(cfg, logits, phat, mode, gamma, gap_tol)
+    r = judged_route(cfg, logits, phat, mode, gamma, gap_tol, fallback=fallback)
     r["p_hat"] = phat
     return r
 
@@ -265,7 +285,7 @@ def verdict_dict(r):
 
 
 def learned_layer_forward(cfg, X, Wr, br, W13, W2, params, mode="warm", gamma=0.9,
-                          gap_tol=GAP_TOL):
+                          gap_tol=GAP_TOL, fallback="device"):
     """The layer forward with learned prices (BF16 experts): router logits,
     statistics and the price network, the judged routing (warm start or
     replacement, the exact update as judge and fallback), dispatch maps, the
@@ -273,7 +293,7 @@ def learned_layer_forward(cfg, X, Wr, br, W13, W2, params, mode="warm", gamma=0.
     Returns the routing dict plus Y and out."""
     from . import layer
     logits = layer.router_logits(cfg, X, Wr, br)
-    r = learned_route(cfg, logits, params, mode, gamma, gap_tol)
+    r = learned_route(cfg, logits, params, mode, gamma, gap_tol, fallback)
     dsp = layer.dispatch(cfg, X, r["idx"], permute=False)
     Y = layer.expert_ffn_gather(cfg, X, dsp["row_map"], dsp["offsets"], W13, W2)
     r.update(dsp)

@@ -350,16 +350,20 @@ def _assert_judged(cfg, r, s, phat, mode, tol, gamma=0.9):
 
 # learned prices: the exact clearing prices and a 10 % under-estimate of
 # them; tolerances that keep (1.0), judge (5e-3) and reject (0.0)
+@pytest.mark.parametrize("fallback", ["device", "host"])
 @pytest.mark.parametrize("tol", [1.0, 5e-3, 0.0])
 @pytest.mark.parametrize("scale", [1.0, 0.9])
 @pytest.mark.parametrize("mode", ["warm", "replace"])
-def test_judged_route_matches_oracle(mode, scale, tol):
+def test_judged_route_matches_oracle(mode, scale, tol, fallback):
+    """fallback "host": moe_route_learned, then the update from p = 0 only
+    when the verdict rejects the learned routing."""
     T, E, k = 3001, 48, 6
     s, sd = _logits(T, E, 93)
     cfg = _cfg(T, E, k)
     pstar = R.route(s, k, cfg.capacity, 50)["p"]
     phat = (pstar * F32(scale)).astype(F32)
-    r = P.judged_route(cfg, sd, torch.from_numpy(phat).cuda(), mode, gap_tol=tol)
+    r = P.judged_route(cfg, sd, torch.from_numpy(phat).cuda(), mode, gap_tol=tol,
+                       fallback=fallback)
     torch.cuda.synchronize()
     v, ref = _assert_judged(cfg, r, s, phat, mode, tol)
     if tol == 1.0:
