@@ -501,16 +501,18 @@ moe_status moe_combine_bwd(const moe_cfg* cfg, const void* dOut, const void* Y,
  * (not read from a saved X_perm), as are A = Xp W1^T and B = Xp W3^T:
  *   U = dY W2_e,  dA = U * B * silu'(A),  dB = U * silu(A),  h = silu(A) * B
  *   dX_perm = dA W1_e + dB W3_e              [N,d] act out
- *   dW13[e] = [dA | dB]^T Xp                 [E,2f,d] f32 out
- *   dW2[e]  = dY^T h                         [E,d,f] f32 out
- * with silu'(z) = s + z s (1 - s), s = 1/(1+exp(-z)).  Requires BF16
+ *   dW13[e] = [dA | dB]^T Xp                 [E,2f,d] out
+ *   dW2[e]  = dY^T h                         [E,d,f] out
+ * with silu'(z) = s + z s (1 - s), s = 1/(1+exp(-z)).  The weight
+ * gradients accumulate in FP32 and are stored as grad_dtype (MOE_F32, or
+ * MOE_BF16 rounded to nearest even; else MOE_EINVAL).  Requires BF16
  * activations and weights, d_ff % 128 == 0 and d % 256 == 0 (otherwise
  * MOE_EUNSUPPORTED).  X [T,d]; row_map [N]; offsets [E+1] from moe_dispatch.
  */
 moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X, const int32_t* row_map,
                               const int32_t* offsets, const void* dY, const void* W13,
-                              const void* W2, void* dX_perm, float* dW13, float* dW2, void* ws,
-                              size_t ws_bytes, void* stream);
+                              const void* W2, void* dX_perm, void* dW13, void* dW2,
+                              int grad_dtype, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * moe_dispatch_bwd -- derivative of moe_dispatch's permute:
@@ -524,7 +526,9 @@ moe_status moe_dispatch_bwd(const moe_cfg* cfg, const void* dX_perm, const int32
  * backward into one dX:
  *   ds[t,j] = w[t,j] (dw[t,j] - sum_i w[t,i] dw[t,i])   (softmax over the
  *             chosen experts' raw logits; dw = dtopk_w)
- *   dX[t]   = sum_j dX_perm[inv_map[t,j]] + sum_j ds[t,j] W_r[e_j]   (f32 out)
+ *   dX[t]   = sum_j dX_perm[inv_map[t,j]] + sum_j ds[t,j] W_r[e_j]   [T,d] out
+ *             (FP32 sums stored as dx_dtype: MOE_F32, or MOE_BF16 rounded
+ *             to nearest even; else MOE_EINVAL)
  *   dWr[e]  = sum over the slots of e of ds * X[t]                    [E,d] f32
  *   dbr[e]  = sum of the same ds                                      [E] f32
  *   (the sums run over chunks of 64 slots in slot order, whose partial
@@ -534,8 +538,8 @@ moe_status moe_dispatch_bwd(const moe_cfg* cfg, const void* dX_perm, const int32
 moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const float* Wr,
                          const int32_t* topk_idx, const float* topk_w, const float* dtopk_w,
                          const int32_t* row_map, const int32_t* offsets, const int32_t* inv_map,
-                         const void* dX_perm, float* dX, float* dWr, float* dbr, void* ws,
-                         size_t ws_bytes, void* stream);
+                         const void* dX_perm, void* dX, int dx_dtype, float* dWr, float* dbr,
+                         void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Optional per-kernel timing for benchmarks (host bookkeeping, not

@@ -65,9 +65,10 @@ SIGNATURES = {
     "moe_quantize_fp8": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P],
     "moe_combine": [_CFG, _P, _P, _P, _P, _P],
     "moe_combine_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P],
-    "moe_expert_ffn_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_expert_ffn_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int, _P, _S, _P],
     "moe_dispatch_bwd": [_CFG, _P, _P, _P, _P],
-    "moe_route_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_route_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int, _P, _P, _P, _S,
+                      _P],
     "moe_route_logits": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_price_update": [_CFG, _P, _P, _P, _P, _S, _P],
     "moe_route_certify": [_CFG, _P, _P, _P, _P, _P, _S, _P],
@@ -188,10 +189,11 @@ def moe_combine_bwd(cfg, dOut, Y, inv_map, topk_w, dY, dtopk_w, stream):
            "moe_combine_bwd")
 
 
-def moe_expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, dX_perm, dW13, dW2, ws, ws_bytes,
-                       stream):
+def moe_expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, dX_perm, dW13, dW2, grad_dtype, ws,
+                       ws_bytes, stream):
     _check(lib().moe_expert_ffn_bwd(ctypes.byref(cfg), X, row_map, offsets, dY, W13, W2, dX_perm,
-                                    dW13, dW2, ws, ws_bytes, stream), "moe_expert_ffn_bwd")
+                                    dW13, dW2, grad_dtype, ws, ws_bytes, stream),
+           "moe_expert_ffn_bwd")
 
 
 def moe_dispatch_noalloc(cfg, X, topk_idx, offsets, row_map, inv_map, X_perm, X_perm_scale,
@@ -205,10 +207,10 @@ def moe_dispatch_bwd(cfg, dX_perm, inv_map, dX, stream):
 
 
 def moe_route_bwd(cfg, X, Wr, topk_idx, topk_w, dtopk_w, row_map, offsets, inv_map, dX_perm, dX,
-                  dWr, dbr, ws, ws_bytes, stream):
+                  dx_dtype, dWr, dbr, ws, ws_bytes, stream):
     _check(lib().moe_route_bwd(ctypes.byref(cfg), X, Wr, topk_idx, topk_w, dtopk_w, row_map,
-                               offsets, inv_map, dX_perm, dX, dWr, dbr, ws, ws_bytes, stream),
-           "moe_route_bwd")
+                               offsets, inv_map, dX_perm, dX, dx_dtype, dWr, dbr, ws, ws_bytes,
+                               stream), "moe_route_bwd")
 
 
 def moe_route_logits(cfg, logits, price, topk_idx, topk_w, load, info, ws, ws_bytes, stream):

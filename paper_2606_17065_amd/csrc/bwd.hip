@@ -25,24 +25,45 @@ __global__ __launch_bounds__(256) void combine_bwd_kernel(const TA* __restrict__
                                                           const float* __restrict__ w,
                                                           TA* __restrict__ dY,
                                                           float* __restrict__ dw) {
+  // one wavefront per token, 8 consecutive elements per lane and step: the
+  // dOut segment is read once for all k slots; each slot's dot product
+  // runs over the elements in the same order as a slot-by-slot loop
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= T) return;
   const int N = T * k;
-  for (int j = 0; j < k; ++j) {
-    const int slot = clampi(inv_map[(size_t)t * k + j], 0, N - 1);
-    const float wj = w[(size_t)t * k + j];
-    float part = 0.0f;
-    for (int c0 = lane * 8; c0 < d; c0 += 64 * 8) {
+  int slots[MOE_MAX_K];
+  float ws_[MOE_MAX_K], part[MOE_MAX_K];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float g = ActIO<TA>::ld(dOut, (size_t)t * d + c0 + i);
-        part = __builtin_fmaf(g, ActIO<TA>::ld(Y, (size_t)slot * d + c0 + i), part);
-        ActIO<TA>::st(dY, (size_t)slot * d + c0 + i, wj * g);
+  for (int j = 0; j < MOE_MAX_K; ++j) {
+    slots[j] = j < k ? clampi(inv_map[(size_t)t * k + j], 0, N - 1) : 0;
+    ws_[j] = j < k ? w[(size_t)t * k + j] : 0.0f;
+    part[j] = 0.0f;
+  }
+  for (int c0 = lane * 8; c0 < d; c0 += 64 * 8) {
+    float g[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) g[i] = ActIO<TA>::ld(dOut, (size_t)t * d + c0 + i);
+#pragma unroll
+    for (int j = 0; j < MOE_MAX_K; ++j) {
+      if (j < k) {
+        const TA* yr = Y + (size_t)slots[j] * d + c0;
+        TA* dyr = dY + (size_t)slots[j] * d + c0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          part[j] = __builtin_fmaf(g[i], ActIO<TA>::ld(yr, i), part[j]);
+          ActIO<TA>::st(dyr, i, ws_[j] * g[i]);
+        }
       }
     }
-    for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
-    if (lane == 0) dw[(size_t)t * k + j] = part;
+  }
+#pragma unroll
+  for (int j = 0; j < MOE_MAX_K; ++j) {
+    if (j < k) {
+      float p = part[j];
+      for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off, 64);
+      if (lane == 0) dw[(size_t)t * k + j] = p;
+    }
   }
 }
 
@@ -51,11 +72,11 @@ __global__ __launch_bounds__(256) void combine_bwd_kernel(const TA* __restrict__
 // ds is formed here from w and dw (and written to ds_out).  Without ROUTER
 // idx, w, dw, Wr and ds_out are not touched (they may be null).  One
 // wavefront per token.
-template <typename TA, bool ROUTER>
+template <typename TA, bool ROUTER, typename TO>
 __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
     const TA* __restrict__ dXp, int T, int d, int k, int E, const int32_t* __restrict__ inv_map,
     const int32_t* __restrict__ idx, const float* __restrict__ w, const float* __restrict__ dw,
-    const float* __restrict__ Wr, float* __restrict__ dX, float* __restrict__ ds_out) {
+    const float* __restrict__ Wr, TO* __restrict__ dX, float* __restrict__ ds_out) {
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= T) return;
@@ -106,7 +127,7 @@ __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
       }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) dX[(size_t)t * d + c0 + i] = acc[i];
+    for (int i = 0; i < 4; ++i) ActIO<TO>::st(dX, (size_t)t * d + c0 + i, acc[i]);
   }
 }
 
@@ -256,11 +277,11 @@ extern "C" moe_status moe_dispatch_bwd(const moe_cfg* cfg, const void* dX_perm,
   hipStream_t st = (hipStream_t)stream;
   PROF_BEGIN("dispatch_bwd", st);
   if (c.act == MOE_F32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float, false>), dim3((c.T + 3) / 4),
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float, false, float>), dim3((c.T + 3) / 4),
                        dim3(256), 0, st, (const float*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr, nullptr,
                        nullptr, nullptr, dX, nullptr);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t, false>), dim3((c.T + 3) / 4),
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t, false, float>), dim3((c.T + 3) / 4),
                        dim3(256), 0, st, (const bf16_t*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr,
                        nullptr, nullptr, nullptr, dX, nullptr);
   PROF_END("dispatch_bwd", st);
@@ -272,11 +293,12 @@ extern "C" moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const flo
                                     const int32_t* topk_idx, const float* topk_w,
                                     const float* dtopk_w, const int32_t* row_map,
                                     const int32_t* offsets, const int32_t* inv_map,
-                                    const void* dX_perm, float* dX, float* dWr, float* dbr,
-                                    void* ws, size_t ws_bytes, void* stream) {
+                                    const void* dX_perm, void* dX, int dx_dtype, float* dWr,
+                                    float* dbr, void* ws, size_t ws_bytes, void* stream) {
   moe_status stc = check_cfg_shape(cfg);
   if (stc != MOE_OK) return stc;
   const moe_cfg& c = *cfg;
+  if (dx_dtype != MOE_F32 && dx_dtype != MOE_BF16) return MOE_EINVAL;
   if (!dWr || !dbr || !offsets) return MOE_EINVAL;
   if (c.T > 0 && (!X || !Wr || !topk_idx || !topk_w || !dtopk_w || !row_map || !inv_map ||
                   !dX_perm || !dX))
@@ -292,14 +314,16 @@ extern "C" moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const flo
   if (c.T > 0) {
     hipLaunchKernelGGL(slot_source, dim3((N + 255) / 256), dim3(256), 0, st, inv_map, N,
                        w.slot_src);
-    if (c.act == MOE_F32)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float, true>), dim3((c.T + 3) / 4),
-                         dim3(256), 0, st, (const float*)dX_perm, c.T, c.d, c.k, c.E, inv_map,
-                         topk_idx, topk_w, dtopk_w, Wr, dX, w.ds);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t, true>), dim3((c.T + 3) / 4),
-                         dim3(256), 0, st, (const bf16_t*)dX_perm, c.T, c.d, c.k, c.E, inv_map,
-                         topk_idx, topk_w, dtopk_w, Wr, dX, w.ds);
+#define DBWD(TA, TO)                                                                          \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<TA, true, TO>), dim3((c.T + 3) / 4),    \
+                     dim3(256), 0, st, (const TA*)dX_perm, c.T, c.d, c.k, c.E, inv_map, topk_idx, \
+                     topk_w, dtopk_w, Wr, (TO*)dX, w.ds);
+    if (c.act == MOE_F32) {
+      if (dx_dtype == MOE_F32) DBWD(float, float) else DBWD(float, bf16_t)
+    } else {
+      if (dx_dtype == MOE_F32) DBWD(bf16_t, float) else DBWD(bf16_t, bf16_t)
+    }
+#undef DBWD
   }
   const int nq = rw_nq(c);
   dim3 g(c.E, (c.d + 255) / 256, nq);

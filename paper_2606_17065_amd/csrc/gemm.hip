@@ -1232,7 +1232,19 @@ MOE_INST_MX(4)
 // Every product is "NT" with both operands contiguous along the reduction:
 // the weights are transposed once per call, and the activations that the
 // weight gradients reduce over are written transposed [channel][slot] with
-// each expert's slot range padded to a multiple of 32 with zeros.
+// each expert's slot range padded to a multiple of PADK with zeros.
+
+// Four consecutive weight-gradient values: FP32, or rounded to BF16.
+__device__ __forceinline__ void store4(float* p, float a, float b, float c, float d) {
+  *(f32x4*)p = (f32x4){a, b, c, d};
+}
+__device__ __forceinline__ void store4(bf16_t* p, float a, float b, float c, float d) {
+  *(bf16x4*)p = (bf16x4){(bf16_t)a, (bf16_t)b, (bf16_t)c, (bf16_t)d};
+}
+
+// Slot ranges of the transposed buffers are padded per expert to a multiple
+// of PADK (one K stage of the 256 x 256 weight-gradient tile).
+constexpr int PADK = 64;
 
 // One epilogue pass of gemm_dgrad1: PASS 0 = dA, 1 = dB, 2 = h.  Values
 // go to LDS transposed [column][row]; dA and dB also go row-major to dAB.
@@ -1330,7 +1342,7 @@ __global__ __launch_bounds__(256, 1) void gemm_dgrad1(
   stage_barrier();
 
   // three passes through LDS (dA, dB, h), each staged transposed [col][row]
-  const size_t pcol0 = (size_t)ptile[e] * 32 + (size_t)(row0 - offsets[e]);
+  const size_t pcol0 = (size_t)ptile[e] * PADK + (size_t)(row0 - offsets[e]);
   dgrad1_pass<0>(acc, lds, AB, dAB, dABT, ldT, row0, rows, n0, f, pcol0, wm, wn, tid, lane);
   dgrad1_pass<1>(acc, lds, AB, dAB, dABT, ldT, row0, rows, n0, f, pcol0, wm, wn, tid, lane);
   dgrad1_pass<2>(acc, lds, AB, dAB, hT, ldT, row0, rows, n0, f, pcol0, wm, wn, tid, lane);
@@ -1339,10 +1351,11 @@ __global__ __launch_bounds__(256, 1) void gemm_dgrad1(
 // Weight gradient of one expert: out_e[m][n] = sum over the expert's padded
 // slot range of At[m][k] * Bt[n][k] (both [rows][ldT], contiguous along k;
 // pads are zero).  Tile 256 x 128, FP32 results stored directly.
+template <typename TO>
 __global__ __launch_bounds__(256, 2) void gemm_wgrad(const bf16_t* __restrict__ At,
                                                      const bf16_t* __restrict__ Bt, int ldT,
                                                      const int32_t* __restrict__ ptile, int E,
-                                                     int M, int Nn, float* __restrict__ out,
+                                                     int M, int Nn, TO* __restrict__ out,
                                                      int m_tiles, int n_tiles, int grid_total) {
   __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
   const int b = blockIdx.x;
@@ -1354,8 +1367,8 @@ __global__ __launch_bounds__(256, 2) void gemm_wgrad(const bf16_t* __restrict__ 
   const int mt = rem / n_tiles, nt = rem - mt * n_tiles;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
-  const size_t k0 = (size_t)ptile[e] * 32;
-  const int nk = ptile[e + 1] - ptile[e];
+  const size_t k0 = (size_t)ptile[e] * PADK;
+  const int nk = (ptile[e + 1] - ptile[e]) * (PADK / GBK);
   const bf16_t* asrc[A_INS];
   const bf16_t* bsrc[B_INS];
 #pragma unroll
@@ -1376,7 +1389,7 @@ __global__ __launch_bounds__(256, 2) void gemm_wgrad(const bf16_t* __restrict__ 
   zero_acc(acc);
   mma_pipeline<A_INS, B_INS>(lds, asrc, bsrc, nk, wv, lane, aoff, asw, boff, bsw, acc);
   const int fr = lane & 31, cbase = (lane >> 5) * 4;
-  float* oe = out + (size_t)e * M * Nn;
+  TO* oe = out + (size_t)e * M * Nn;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const size_t m = (size_t)mt * GBM + wm * 128 + i * 32 + fr;
@@ -1385,13 +1398,143 @@ __global__ __launch_bounds__(256, 2) void gemm_wgrad(const bf16_t* __restrict__ 
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int n = nt * GBN + wn * 64 + j * 32 + g * 8 + cbase;
-        f32x4 v;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = acc[i][j][g * 4 + q];
-        *(f32x4*)(oe + m * Nn + n) = v;
+        store4(oe + m * Nn + n, acc[i][j][g * 4], acc[i][j][g * 4 + 1], acc[i][j][g * 4 + 2],
+               acc[i][j][g * 4 + 3]);
       }
   }
 }
+
+// Weight gradient on the 256 x 256 tile of gemm_bf16_wide (8 wavefronts,
+// K = 64 per stage, two 64 KB stages): out_e[m][n] = sum over the expert's
+// padded slot range of At[m][k] * Bt[n][k], FP32 results stored directly.
+// M and Nn are multiples of 256; an expert without slots stores zeros.
+template <typename TO>
+__global__ __launch_bounds__(64 * XW, 1) void gemm_wgrad_wide(
+    const bf16_t* __restrict__ At, const bf16_t* __restrict__ Bt, int ldT,
+    const int32_t* __restrict__ ptile, int E, int M, int Nn, TO* __restrict__ out,
+    int m_tiles, int n_tiles, int grid_total) {
+  typedef __attribute__((address_space(3))) void lds_void;
+  __shared__ __attribute__((aligned(1024))) char lds[2 * XSTAGE];
+  const int b = blockIdx.x;
+  const int per = grid_total >> 3;
+  const int Lt = (b & 7) * per + (b >> 3);
+  const int tiles_e = m_tiles * n_tiles;
+  if (Lt >= E * tiles_e) return;
+  const int e = Lt / tiles_e, rem = Lt - e * tiles_e;
+  const int mt = rem / n_tiles, nt = rem - mt * n_tiles;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 2, wn = wv & 3;
+  const size_t k0 = (size_t)ptile[e] * PADK;
+  const int nk = (ptile[e + 1] - ptile[e]) * (PADK / XBK);
+  const bf16_t* asrc[XA_INS];
+  const bf16_t* bsrc[XB_INS];
+#pragma unroll
+  for (int i = 0; i < XA_INS; ++i) {
+    const int R = wv * (GBM / XW) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
+    asrc[i] = At + (size_t)(mt * GBM + R) * ldT + k0 + c * 8;
+  }
+#pragma unroll
+  for (int i = 0; i < XB_INS; ++i) {
+    const int R = wv * (XBN / XW) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
+    bsrc[i] = Bt + (size_t)(nt * XBN + R) * ldT + k0 + c * 8;
+  }
+  const int fr = lane & 31, fh = lane >> 5;
+  int aoff[4], asw[4], boff[2], bsw[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int R = wm * 128 + i * 32 + fr;
+    aoff[i] = R * 128;
+    asw[i] = (R >> 1) & 7;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int R = wn * 64 + j * 32 + fr;
+    boff[j] = XSTAGE_A + R * 128;
+    bsw[j] = (R >> 1) & 7;
+  }
+  f32x16 acc[4][2];
+  zero_acc(acc);
+#define W_ISSUE(kstep)                                                                         \
+  {                                                                                            \
+    char* st_ = lds + ((kstep) & 1) * XSTAGE;                                                  \
+    const int k0_ = (kstep) * XBK;                                                             \
+    _Pragma("unroll") for (int i = 0; i < XA_INS; ++i) __builtin_amdgcn_global_load_lds(       \
+        asrc[i] + k0_, (lds_void*)(st_ + (wv * (GBM / XW) + i * 8) * 128), 16, 0, 0);          \
+    _Pragma("unroll") for (int i = 0; i < XB_INS; ++i) __builtin_amdgcn_global_load_lds(       \
+        bsrc[i] + k0_, (lds_void*)(st_ + XSTAGE_A + (wv * (XBN / XW) + i * 8) * 128), 16, 0,   \
+        0);                                                                                    \
+  }
+#define W_READ(AF, BF, stp, ks)                                                          \
+  {                                                                                      \
+    const char* st_ = lds + ((stp) & 1) * XSTAGE;                                        \
+    const int c_ = (ks) * 2 + fh;                                                        \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) AF[i] =                                \
+        *(const bf16x8*)(st_ + aoff[i] + ((c_ ^ asw[i]) << 4));                          \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) BF[j] =                                \
+        *(const bf16x8*)(st_ + boff[j] + ((c_ ^ bsw[j]) << 4));                          \
+  }
+#define W_MFMA(AF, BF)                                                                   \
+  _Pragma("unroll") for (int i = 0; i < 4; ++i) _Pragma("unroll") for (int j = 0; j < 2; \
+                                                                       ++j) acc[i][j] =  \
+      __builtin_amdgcn_mfma_f32_32x32x16_bf16(BF[j], AF[i], acc[i][j], 0, 0, 0);
+  if (nk > 0) {
+    bf16x8 a0[4], b0[2], a1[4], b1[2];
+    W_ISSUE(0);
+    if (nk > 1) {
+      W_ISSUE(1);
+      WAIT_VM_LGKM0(XA_INS + XB_INS);
+    } else {
+      WAIT_VM_LGKM0(0);
+    }
+    stage_barrier();
+    W_READ(a0, b0, 0, 0);
+    for (int kt = 0; kt < nk; ++kt) {
+      __builtin_amdgcn_iglp_opt(1);
+      W_READ(a1, b1, kt, 1);
+      W_MFMA(a0, b0);
+      W_READ(a0, b0, kt, 2);
+      W_MFMA(a1, b1);
+      W_READ(a1, b1, kt, 3);
+      W_MFMA(a0, b0);
+      WAIT_VM_LGKM0(0);
+      stage_barrier();
+      if (kt + 2 < nk) W_ISSUE(kt + 2);
+      if (kt + 1 < nk) W_READ(a0, b0, kt + 1, 0);
+      W_MFMA(a1, b1);
+    }
+  }
+#undef W_ISSUE
+#undef W_READ
+#undef W_MFMA
+  const int cbase = fh * 4;
+  TO* oe = out + (size_t)e * M * Nn;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const size_t m = (size_t)mt * GBM + wm * 128 + i * 32 + fr;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int n = nt * XBN + wn * 64 + j * 32 + g * 8 + cbase;
+        store4(oe + m * Nn + n, acc[i][j][g * 4], acc[i][j][g * 4 + 1], acc[i][j][g * 4 + 2],
+               acc[i][j][g * 4 + 3]);
+      }
+  }
+}
+
+#define MOE_INST_WG(TO)                                                                      \
+  template __global__ void gemm_wgrad<TO>(const bf16_t* __restrict__, const bf16_t* __restrict__, \
+                                          int, const int32_t* __restrict__, int, int, int,     \
+                                          TO* __restrict__, int, int, int);                    \
+  template __global__ void gemm_wgrad_wide<TO>(const bf16_t* __restrict__,                     \
+                                               const bf16_t* __restrict__, int,                \
+                                               const int32_t* __restrict__, int, int, int,     \
+                                               TO* __restrict__, int, int, int);
+MOE_INST_WG(float)
+MOE_INST_WG(bf16_t)
+#undef MOE_INST_WG
 
 // out[b][c][r] = in[b][r][c], 64 x 64 tiles through LDS.
 __global__ __launch_bounds__(256) void batched_transpose(const bf16_t* __restrict__ in,
@@ -1425,7 +1568,7 @@ __global__ __launch_bounds__(256) void slot_transpose(const bf16_t* __restrict__
   __shared__ __attribute__((aligned(16))) bf16_t tile[64][72];
   __shared__ int srow[64];
   const int p0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
-  const int total = ptile[E] * 32;
+  const int total = ptile[E] * PADK;
   if (p0 >= total) return;
   if (threadIdx.x < 64) {
     const int p = p0 + threadIdx.x;
@@ -1434,10 +1577,10 @@ __global__ __launch_bounds__(256) void slot_transpose(const bf16_t* __restrict__
       int lo = 0, hi = E - 1;  // largest e with pad_off[e] <= p
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (ptile[mid] * 32 <= p) lo = mid;
+        if (ptile[mid] * PADK <= p) lo = mid;
         else hi = mid - 1;
       }
-      const int i = p - ptile[lo] * 32;
+      const int i = p - ptile[lo] * PADK;
       if (i < offsets[lo + 1] - offsets[lo]) {
         r = offsets[lo] + i;
         if (row_map) r = min(max(row_map[r], 0), T - 1);
@@ -1477,7 +1620,7 @@ __global__ __launch_bounds__(256) void pad_zero(bf16_t* __restrict__ buf, int M,
   const int e = blockIdx.x;
   const int m = blockIdx.y * 256 + threadIdx.x;
   if (m >= M) return;
-  const int a = ptile[e] * 32 + (offsets[e + 1] - offsets[e]), z = ptile[e + 1] * 32;
+  const int a = ptile[e] * PADK + (offsets[e + 1] - offsets[e]), z = ptile[e + 1] * PADK;
   for (int p = a; p < z; ++p) buf[(size_t)m * ldT + p] = (bf16_t)0.0f;
 }
 
@@ -1738,10 +1881,10 @@ struct FfnBwdWs {
 };
 
 // Row pitch of the transposed slot-major buffers: every expert's slot range
-// padded to a multiple of 32, rounded up to 64 elements.
+// padded to a multiple of PADK, rounded up to 64 elements.
 int bwd_ldT(const moe_cfg& c) {
   const size_t N = (size_t)c.T * c.k;
-  return (int)align_up(N + (size_t)32 * c.E, 64);
+  return (int)align_up(N + (size_t)PADK * c.E, 64);
 }
 
 FfnBwdWs carve_ffn_bwd(const moe_cfg& c, void* base, size_t* total) {
@@ -1775,13 +1918,14 @@ size_t ffn_bwd_ws_bytes(const moe_cfg& c) {
 extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
                                          const int32_t* row_map, const int32_t* offsets,
                                          const void* dY, const void* W13, const void* W2,
-                                         void* dX_perm, float* dW13, float* dW2, void* ws,
-                                         size_t ws_bytes, void* stream) {
+                                         void* dX_perm, void* dW13, void* dW2, int grad_dtype,
+                                         void* ws, size_t ws_bytes, void* stream) {
   moe_status stc = check_cfg_shape(cfg);
   if (stc != MOE_OK) return stc;
   const moe_cfg& c = *cfg;
   if (c.act != MOE_BF16 || c.w != MOE_BF16) return MOE_EUNSUPPORTED;
   if (c.d_ff % 128 != 0 || c.d % 256 != 0) return MOE_EUNSUPPORTED;
+  if (grad_dtype != MOE_F32 && grad_dtype != MOE_BF16) return MOE_EINVAL;
   if (!offsets || !W13 || !W2 || !dW13 || !dW2) return MOE_EINVAL;
   if (c.T > 0 && (!X || !row_map || !dY || !dX_perm)) return MOE_EINVAL;
   if (!aligned(X, 16) || !aligned(dY, 16) || !aligned(W13, 16) || !aligned(W2, 16) ||
@@ -1796,7 +1940,7 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
   const bf16_t* dYb = (const bf16_t*)dY;
   PROF_BEGIN("ffn_bwd", st);
   hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, GBM, w.tile_start);
-  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, 32, w.ptile);
+  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, PADK, w.ptile);
   hipLaunchKernelGGL(batched_transpose, dim3(d / 64, 2 * f / 64, E), dim3(256), 0, st,
                      (const bf16_t*)W13, w.W13T, 2 * f, d);
   hipLaunchKernelGGL(batched_transpose, dim3(f / 64, d / 64, E), dim3(256), 0, st,
@@ -1830,15 +1974,28 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
     hipLaunchKernelGGL(pad_zero, dim3(E, (f + 255) / 256), dim3(256), 0, st, w.hT, f, w.ldT,
                        offsets, w.ptile);
   }
-  {  // dW13_e = [dA|dB]^T Xp (M = 2f, N = d); dW2_e = dY^T h (M = d, N = f)
-    const int m1 = 2 * f / GBM, n1 = d / GBN;
+  {  // dW13_e = [dA|dB]^T Xp (M = 2f, N = d); dW2_e = dY^T h (M = d, N = f);
+     // the 256 x 256 tile where the output width is a multiple of 256
+    const int m1 = 2 * f / GBM, n1 = d / XBN;  // d % 256 == 0 was checked
     const int G1 = (E * m1 * n1 + 7) / 8 * 8;
-    hipLaunchKernelGGL(gemm_wgrad, dim3(G1), dim3(256), 0, st, w.dABT, w.XpT, w.ldT, w.ptile, E,
-                       2 * f, d, dW13, m1, n1, G1);
-    const int m2 = d / GBM, n2 = f / GBN;
+    const int m2 = d / GBM;
+    const bool wide2 = f % XBN == 0;
+    const int n2 = wide2 ? f / XBN : f / GBN;
     const int G2 = (E * m2 * n2 + 7) / 8 * 8;
-    hipLaunchKernelGGL(gemm_wgrad, dim3(G2), dim3(256), 0, st, w.dYT, w.hT, w.ldT, w.ptile, E, d,
-                       f, dW2, m2, n2, G2);
+#define WGRAD(TO)                                                                              \
+  {                                                                                            \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_wgrad_wide<TO>), dim3(G1), dim3(64 * XW), 0, st,   \
+                       w.dABT, w.XpT, w.ldT, w.ptile, E, 2 * f, d, (TO*)dW13, m1, n1, G1);     \
+    if (wide2)                                                                                 \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_wgrad_wide<TO>), dim3(G2), dim3(64 * XW), 0, st, \
+                         w.dYT, w.hT, w.ldT, w.ptile, E, d, f, (TO*)dW2, m2, n2, G2);          \
+    else                                                                                       \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_wgrad<TO>), dim3(G2), dim3(256), 0, st, w.dYT,   \
+                         w.hT, w.ldT, w.ptile, E, d, f, (TO*)dW2, m2, n2, G2);                 \
+  }
+    if (grad_dtype == MOE_BF16) WGRAD(bf16_t)
+    else WGRAD(float)
+#undef WGRAD
   }
   PROF_END("ffn_bwd", st);
   MOE_LAUNCH_CHECK();

@@ -321,17 +321,22 @@ def combine_bwd(cfg, dOut, Y, inv_map, w):
     return dY, dw
 
 
-def expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, ws=None):
+_GRAD_DT = {torch.float32: L.MOE_F32, torch.bfloat16: L.MOE_BF16}
+
+
+def expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, ws=None, grad_dtype=torch.float32):
+    """dX_perm [N,d] (act dtype) and the weight gradients dW13, dW2 stored in
+    grad_dtype (float32 or bfloat16; FP32 accumulation either way)."""
     N, d, E, f = cfg.T * cfg.k, cfg.d, cfg.E, cfg.d_ff
     _need(X, "X", _DT[cfg.act], (cfg.T, d))
     _need(dY, "dY", _DT[cfg.act], (N, d))
     dev = X.device
     dXp = torch.empty(N, d, dtype=X.dtype, device=dev)
-    dW13 = torch.empty(E, 2 * f, d, dtype=torch.float32, device=dev)
-    dW2 = torch.empty(E, d, f, dtype=torch.float32, device=dev)
+    dW13 = torch.empty(E, 2 * f, d, dtype=grad_dtype, device=dev)
+    dW2 = torch.empty(E, d, f, dtype=grad_dtype, device=dev)
     ws = _WS.get(cfg, dev) if ws is None else ws
     L.moe_expert_ffn_bwd(cfg, _p(X), _p(row_map), _p(offsets), _p(dY), _p(W13), _p(W2), _p(dXp),
-                         _p(dW13), _p(dW2), _p(ws), ws.numel(), _stream())
+                         _p(dW13), _p(dW2), _GRAD_DT[grad_dtype], _p(ws), ws.numel(), _stream())
     return dXp, dW13, dW2
 
 
@@ -341,14 +346,16 @@ def dispatch_bwd(cfg, dXp, inv_map):
     return dX
 
 
-def route_bwd(cfg, X, Wr, idx, w, dw, row_map, offsets, inv_map, dXp, ws=None):
+def route_bwd(cfg, X, Wr, idx, w, dw, row_map, offsets, inv_map, dXp, ws=None,
+              dx_dtype=torch.float32):
     dev = X.device
-    dX = torch.empty(cfg.T, cfg.d, dtype=torch.float32, device=dev)
+    dX = torch.empty(cfg.T, cfg.d, dtype=dx_dtype, device=dev)
     dWr = torch.empty(cfg.E, cfg.d, dtype=torch.float32, device=dev)
     dbr = torch.empty(cfg.E, dtype=torch.float32, device=dev)
     ws = _WS.get(cfg, dev) if ws is None else ws
     L.moe_route_bwd(cfg, _p(X), _p(Wr), _p(idx), _p(w), _p(dw), _p(row_map), _p(offsets),
-                    _p(inv_map), _p(dXp), _p(dX), _p(dWr), _p(dbr), _p(ws), ws.numel(), _stream())
+                    _p(inv_map), _p(dXp), _p(dX), _GRAD_DT[dx_dtype], _p(dWr), _p(dbr), _p(ws),
+                    ws.numel(), _stream())
     return dX, dWr, dbr
 
 
@@ -372,9 +379,12 @@ class MoEFunction(torch.autograd.Function):
         cfg = ctx.cfg
         dOut = dOut.to(Y.dtype).contiguous()
         dY, dw = combine_bwd(cfg, dOut, Y, inv_map, w)
-        dXp, dW13, dW2 = expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2)
-        dX, dWr, dbr = route_bwd(cfg, X, Wr, idx, w, dw, row_map, offsets, inv_map, dXp)
-        return (dX.to(X.dtype), dWr, dbr, dW13.to(W13.dtype), dW2.to(W2.dtype), None, None)
+        # gradients stored directly in their parameters' dtypes (FP32 sums)
+        dXp, dW13, dW2 = expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2,
+                                        grad_dtype=W13.dtype)
+        dX, dWr, dbr = route_bwd(cfg, X, Wr, idx, w, dw, row_map, offsets, inv_map, dXp,
+                                 dx_dtype=X.dtype)
+        return (dX, dWr, dbr, dW13, dW2, None, None)
 
 
 def moe_layer(cfg, X, Wr, br, W13, W2, check=True):

@@ -80,6 +80,27 @@ def test_backward_pieces_match_oracle(shape, config):
     assert_close(dbr.cpu().numpy(), ref["dbr"], 2e-2, "dbr")
 
 
+@pytest.mark.parametrize("shape,config", [(BWD, 36), (BWD2, 37)])
+def test_backward_bf16_outputs_are_the_rounded_fp32_results(shape, config):
+    """Weight and token gradients stored as BF16 are the FP32 results rounded
+    to nearest even, bit for bit (same accumulation, rounding at the store;
+    the 256-wide weight-gradient tile at d_ff = 256 and the 128-wide one at
+    d_ff = 384)."""
+    cfg, d, h, fw, dOut = _setup(shape, config)
+    dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
+    outs = {}
+    for dt in (torch.float32, torch.bfloat16):
+        dXp, dW13, dW2 = layer.expert_ffn_bwd(cfg, d["X"], fw["row_map"], fw["offsets"], dY,
+                                              d["W13"], d["W2"], grad_dtype=dt)
+        dX, _, _ = layer.route_bwd(cfg, d["X"], d["Wr"], fw["idx"], fw["w"], dw, fw["row_map"],
+                                   fw["offsets"], fw["inv_map"], dXp, dx_dtype=dt)
+        outs[dt] = (dW13, dW2, dX)
+    torch.cuda.synchronize()
+    for name, a, b in zip(("dW13", "dW2", "dX"), outs[torch.float32], outs[torch.bfloat16]):
+        np.testing.assert_array_equal(a.to(torch.bfloat16).view(torch.int16).cpu().numpy(),
+                                      b.view(torch.int16).cpu().numpy(), err_msg=name)
+
+
 def test_dispatch_backward_is_a_gather_sum():
     cfg, d, h, fw, dOut = _setup(BWD, 33)
     dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
