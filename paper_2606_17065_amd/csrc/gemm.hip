@@ -1224,11 +1224,12 @@ MOE_INST_MX(4)
 // ------------------------------------------------------------- backward
 // Recompute-based backward of the expert FFN for the rows of each expert
 // (dY = w * dOut in slot order, supplied by the combine backward):
-//   [A|B] = Xp W13^T               (gemm_bf16_big<EPI_AB, gather>)
-//   U = dY W2  -> h = silu(A) B, dA = U B silu'(A), dB = U silu(A)
-//                                   (gemm_dgrad1, reading [A|B])
-//   dX_perm = [dA|dB] W13          (gemm_bf16_big<EPI_PLAIN> on W13^T)
-//   dW13_e = [dA|dB]^T Xp,  dW2_e = dY^T h          (gemm_wgrad)
+//   [A|B] = Xp W13^T               (gemm_bf16_wide<EPI_AB, gather>)
+//   U = dY W2 (BF16)               (gemm_bf16_wide<EPI_PLAIN> on W2^T)
+//   h = silu(A) B, dA = U B silu'(A), dB = U silu(A)
+//                                   (dgrad_elem, reading U and [A|B])
+//   dX_perm = [dA|dB] W13          (gemm_bf16_wide<EPI_PLAIN> on W13^T)
+//   dW13_e = [dA|dB]^T Xp,  dW2_e = dY^T h          (gemm_wgrad_wide)
 // Every product is "NT" with both operands contiguous along the reduction:
 // the weights are transposed once per call, and the activations that the
 // weight gradients reduce over are written transposed [channel][slot] with
@@ -1246,106 +1247,65 @@ __device__ __forceinline__ void store4(bf16_t* p, float a, float b, float c, flo
 // of PADK (one K stage of the 256 x 256 weight-gradient tile).
 constexpr int PADK = 64;
 
-// One epilogue pass of gemm_dgrad1: PASS 0 = dA, 1 = dB, 2 = h.  Values
-// go to LDS transposed [column][row]; dA and dB also go row-major to dAB.
-template <int PASS>
-__device__ __forceinline__ void dgrad1_pass(const f32x16 (&acc)[4][2], char* lds,
-                                            const bf16_t* __restrict__ AB, bf16_t* __restrict__ dAB,
-                                            bf16_t* __restrict__ dst, int ldT, int row0, int rows,
-                                            int n0, int f, size_t pcol0, int wm, int wn, int tid,
-                                            int lane) {
-  constexpr int TLD = GBM + 8;
-  bf16_t* Ls = (bf16_t*)lds;
-  const int fr = lane & 31, cbase = (lane >> 5) * 4;
+// dA, dB and h from U = dY W2 (BF16) and the recomputed [A|B], one block per
+// 64 slot rows of one expert (tile_start of 64-row tiles) and 64 columns of
+// f: dA and dB are stored row-major into [dA|dB] and, like h, transposed
+// through LDS into the slot-major buffers at the expert's padded slot
+// offset.  silu(a) = a s, s = 1/(1+exp(-a)); dA = U B (s + a s (1 - s)),
+// dB = U a s, h = a s B.
+constexpr int DE_TILE = 64;
+
+__global__ __launch_bounds__(256) void dgrad_elem(
+    const bf16_t* __restrict__ U, const bf16_t* __restrict__ AB, bf16_t* __restrict__ dAB,
+    bf16_t* __restrict__ dABT, bf16_t* __restrict__ hT, int ldT,
+    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile64,
+    const int32_t* __restrict__ ptile, int E, int N, int f) {
+  __shared__ __attribute__((aligned(16))) bf16_t Ls[3][DE_TILE][DE_TILE + 8];
+  int e, row0, rows;
+  if (!find_tile(tile64, offsets, E, DE_TILE, N, blockIdx.x, e, row0, rows)) return;
+  const int n0 = blockIdx.y * DE_TILE, tid = threadIdx.x;
   const size_t ld2f = (size_t)2 * f;
+  for (int it = tid; it < DE_TILE * (DE_TILE / 8); it += 256) {
+    const int r = it >> 3, c8 = (it & 7) * 8;
+    bf16x8 oa, ob, oh;
+    if (r < rows) {
+      const size_t row = (size_t)(row0 + r);
+      const bf16x8 u = *(const bf16x8*)(U + row * f + n0 + c8);
+      const bf16x8 av = *(const bf16x8*)(AB + row * ld2f + n0 + c8);
+      const bf16x8 bv = *(const bf16x8*)(AB + row * ld2f + f + n0 + c8);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int rl = wm * 128 + i * 32 + fr;
-    const size_t row = (size_t)(row0 + min(rl, rows - 1));
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int cl = wn * 64 + j * 32 + g * 8 + cbase;
-        const int n = n0 + cl;
-        const bf16x4 av = *(const bf16x4*)(AB + row * ld2f + n);
-        const bf16x4 bv = *(const bf16x4*)(AB + row * ld2f + f + n);
-        bf16x4 o;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float u = acc[i][j][g * 4 + q];
-          const float a = (float)av[q], bb = (float)bv[q];
-          const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-a));
-          const float sa = a * sg;
-          float v;
-          if (PASS == 0) v = u * bb * (sg + sa * (1.0f - sg));  // dA
-          else if (PASS == 1) v = u * sa;                       // dB
-          else v = sa * bb;                                      // h
-          o[q] = (bf16_t)v;
-          Ls[(cl + q) * TLD + rl] = o[q];
-        }
-        if (PASS < 2 && rl < rows)
-          *(bf16x4*)(dAB + (size_t)(row0 + rl) * ld2f + (PASS == 0 ? 0 : f) + n) = o;
+      for (int q = 0; q < 8; ++q) {
+        const float uu = (float)u[q], a = (float)av[q], bb = (float)bv[q];
+        const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-a));
+        const float sa = a * sg;
+        oa[q] = (bf16_t)(uu * bb * (sg + sa * (1.0f - sg)));
+        ob[q] = (bf16_t)(uu * sa);
+        oh[q] = (bf16_t)(sa * bb);
       }
-      // keep the loads of later groups from being hoisted here (they would
-      // not fit in registers next to the accumulators)
-      asm volatile("" ::: "memory");
+      *(bf16x8*)(dAB + row * ld2f + n0 + c8) = oa;
+      *(bf16x8*)(dAB + row * ld2f + f + n0 + c8) = ob;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) oa[q] = ob[q] = oh[q] = (bf16_t)0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      Ls[0][c8 + q][r] = oa[q];
+      Ls[1][c8 + q][r] = ob[q];
+      Ls[2][c8 + q][r] = oh[q];
     }
   }
   __syncthreads();
-  const size_t rbase = PASS == 1 ? (size_t)f + n0 : (size_t)n0;
-  for (int cidx = tid; cidx < 128 * (GBM / 8); cidx += 256) {
-    const int cl = cidx / (GBM / 8), r8 = (cidx - cl * (GBM / 8)) * 8;
-    if (r8 < rows)
-      *(u32x4*)(dst + (rbase + cl) * ldT + pcol0 + r8) = *(const u32x4*)(Ls + cl * TLD + r8);
-  }
-  __syncthreads();
-}
-
-// U tile = dY rows x 128 columns of f (weight rows of W2^T_e); epilogue
-// computes dA, dB, h and writes dAB row-major plus dAB^T and h^T.
-__global__ __launch_bounds__(256, 1) void gemm_dgrad1(
-    const bf16_t* __restrict__ dY, const bf16_t* __restrict__ W2T, const bf16_t* __restrict__ AB,
-    bf16_t* __restrict__ dAB, bf16_t* __restrict__ dABT, bf16_t* __restrict__ hT, int ldT,
-    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start,
-    const int32_t* __restrict__ ptile, int E, int N, int d, int f, int n_tiles, int grid_total) {
-  __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
-  const int b = blockIdx.x;
-  const int per = grid_total >> 3;
-  const int Lt = (b & 7) * per + (b >> 3);
-  int e, row0, rows, nt;
-  if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
-  const int n0 = nt * 128;
-  const bf16_t* Be = W2T + (size_t)e * f * d;
-  const bf16_t* asrc[A_INS];
-  const bf16_t* bsrc[B_INS];
-#pragma unroll
-  for (int i = 0; i < A_INS; ++i) {
-    const int R = wv * (GBM / 4) + i * 16 + (lane >> 2);
-    const int c = (lane & 3) ^ swz(R);
-    asrc[i] = dY + (size_t)(row0 + min(R, rows - 1)) * d + c * 8;
-  }
-#pragma unroll
-  for (int i = 0; i < B_INS; ++i) {
-    const int R = wv * (GBN / 4) + i * 16 + (lane >> 2);
-    const int c = (lane & 3) ^ swz(R);
-    bsrc[i] = Be + (size_t)(n0 + R) * d + c * 8;
-  }
-  int aoff[4], asw[4], boff[2], bsw[2];
-  frag_offsets(wm, wn * 64, wn * 64 + 32, lane, aoff, asw, boff, bsw);
-  f32x16 acc[4][2];
-  zero_acc(acc);
-  mma_pipeline<A_INS, B_INS>(lds, asrc, bsrc, d / GBK, wv, lane, aoff, asw, boff, bsw, acc);
-  WAIT_VM_LGKM0(0);
-  stage_barrier();
-
-  // three passes through LDS (dA, dB, h), each staged transposed [col][row]
   const size_t pcol0 = (size_t)ptile[e] * PADK + (size_t)(row0 - offsets[e]);
-  dgrad1_pass<0>(acc, lds, AB, dAB, dABT, ldT, row0, rows, n0, f, pcol0, wm, wn, tid, lane);
-  dgrad1_pass<1>(acc, lds, AB, dAB, dABT, ldT, row0, rows, n0, f, pcol0, wm, wn, tid, lane);
-  dgrad1_pass<2>(acc, lds, AB, dAB, hT, ldT, row0, rows, n0, f, pcol0, wm, wn, tid, lane);
+  for (int it = tid; it < 3 * DE_TILE * (DE_TILE / 8); it += 256) {
+    const int q = it / (DE_TILE * (DE_TILE / 8));
+    const int rem = it - q * DE_TILE * (DE_TILE / 8);
+    const int c = rem >> 3, r8 = (rem & 7) * 8;
+    if (r8 >= rows) continue;
+    bf16_t* dst = q == 2 ? hT + (size_t)(n0 + c) * ldT
+                         : dABT + ((size_t)(q == 1 ? f : 0) + n0 + c) * ldT;
+    *(u32x4*)(dst + pcol0 + r8) = *(const u32x4*)&Ls[q][c][r8];
+  }
 }
 
 // Weight gradient of one expert: out_e[m][n] = sum over the expert's padded
@@ -1876,7 +1836,8 @@ namespace moe_gemm {
 struct FfnBwdWs {
   int32_t* tile_start;
   int32_t* ptile;
-  bf16_t *W13T, *W2T, *AB, *dAB, *dABT, *hT, *XpT, *dYT;
+  int32_t* tile64;  // schedule of 64-row tiles (the dA/dB/h pass)
+  bf16_t *W13T, *W2T, *AB, *U, *dAB, *dABT, *hT, *XpT, *dYT;
   int ldT;
 };
 
@@ -1894,9 +1855,11 @@ FfnBwdWs carve_ffn_bwd(const moe_cfg& c, void* base, size_t* total) {
   r.ldT = bwd_ldT(c);
   r.tile_start = wc.take<int32_t>(E + 1);
   r.ptile = wc.take<int32_t>(E + 1);
+  r.tile64 = wc.take<int32_t>(E + 1);
   r.W13T = wc.take<bf16_t>(E * 2 * f * d);
   r.W2T = wc.take<bf16_t>(E * f * d);
   r.AB = wc.take<bf16_t>(N * 2 * f);
+  r.U = wc.take<bf16_t>(N * f);
   r.dAB = wc.take<bf16_t>(N * 2 * f);
   r.dABT = wc.take<bf16_t>(2 * f * r.ldT);
   r.hT = wc.take<bf16_t>(f * r.ldT);
@@ -1941,6 +1904,7 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
   PROF_BEGIN("ffn_bwd", st);
   hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, GBM, w.tile_start);
   hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, PADK, w.ptile);
+  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, DE_TILE, w.tile64);
   hipLaunchKernelGGL(batched_transpose, dim3(d / 64, 2 * f / 64, E), dim3(256), 0, st,
                      (const bf16_t*)W13, w.W13T, 2 * f, d);
   hipLaunchKernelGGL(batched_transpose, dim3(f / 64, d / 64, E), dim3(256), 0, st,
@@ -1953,10 +1917,21 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
                          st, Xb, row_map, c.T, (const bf16_t*)W13, w.AB, offsets, w.tile_start, E,
                          N, d, f, 2 * f, nt, G);
     }
-    {  // U = dY W2, then dA, dB, h
-      const int nt = f / 128, G = (mt * nt + 7) / 8 * 8;
-      hipLaunchKernelGGL(gemm_dgrad1, dim3(G), dim3(256), 0, st, dYb, w.W2T, w.AB, w.dAB, w.dABT,
-                         w.hT, w.ldT, offsets, w.tile_start, w.ptile, E, N, d, f, nt, G);
+    {  // U = dY W2 (BF16, 256 columns of f per tile when f allows), then dA, dB, h
+      if (f % XBN == 0) {
+        const int nt = f / XBN, G = (mt * nt + 7) / 8 * 8;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G),
+                           dim3(64 * XW), 0, st, dYb, nullptr, 0, w.W2T, w.U, offsets,
+                           w.tile_start, E, N, d, d, f, nt, G);
+      } else {
+        const int nt = f / GBN, G = (mt * nt + 7) / 8 * 8;
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_PLAIN, false>), dim3(G), dim3(256),
+                           0, st, dYb, nullptr, 0, w.W2T, w.U, offsets, w.tile_start, E, N, d, d,
+                           f, nt, G);
+      }
+      const int m64 = (N + DE_TILE - 1) / DE_TILE + E;
+      hipLaunchKernelGGL(dgrad_elem, dim3(m64, f / DE_TILE), dim3(256), 0, st, w.U, w.AB, w.dAB,
+                         w.dABT, w.hT, w.ldT, offsets, w.tile64, w.ptile, E, N, f);
     }
     {  // dX_perm = [dA|dB] W13 (d % 256 == 0: the 256 x 256 tile)
       const int nt = d / 256, G = (mt * nt + 7) / 8 * 8;
