@@ -17,9 +17,10 @@ routing of fresh batches and the judge's verdict on learned prices alone);
 the per-stage kernel times (HIP events on the launch stream), the roofline
 of the dominant kernel, and the CPU oracle on the same forward batch.
 
-Prints ONE JSON line.  `--profile-only fwd|copy|fp8` runs a few steps
-without output for hardware-counter runs (copy = a plain device copy of
-1 GiB used to calibrate the byte counters).
+Prints ONE JSON line.  `--profile-only fwd|copy|copylds|fp8` runs a few
+steps without output for hardware-counter runs (copy = a plain device copy
+of 1 GiB, copylds = the same bytes read by direct-to-LDS loads, both used to
+calibrate the byte counters).
 """
 from __future__ import annotations
 
@@ -59,7 +60,7 @@ def parse():
     ap.add_argument("--price-batches", type=int, default=10000,
                     help="training batches of the price network (0 = skip that part)")
     ap.add_argument("--price-steps", type=int, default=4000)
-    ap.add_argument("--profile-only", choices=["fwd", "copy", "fp8"], default=None)
+    ap.add_argument("--profile-only", choices=["fwd", "copy", "copylds", "fp8"], default=None)
     return ap.parse_args()
 
 
@@ -138,6 +139,17 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print("copied 1 GiB x3")
+        return
+
+    if args.profile_only == "copylds":
+        a = torch.empty(1 << 29, dtype=torch.int16, device=dev).fill_(1)  # 1 GiB
+        b = torch.empty_like(a)
+        stream = torch.cuda.current_stream().cuda_stream
+        for _ in range(3):
+            L.moe_prof_lds_copy(a.data_ptr(), b.data_ptr(), a.numel() * 2, stream)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        print("copied 1 GiB x3 through LDS")
         return
 
     if args.profile_only == "fp8":

@@ -556,6 +556,15 @@ moe_status moe_prof_reset(void);
 moe_status moe_prof_get(const char* kernel /* host */, double* total_ms /* host out */,
                         int32_t* launches /* host out */);
 
+/*
+ * moe_prof_lds_copy -- calibration copy for hardware byte counters: dst =
+ *   src (bytes % 16 == 0, both 16-byte aligned, device pointers), every
+ *   16-byte piece read from memory straight into LDS by the direct-to-LDS
+ *   load the expert products use for their operands, then written out by
+ *   ordinary vector stores.  Not on any layer path.
+ */
+moe_status moe_prof_lds_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Status text (host, static storage). */
 const char* moe_strerror(int status);
 

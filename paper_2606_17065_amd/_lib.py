@@ -84,6 +84,7 @@ SIGNATURES = {
                       ctypes.c_float, ctypes.c_float, ctypes.c_int, _P],
     "moe_prof_enable": [ctypes.c_int],
     "moe_prof_reset": [],
+    "moe_prof_lds_copy": [_P, _P, _S, _P],
     "moe_prof_get": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)],
 }
 
@@ -280,6 +281,10 @@ def moe_adam_step(n, params, grads, m, v, lr, beta1, beta2, eps, step, stream):
 
 def moe_prof_enable(on: bool) -> None:
     _check(lib().moe_prof_enable(1 if on else 0), "moe_prof_enable")
+
+
+def moe_prof_lds_copy(src, dst, nbytes, stream) -> None:
+    _check(lib().moe_prof_lds_copy(src, dst, nbytes, stream), "moe_prof_lds_copy")
 
 
 def moe_prof_reset() -> None:

@@ -2160,3 +2160,38 @@ extern "C" moe_status moe_expert_ffn_mx(const moe_cfg* cfg, const uint8_t* X_cod
   MOE_LAUNCH_CHECK();
   return MOE_OK;
 }
+
+// ---------------------------------------------------- counter calibration
+namespace {
+__global__ __launch_bounds__(256) void lds_copy_kernel(const u32x4* __restrict__ src,
+                                                       u32x4* __restrict__ dst, size_t n16) {
+  typedef __attribute__((address_space(3))) void lds_void;
+  __shared__ __attribute__((aligned(1024))) u32x4 buf[256];
+  const int tid = threadIdx.x, wv = tid >> 6;
+  for (size_t off = (size_t)blockIdx.x * 256; off < n16; off += (size_t)gridDim.x * 256) {
+    if (off + 256 <= n16) {
+      // each wavefront deposits its 64 x 16 bytes contiguously
+      __builtin_amdgcn_global_load_lds(src + off + tid, (lds_void*)(buf + wv * 64), 16, 0, 0);
+      WAIT_VM_LGKM0(0);
+      __syncthreads();
+      dst[off + tid] = buf[tid];
+      __syncthreads();
+    } else if (off + tid < n16) {
+      dst[off + tid] = src[off + tid];
+    }
+  }
+}
+}  // namespace
+
+extern "C" moe_status moe_prof_lds_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (bytes % 16 != 0 || !aligned(src, 16) || !aligned(dst, 16)) return MOE_EINVAL;
+  if (bytes == 0) return MOE_OK;
+  if (!src || !dst) return MOE_EINVAL;
+  const size_t n16 = bytes / 16;
+  const size_t blocks = (n16 + 255) / 256;
+  const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
+  hipLaunchKernelGGL(lds_copy_kernel, dim3(g), dim3(256), 0, (hipStream_t)stream,
+                     (const u32x4*)src, (u32x4*)dst, n16);
+  MOE_LAUNCH_CHECK();
+  return MOE_OK;
+}
