@@ -336,3 +336,52 @@ def test_feature_loads_follow_the_ranking_rule_on_ties():
             load[e] += 1
     np.testing.assert_array_equal(np.rint(Fm[:, 4] * C).astype(np.int64), load)
     np.testing.assert_array_equal(load, R.acp_prices(s, k, C, max_iters=0)["load"])
+
+
+@pytest.mark.slow
+def test_backward_matches_central_differences_on_a_c4_slice():
+    """The oracle's gradient against central differences on a 64-token slice
+    of the forward+backward workload (d=2048, E=128, top-8, d_ff=1024,
+    Zipf 1.3, upstream N(0,1)): the slice is routed by the workload's router
+    (capacity for 64 tokens), and only the experts it uses take part, so the
+    router rows, biases and expert weights are restricted to those experts
+    (an unused expert's logit never enters the softmax over the chosen
+    ones).  Expert weights N(0, 0.02^2) from a seeded generator; h = 1e-6
+    max(1, |theta|); agreement <= 1e-6 relative."""
+    from paper_2606_17065_amd import synth
+    shape = synth.SHAPES[4]
+    inp = synth.make_inputs(shape, 4, experts=False)
+    T, k, E = 64, shape.k, shape.E
+    X = inp["X"][:T].astype(np.float64)
+    Wr = inp["Wr"].astype(np.float64)
+    br = inp["br"].astype(np.float64)
+    s = R.logits_fp64(X, Wr, br).astype(F32)
+    r = R.route(s, k, synth.capacity(T, k, E), 50)
+    assert r["status"] == R.OK
+    used = np.unique(r["sel"])
+    remap = np.full(E, -1)
+    remap[used] = np.arange(used.shape[0])
+    sel = remap[r["sel"]].astype(np.int32)
+    rng = np.random.default_rng(4064)
+    U, d, f = used.shape[0], shape.d, shape.f
+    W13 = 0.02 * rng.standard_normal((U, 2 * f, d))
+    W2 = 0.02 * rng.standard_normal((U, d, f))
+    Wr_u, br_u = Wr[used].copy(), br[used].copy()
+    dOut = synth.make_upstream(T, d, 4).astype(np.float64)
+    g = grad.layer_backward(X, Wr_u, br_u, W13, W2, sel, dOut)
+    params = dict(X=X, Wr=Wr_u, br=br_u, W13=W13, W2=W2)
+    names = dict(X="dX", Wr="dWr", br="dbr", W13="dW13", W2="dW2")
+    for name, arr in params.items():
+        flat = arr.reshape(-1)
+        # every compacted expert holds slots, so any coordinate is live
+        for i in rng.choice(flat.shape[0], size=3, replace=False):
+            h = 1e-6 * max(1.0, abs(flat[i]))
+            old = flat[i]
+            flat[i] = old + h
+            lp = grad.layer_loss(X, Wr_u, br_u, W13, W2, sel, dOut)
+            flat[i] = old - h
+            lm = grad.layer_loss(X, Wr_u, br_u, W13, W2, sel, dOut)
+            flat[i] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[names[name]].reshape(-1)[i]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (name, i, fd, an)
