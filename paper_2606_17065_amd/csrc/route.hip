@@ -350,14 +350,63 @@ __device__ __forceinline__ uint64_t pick(const uint64_t (&v)[L], int j) {
 
 __device__ __forceinline__ int key_expert(uint64_t v) { return (int)(0xFFFFFFFFu - (uint32_t)v); }
 
+// The N composite keys sorted in descending order (bitonic network, N a
+// power of two): the same list insert_top builds from them, with fewer
+// compare-exchanges.
+template <int N>
+__device__ __forceinline__ void sort_desc(uint64_t (&v)[N]) {
+#pragma unroll
+  for (int kk = 2; kk <= N; kk <<= 1) {
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint64_t a = v[i], b = v[l];
+          const bool sw = (i & kk) == 0 ? a < b : a > b;
+          v[i] = sw ? b : a;
+          v[l] = sw ? a : b;
+        }
+      }
+    }
+  }
+}
+
+// Value of lane (lane ^ 1), (lane ^ 2) or of the mirrored lane in its half
+// row of eight (lane ^ 7) for the quad_perm / row_half_mirror DPP controls.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)x, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), CTRL, 0xF, 0xF, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
+// Maximum over each group of G (4 or 8) consecutive lanes, in every lane of
+// the group.  The whole wavefront must be active.
+template <int G>
+__device__ __forceinline__ uint64_t group_max(uint64_t x) {
+  uint64_t y = dpp64<0xB1>(x);  // quad_perm [1,0,3,2]
+  x = x > y ? x : y;
+  y = dpp64<0x4E>(x);  // quad_perm [2,3,0,1]
+  x = x > y ? x : y;
+  if (G == 8) {
+    y = dpp64<0x141>(x);  // row_half_mirror
+    x = x > y ? x : y;
+  }
+  return x;
+}
+
 // One ranking pass of the price loop.  A block owns TG groups of 64 tokens
 // (one token per lane) and splits the experts into RW contiguous ranges,
 // one wavefront per (token group, range); each wavefront keeps its logits
-// in registers and builds a partial top-L list per token.  One wavefront
-// per token group merges the RW sorted lists (k+1 steps) and writes the
-// routing for the current prices; then every wavefront writes the margin
-// keys mT[e][t] of its experts.  The block's per-expert counts go to row
-// blockIdx.x of cnt[nblk][E] (no global atomics).
+// in registers and builds a partial top-L list per token.  The RW sorted
+// lists of a token are then merged by RW lanes of one wavefront (one list
+// per lane, k+1 rounds of a DPP maximum over the group; every wavefront
+// merges 64/RW tokens) and the routing for the current prices is written;
+// then every wavefront writes the margin keys mT[e][t] of its experts.  The
+// block's per-expert counts go to row blockIdx.x of cnt[nblk][E] (no global
+// atomics).
 
 // Token group of sub-group tg: gbase + tg * gstride (64 tokens each);
 // the block's per-expert counts go to row crow of cnt.  With a state
@@ -371,8 +420,9 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
                                           int crow) {
   __shared__ int hist[MOE_MAX_E];
   __shared__ float ps[MOE_MAX_E];
-  __shared__ uint32_t partk[TG][RW][L][64];
-  __shared__ int parte[TG][RW][L][64];
+  // partial lists, one padding entry per row against bank conflicts of
+  // the merge's reads (RW lists of one token in one read)
+  __shared__ uint64_t partv[TG][RW][L][65];
   __shared__ uint32_t kthk_s[TG][64];
   __shared__ int kthe_s[TG][64];
   __shared__ float k1_s[TG][64], k2_s[TG][64];
@@ -396,18 +446,28 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
       sv[i] = sT[(size_t)min(e_lo + min(i, max(ne - 1, 0)), E - 1) * T + tl];
   }
   const int done = state ? state[ST_DONE] : 0;
-  if (done) return;  // uniform: every thread read the same flag
   for (int e = tid; e < E; e += NT) {
     hist[e] = 0;
     ps[e] = price[e];
   }
+  if (done) return;  // uniform: every thread read the same flag
   __syncthreads();
   // the top-L list of this wavefront's experts as composite rank keys
   // (key, then lower expert first): one 64-bit comparison per step
   uint64_t V[L];
 #pragma unroll
   for (int j = 0; j < L; ++j) V[j] = 0ull;
-  if (cached) {
+  if (cached && NV <= L) {
+    uint64_t W[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const uint32_t key = i < ne ? f32_key(sv[i] - ps[min(e_lo + i, E - 1)]) : 0u;
+      W[i] = ((uint64_t)key << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)(e_lo + i));
+    }
+    sort_desc<NV>(W);
+#pragma unroll
+    for (int j = 0; j < L; ++j) V[j] = j < NV ? W[j < NV ? j : 0] : 0ull;
+  } else if (cached) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const uint32_t key = i < ne ? f32_key(sv[i] - ps[min(e_lo + i, E - 1)]) : 0u;
@@ -426,48 +486,39 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
     }
   }
 #pragma unroll
-  for (int j = 0; j < L; ++j) {
-    partk[tg][wv][j][lane] = (uint32_t)(V[j] >> 32);
-    parte[tg][wv][j][lane] = key_expert(V[j]);
-  }
+  for (int j = 0; j < L; ++j) partv[tg][wv][j][lane] = V[j];
   __syncthreads();
-  if (wv == 0 && valid) {
-    // merge the RW sorted lists (k+1 steps); on equal keys the list of
-    // the lower expert range wins
-    int h[RW];
+  {
+    // lane: list src of token tm; the k+1 best keys of the token's RW lists
+    // in order (the keys are distinct: equal scores order by expert)
+    constexpr int TPW = 64 / RW;
+    const int src = lane % RW, tm = wv * TPW + lane / RW;
+    const int tt = (gbase + tg * gstride) * 64 + tm;
+    uint64_t Q[L];
 #pragma unroll
-    for (int w = 0; w < RW; ++w) h[w] = 0;
-    uint32_t kk1 = 0, kk2 = 0;
-    int ek1 = 0;
+    for (int j = 0; j < L; ++j) Q[j] = partv[tg][src][j][tm];
+    uint64_t k1v = 0ull, k2v = 0ull;
     for (int j = 0; j <= k && j < L; ++j) {
-      uint32_t m = 0u;
-      int src = 0, hs = 0;
+      const uint64_t m = group_max<RW>(Q[0]);
+      const bool win = Q[0] == m;
 #pragma unroll
-      for (int w = 0; w < RW; ++w) {
-        const uint32_t c = h[w] < L ? partk[tg][w][h[w]][lane] : 0u;
-        if (w == 0 || c > m) {
-          m = c;
-          src = w;
-          hs = h[w];
-        }
-      }
-      const int ej = parte[tg][src][hs][lane];
-#pragma unroll
-      for (int w = 0; w < RW; ++w) h[w] += (w == src) ? 1 : 0;
-      if (j < k) {
-        idx[(size_t)t * k + j] = ej;
+      for (int i = 0; i + 1 < L; ++i) Q[i] = win ? Q[i + 1] : Q[i];
+      Q[L - 1] = win ? 0ull : Q[L - 1];
+      if (j < k && src == j % RW && tt < T) {
+        const int ej = key_expert(m);
+        idx[(size_t)tt * k + j] = ej;
         atomicAdd(&hist[ej], 1);
       }
-      if (j == k - 1) {
-        kk1 = m;
-        ek1 = ej;
-      }
-      if (j == k) kk2 = m;
+      if (j == k - 1) k1v = m;
+      if (j == k) k2v = m;
     }
-    kthk_s[tg][lane] = kk1;
-    kthe_s[tg][lane] = ek1;
-    k1_s[tg][lane] = key_f32(kk1);
-    k2_s[tg][lane] = (k < E) ? key_f32(kk2) : -INFINITY;
+    if (src == 0) {
+      const uint32_t kk1 = (uint32_t)(k1v >> 32);
+      kthk_s[tg][tm] = kk1;
+      kthe_s[tg][tm] = key_expert(k1v);
+      k1_s[tg][tm] = key_f32(kk1);
+      k2_s[tg][tm] = (k < E) ? key_f32((uint32_t)(k2v >> 32)) : -INFINITY;
+    }
   }
   __syncthreads();
   // margins m = s - (held ? kappa2 : kappa1), stored as sortable keys;
@@ -640,71 +691,87 @@ __device__ int block_excl_scan(int flag, int* red, int* total) {
 }
 
 // --------------------------------------------------------- price update
-// One block per expert.  All blocks first agree, from the loads of this
-// iteration, whether the loop ends here; block 0 then records the outcome.
-// An overloaded expert finds the (C+1)-th largest margin key by a 3-pass
-// radix selection (11, 11, 10 bits) whose keys stay in registers when T is
-// at most SEL_THREADS * SEL_KPT.  Only keys at or above a floor a little
-// below the expert's current price enter the histograms (the tokens that
-// do not hold the expert have margins below its price); if fewer than C+1
-// keys pass the floor, the selection restarts with no floor, so the result
-// is always the exact order statistic over all T margins.
+// One block per expert.  Every wavefront first finds, from the loads of
+// this iteration, whether the loop ends here; block 0 then records the
+// outcome.  An overloaded expert finds the (C+1)-th largest margin key by a
+// 3-pass radix selection (11, 11, 10 bits) whose keys stay in registers
+// when T is at most SEL_THREADS * SEL_KPT.  Only keys at or above a floor a
+// little below the expert's current price enter the histograms (the tokens
+// that do not hold the expert have margins below its price); if fewer than
+// C+1 keys pass the floor, the selection restarts with no floor, so the
+// result is always the exact order statistic over all T margins.
 constexpr int SEL_KPT = 16;
 
-// Digit holding the rr-th largest key of a 2048-bin histogram, found by the
-// 1024 threads of the block (two bins each) with a block suffix scan.
-// Writes the digit (or -1 if fewer than rr keys were counted) and the count
-// of keys in higher digits.
-__device__ void block_pick_digit(const uint32_t* hist, int rr, int* red, int* pick_digit,
-                                 uint32_t* pick_above) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const uint32_t lo = hist[2 * tid], hi = hist[2 * tid + 1];
-  const uint32_t loc = lo + hi;
-  uint32_t suf = loc;
+struct alignas(16) SelShared {
+  uint32_t hist[2][2048];  // passes alternate: one fills while the other is cleared
+  int pick_digit;
+  uint32_t pick_above;
+};
+
+// Digit holding the rr-th largest key of a 2048-bin histogram, found by one
+// wavefront: lane l sums bins [32 l, 32 l + 32) (eight 16-byte reads in a
+// rotated order against bank conflicts), a suffix scan over the lanes finds
+// the owning lane, and 32 lanes scan that lane's bins from the top.  Writes
+// the digit (or -1 if fewer than rr keys were counted) and the count of
+// keys in higher digits; the caller synchronises.
+__device__ void wave_pick_digit(const uint32_t* hist, int rr, SelShared& sh) {
+  const int l = threadIdx.x & 63;
+  const uint4* h4 = (const uint4*)hist + l * 8;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const uint4 v = h4[(c + l) & 7];
+    sum += v.x + v.y + v.z + v.w;
+  }
+  uint32_t suf = sum;
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t o = __shfl_down(suf, off, 64);
-    if (lane + off < 64) suf += o;
+    if (l + off < 64) suf += o;
   }
-  if (lane == 0) red[wv] = (int)suf;
-  if (tid == 0) *pick_digit = -1;
-  __syncthreads();
-  uint32_t after = 0;
-  for (int w = wv + 1; w < SEL_THREADS / 64; ++w) after += (uint32_t)red[w];
-  const uint32_t S = suf + after;
-  const uint32_t above = S - loc;
-  if (above < (uint32_t)rr && (uint32_t)rr <= S) {
-    if (above + hi >= (uint32_t)rr) {
-      *pick_digit = 2 * tid + 1;
-      *pick_above = above;
-    } else {
-      *pick_digit = 2 * tid;
-      *pick_above = above + hi;
-    }
+  const uint32_t above = suf - sum;
+  const uint64_t own = __ballot(above < (uint32_t)rr && (uint32_t)rr <= suf);
+  if (own == 0ull) {
+    if (l == 0) sh.pick_digit = -1;
+    return;
   }
-  __syncthreads();
+  const int ow = __ffsll((unsigned long long)own) - 1;
+  const uint32_t base = __shfl(above, ow, 64);
+  // lanes 0..31 take the owner's bins from the highest down; inclusive
+  // prefix sums over them
+  const uint32_t h = l < 32 ? hist[ow * 32 + 31 - l] : 0u;
+  uint32_t pre = h;
+  for (int off = 1; off < 32; off <<= 1) {
+    const uint32_t o = __shfl_up(pre, off, 64);
+    if (l >= off) pre += o;
+  }
+  const uint64_t hit = __ballot(l < 32 && base + pre >= (uint32_t)rr);
+  const int fl = __ffsll((unsigned long long)hit) - 1;
+  if (l == fl) {
+    sh.pick_digit = ow * 32 + 31 - l;
+    sh.pick_above = base + pre - h;
+  }
 }
 
 // The price update of one overloaded expert e (all SEL_THREADS threads):
-// q = (C+1)-th largest margin key of the column by a three-pass 11/11/10-bit
-// radix select over the keys at or above a floor just below the current
-// price (restarting over all keys if fewer than C+1 lie above it), then
+// q = (C+1)-th largest margin key of the column, then
 // p_e = max(p_e, nextafter(q, +inf) + eps).  kk holds the column when
-// cached (T <= SEL_THREADS * SEL_KPT).
+// cached (T <= SEL_THREADS * SEL_KPT); both histograms are zero on entry.
 __device__ __forceinline__ void select_update(const uint32_t* __restrict__ col,
                                               uint32_t (&kk)[SEL_KPT], bool cached, int T,
-                                              int C, int e, float* __restrict__ price,
-                                              float eps, SelScratch& sc, int* red) {
+                                              int C, int e, float p_e, float* __restrict__ price,
+                                              float eps, SelShared& sh) {
   const int tid = threadIdx.x;
-  const uint32_t pkey = f32_key(price[e]);
+  const uint32_t pkey = f32_key(p_e);
   uint32_t floor_key = pkey > 4096u ? pkey - 4096u : 0u;
   uint32_t prefix = 0, mask = 0;
   int rr = C + 1;
 #pragma unroll 1
   for (int pass = 0; pass < 3; ++pass) {
-    const int sh = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+    const int sft = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
     const uint32_t dm = pass == 2 ? 1023u : 2047u;
-    for (int i = tid; i < 2048; i += SEL_THREADS) sc.hist[i] = 0;
-    __syncthreads();
+    uint32_t* H = sh.hist[pass & 1];
+    if (pass == 1)  // for the third pass; the first pass's pick is done
+      for (int i = tid; i < 2048; i += SEL_THREADS) sh.hist[0][i] = 0;
     for (int c0 = 0; c0 < T; c0 += SEL_THREADS * SEL_KPT) {
       if (!cached) {
 #pragma unroll
@@ -716,31 +783,36 @@ __device__ __forceinline__ void select_update(const uint32_t* __restrict__ col,
 #pragma unroll
       for (int i = 0; i < SEL_KPT; ++i) {
         if ((c0 + i * SEL_THREADS + tid < T) && kk[i] >= floor_key && ((kk[i] & mask) == prefix))
-          atomicAdd(&sc.hist[(kk[i] >> sh) & dm], 1u);
+          atomicAdd(&H[(kk[i] >> sft) & dm], 1u);
       }
     }
     __syncthreads();
-    block_pick_digit(sc.hist, rr, red, &sc.pick_digit, &sc.pick_above);
-    const int dsel = sc.pick_digit;
-    const uint32_t above = sc.pick_above;
+    if (tid < 64) wave_pick_digit(H, rr, sh);
     __syncthreads();
+    const int dsel = sh.pick_digit;
+    const uint32_t above = sh.pick_above;
     if (dsel < 0) {
-      // fewer than C+1 keys above the floor: restart over all keys (a
-      // second miss cannot happen while load_e > C; leave the price as is)
+      // fewer than C+1 keys above the floor: restart over all keys with
+      // cleared histograms (a second miss cannot happen while load_e > C;
+      // leave the price as is)
       if (floor_key == 0u) return;
       floor_key = 0u;
+      prefix = 0u;
+      mask = 0u;
+      rr = C + 1;
+      for (int i = tid; i < 2 * 2048; i += SEL_THREADS) (&sh.hist[0][0])[i] = 0;
+      __syncthreads();
       pass = -1;
       continue;
     }
     rr -= (int)above;
-    prefix |= (uint32_t)dsel << sh;
-    mask |= dm << sh;
+    prefix |= (uint32_t)dsel << sft;
+    mask |= dm << sft;
   }
   if (tid == 0) {
     const float qf = key_f32(prefix);
-    const float cand = nextafterf(qf, INFINITY) + eps;
-    const float old = price[e];
-    price[e] = cand > old ? cand : old;
+    const float cnd = nextafterf(qf, INFINITY) + eps;
+    price[e] = cnd > p_e ? cnd : p_e;
   }
 }
 
@@ -748,17 +820,21 @@ __global__ __launch_bounds__(SEL_THREADS) void acp_select(
     const uint32_t* __restrict__ mT, float* __restrict__ price, int T, int E, int C, int it,
     int max_iters, int nblk, const int32_t* __restrict__ cnt, int32_t* __restrict__ state,
     int32_t* __restrict__ load_out) {
-  __shared__ SelScratch sc;
-  __shared__ int red[32];
+  __shared__ SelShared sh;
   __shared__ int ld[MOE_MAX_E];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int done = state[ST_DONE];
   for (int e = tid; e < E; e += SEL_THREADS) ld[e] = 0;
+  for (int i = tid; i < 2 * 2048; i += SEL_THREADS) (&sh.hist[0][0])[i] = 0;
   if (done) return;  // uniform
   // this block's margin column, requested before the load count is known
   // (the latencies overlap; blocks of experts within capacity discard it)
   const uint32_t* col = mT + (size_t)blockIdx.x * T;
   const bool cached = T <= SEL_THREADS * SEL_KPT;
+  // the price and increment of this block's expert (only this block
+  // writes the price, at its end)
+  const float p_e = price[blockIdx.x];
+  const float eps = __int_as_float(state[ST_EPS]);
   uint32_t kk[SEL_KPT];
   if (cached) {
 #pragma unroll
@@ -769,7 +845,7 @@ __global__ __launch_bounds__(SEL_THREADS) void acp_select(
   }
   __syncthreads();
   // loads of this iteration: column sums of the per-block count matrix,
-  // eight independent loads in flight per thread
+  // sixteen independent loads in flight per thread
   {
     const int lanes_per_e = max(1, SEL_THREADS / E);
     for (int e0 = 0; e0 < E; e0 += SEL_THREADS) {
@@ -778,12 +854,12 @@ __global__ __launch_bounds__(SEL_THREADS) void acp_select(
       if (e < E && r0 < lanes_per_e) {
         int sum = 0;
         int r = r0;
-        for (; r + 7 * lanes_per_e < nblk; r += 8 * lanes_per_e) {
-          int v[8];
+        for (; r + 15 * lanes_per_e < nblk; r += 16 * lanes_per_e) {
+          int v[16];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) v[u] = cnt[(size_t)(r + u * lanes_per_e) * E + e];
+          for (int u = 0; u < 16; ++u) v[u] = cnt[(size_t)(r + u * lanes_per_e) * E + e];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) sum += v[u];
+          for (int u = 0; u < 16; ++u) sum += v[u];
         }
         for (; r < nblk; r += lanes_per_e) sum += cnt[(size_t)r * E + e];
         atomicAdd(&ld[e], sum);
@@ -791,32 +867,31 @@ __global__ __launch_bounds__(SEL_THREADS) void acp_select(
     }
   }
   __syncthreads();
-  int over = 0, excess = 0;
-  for (int e = tid; e < E; e += SEL_THREADS) {
-    int x = ld[e] - C;
-    if (x > 0) {
-      over = 1;
-      excess += x;
-    }
-  }
-  const int n_over = block_sum(over, red);
+  // every wavefront tests the loads itself (no block reduction)
+  int ov = 0;
+  for (int e2 = lane; e2 < E; e2 += 64) ov |= ld[e2] > C ? 1 : 0;
+  const bool any_over = __ballot(ov) != 0ull;
   const int e = blockIdx.x;
-  if (n_over == 0 || it >= max_iters) {
+  if (!any_over || it >= max_iters) {
     if (e == 0) {
-      const int tot_excess = block_sum(excess, red);
       for (int i = tid; i < E; i += SEL_THREADS) load_out[i] = ld[i];
-      if (tid == 0) {
-        state[ST_ITERS] = it;
-        state[ST_CONVERGED] = n_over == 0;
-        state[ST_OVERFLOW] = tot_excess;
-        state[ST_NEED_REPAIR] = n_over != 0;
-        state[ST_DONE] = 1;
+      if (tid < 64) {
+        int ex = 0;
+        for (int e2 = lane; e2 < E; e2 += 64) ex += max(ld[e2] - C, 0);
+        for (int off = 32; off >= 1; off >>= 1) ex += __shfl_down(ex, off, 64);
+        if (tid == 0) {
+          state[ST_ITERS] = it;
+          state[ST_CONVERGED] = !any_over;
+          state[ST_OVERFLOW] = ex;
+          state[ST_NEED_REPAIR] = any_over;
+          state[ST_DONE] = 1;
+        }
       }
     }
     return;
   }
   if (ld[e] <= C) return;
-  select_update(col, kk, cached, T, C, e, price, __int_as_float(state[ST_EPS]), sc, red);
+  select_update(col, kk, cached, T, C, e, p_e, price, eps, sh);
 }
 
 // --------------------------------------------- epsilon-scaled restarts
