@@ -506,7 +506,7 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
       Q[L - 1] = win ? 0ull : Q[L - 1];
       if (j < k && src == j % RW && tt < T) {
         const int ej = key_expert(m);
-        idx[(size_t)tt * k + j] = ej;
+        __builtin_nontemporal_store(ej, &idx[(size_t)tt * k + j]);
         atomicAdd(&hist[ej], 1);
       }
       if (j == k - 1) k1v = m;
@@ -521,7 +521,10 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
     }
   }
   __syncthreads();
-  // margins m = s - (held ? kappa2 : kappa1), stored as sortable keys;
+  // margins m = s - (held ? kappa2 : kappa1), stored as sortable keys
+  // (non-temporal stores, like the routing above: both are rewritten every
+  // update and read by the next kernel from memory, so they are kept out
+  // of the L2 write-back at the kernel boundary);
   // e is held iff (key(a_te), -e) >= (key of rank k, -its expert)
   if (valid) {
     const uint32_t kk1 = kthk_s[tg][lane];
@@ -534,7 +537,7 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
           const int e = e_lo + i;
           const uint32_t key = f32_key(sv[i] - ps[e]);
           const bool held = key > kk1 || (key == kk1 && e <= ek1);
-          mT[(size_t)e * T + t] = f32_key(sv[i] - (held ? kap2 : kap1));
+          __builtin_nontemporal_store(f32_key(sv[i] - (held ? kap2 : kap1)), &mT[(size_t)e * T + t]);
         }
       }
     } else {
@@ -543,7 +546,7 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
         const float s = sT[(size_t)e * T + t];
         const uint32_t key = f32_key(s - ps[e]);
         const bool held = key > kk1 || (key == kk1 && e <= ek1);
-        mT[(size_t)e * T + t] = f32_key(s - (held ? kap2 : kap1));
+        __builtin_nontemporal_store(f32_key(s - (held ? kap2 : kap1)), &mT[(size_t)e * T + t]);
       }
     }
   }
