@@ -389,6 +389,21 @@ moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X, const int32_
                                  void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * moe_expert_ffn_gather_save -- moe_expert_ffn_gather that also stores the
+ *   first product's pre-activations for the backward (training forwards):
+ *     AB[r] = [A_r | B_r] = [Xp_r W1_e^T | Xp_r W3_e^T]   [N, 2*d_ff] BF16 out
+ *   (A in columns 0..d_ff-1, B in d_ff..2*d_ff-1; each value is the FP32
+ *   product rounded to BF16, the same values moe_expert_ffn_bwd recomputes).
+ *   Y is bit-identical to moe_expert_ffn_gather's.  AB: caller-owned, 16-byte
+ *   aligned, not NULL when T > 0 (else MOE_EINVAL); other arguments and
+ *   errors as moe_expert_ffn_gather.
+ */
+moe_status moe_expert_ffn_gather_save(const moe_cfg* cfg, const void* X, const int32_t* row_map,
+                                      const int32_t* offsets, const void* W13, const void* W2,
+                                      void* Y, void* AB, void* ws, size_t ws_bytes,
+                                      void* stream);
+
+/*
  * moe_expert_ffn_gather_fp8 -- the FP8-expert moe_expert_ffn with the permute
  *   fused into the first product: slot row r reads token row row_map[r] of
  *   the per-token codes X_codes [T,d] u8 and scales X_scale [T, d/128] f32
@@ -513,6 +528,21 @@ moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X, const int32_t* 
                               const int32_t* offsets, const void* dY, const void* W13,
                               const void* W2, void* dX_perm, void* dW13, void* dW2,
                               int grad_dtype, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * moe_expert_ffn_bwd_saved -- moe_expert_ffn_bwd reading the pre-activations
+ *   AB [N, 2*d_ff] BF16 that moe_expert_ffn_gather_save stored for the same
+ *   X, row_map, offsets and W13, instead of recomputing them (the first
+ *   product of the backward is skipped).  Results are bit-identical to
+ *   moe_expert_ffn_bwd's.  AB: 16-byte aligned, not NULL when T > 0 (else
+ *   MOE_EINVAL); read only.  Other arguments, workspace size and errors as
+ *   moe_expert_ffn_bwd.
+ */
+moe_status moe_expert_ffn_bwd_saved(const moe_cfg* cfg, const void* X, const int32_t* row_map,
+                                    const int32_t* offsets, const void* dY, const void* W13,
+                                    const void* W2, const void* AB, void* dX_perm, void* dW13,
+                                    void* dW2, int grad_dtype, void* ws, size_t ws_bytes,
+                                    void* stream);
 
 /*
  * moe_dispatch_bwd -- derivative of moe_dispatch's permute:

@@ -59,6 +59,7 @@ SIGNATURES = {
     "moe_dispatch_noalloc": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P],
     "moe_expert_ffn": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_expert_ffn_gather": [_CFG, _P, _P, _P, _P, _P, _P, _P, _S, _P],
+    "moe_expert_ffn_gather_save": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_expert_ffn_gather_fp8": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
     "moe_quantize_mx": [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P],
     "moe_expert_ffn_mx": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _S, _P],
@@ -66,6 +67,8 @@ SIGNATURES = {
     "moe_combine": [_CFG, _P, _P, _P, _P, _P],
     "moe_combine_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P],
     "moe_expert_ffn_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int, _P, _S, _P],
+    "moe_expert_ffn_bwd_saved": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int, _P,
+                                 _S, _P],
     "moe_dispatch_bwd": [_CFG, _P, _P, _P, _P],
     "moe_route_bwd": [_CFG, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_int, _P, _P, _P, _S,
                       _P],
@@ -176,6 +179,12 @@ def moe_expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, Y, ws, ws_bytes, st
                                        ws_bytes, stream), "moe_expert_ffn_gather")
 
 
+def moe_expert_ffn_gather_save(cfg, X, row_map, offsets, W13, W2, Y, AB, ws, ws_bytes, stream):
+    _check(lib().moe_expert_ffn_gather_save(ctypes.byref(cfg), X, row_map, offsets, W13, W2, Y,
+                                            AB, ws, ws_bytes, stream),
+           "moe_expert_ffn_gather_save")
+
+
 def moe_quantize_fp8(rows, cols, block_rows, src_dtype, src, codes, scales, stream):
     _check(lib().moe_quantize_fp8(int(rows), int(cols), int(block_rows), int(src_dtype), src, codes,
                                   scales, stream), "moe_quantize_fp8")
@@ -195,6 +204,14 @@ def moe_expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, dX_perm, dW13, dW2
     _check(lib().moe_expert_ffn_bwd(ctypes.byref(cfg), X, row_map, offsets, dY, W13, W2, dX_perm,
                                     dW13, dW2, grad_dtype, ws, ws_bytes, stream),
            "moe_expert_ffn_bwd")
+
+
+def moe_expert_ffn_bwd_saved(cfg, X, row_map, offsets, dY, W13, W2, AB, dX_perm, dW13, dW2,
+                             grad_dtype, ws, ws_bytes, stream):
+    _check(lib().moe_expert_ffn_bwd_saved(ctypes.byref(cfg), X, row_map, offsets, dY, W13, W2,
+                                          AB, dX_perm, dW13, dW2, grad_dtype, ws, ws_bytes,
+                                          stream),
+           "moe_expert_ffn_bwd_saved")
 
 
 def moe_dispatch_noalloc(cfg, X, topk_idx, offsets, row_map, inv_map, X_perm, X_perm_scale,

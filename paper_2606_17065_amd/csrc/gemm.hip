@@ -238,7 +238,7 @@ __device__ __forceinline__ void zero_acc(f32x16 (&acc)[4][2]) {
 }
 
 // Epilogue modes of the row-grouped kernel.
-enum { EPI_SWIGLU = 0, EPI_PLAIN = 1, EPI_AB = 2 };
+enum { EPI_SWIGLU = 0, EPI_PLAIN = 1, EPI_AB = 2, EPI_SWIGLU_AB = 3 };
 
 // Row-grouped kernel (rows of each expert against that expert's weights).
 //   EPI_SWIGLU: B-tile = 64 W1 rows + the 64 matching W3 rows; stores
@@ -375,12 +375,60 @@ constexpr int XA_INS = GBM * 128 / 1024 / XW, XB_INS = XBN * 128 / 1024 / XW;
 // EPI_AB (backward): the SwiGLU tiles, storing A and B themselves (row
 // length 2f: A at column n, B at column f + n).  GATHER: token row r of
 // the A operand is X[row_map[r]] (the permute recomputed, not read).
+// Epilogue of the 256 x 256 tile: the wavefront's 128 x 64 accumulators
+// (4 x 2 tiles of 32 x 32) staged through LDS and written as rows of 16-byte
+// chunks.  WS_H: h = silu(A) * B of the paired tile (128 columns at
+// nt * 128); WS_AB: A in columns 0..127 of the staged tile, B in 128..255,
+// stored at n0 + c and f + n0 + c; WS_PLAIN: 256 columns at nt * 256.
+enum { WS_H = 0, WS_AB = 1, WS_PLAIN = 2 };
+template <int MODE>
+__device__ __forceinline__ void wide_store(const f32x16 (&acc)[4][2], char* lds,
+                                           bf16_t* __restrict__ C, int Ncols, int rows,
+                                           int row0, int n0, int nt, int f) {
+  constexpr int CS = MODE == WS_H ? 128 : 256;
+  constexpr int CLD = CS + 8;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 2, wn = wv & 3, fr = lane & 31, fh = lane >> 5;
+  bf16_t* Cs = (bf16_t*)lds;
+  const int cbase = fh * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rl = wm * 128 + i * 32 + fr;
+#pragma unroll
+    for (int j = 0; j < (MODE == WS_H ? 1 : 2); ++j) {
+      const int col0 =
+          MODE == WS_H ? wn * 32 : (MODE == WS_AB ? j * 128 + wn * 32 : wn * 64 + j * 32);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        bf16x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float x = acc[i][j][g * 4 + q];
+          if (MODE == WS_H) v[q] = (bf16_t)(silu(x) * acc[i][1][g * 4 + q]);
+          else v[q] = (bf16_t)x;
+        }
+        *(bf16x4*)(Cs + rl * CLD + col0 + g * 8 + cbase) = v;
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int CPR = CS / 8;
+  for (int c = tid; c < GBM * CPR; c += 64 * XW) {
+    const int rr = c / CPR, cc = (c - rr * CPR) * 8;
+    if (rr >= rows) continue;
+    size_t col;
+    if (MODE == WS_AB) col = cc < 128 ? (size_t)n0 + cc : (size_t)f + n0 + (cc - 128);
+    else col = (size_t)nt * CS + cc;
+    *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + col) = *(const u32x4*)(Cs + rr * CLD + cc);
+  }
+}
+
 template <int EPI, bool GATHER>
 __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
     const bf16_t* __restrict__ A, const int32_t* __restrict__ row_map, int T,
     const bf16_t* __restrict__ B, bf16_t* __restrict__ C, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ tile_start, int E, int N, int K, int f, int Ncols, int n_tiles,
-    int grid_total) {
+    int grid_total, bf16_t* __restrict__ C2) {
   typedef __attribute__((address_space(3))) void lds_void;
   constexpr bool PAIRED = EPI != EPI_PLAIN;
   __shared__ __attribute__((aligned(1024))) char lds[XLDS];
@@ -484,41 +532,13 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   WAIT_VM_LGKM0(0);
   stage_barrier();
 
-  // SwiGLU: 128 h columns per tile; EPI_AB: the A half in columns 0..127 of
-  // the LDS tile and the B half in 128..255; plain: 256 columns
-  constexpr int CS = EPI == EPI_SWIGLU ? 128 : 256;
-  constexpr int CLD = CS + 8;
-  bf16_t* Cs = (bf16_t*)lds;
-  const int cbase = fh * 4;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int rl = wm * 128 + i * 32 + fr;
-#pragma unroll
-    for (int j = 0; j < (EPI == EPI_SWIGLU ? 1 : 2); ++j) {
-      const int col0 = EPI == EPI_SWIGLU ? wn * 32
-                                         : (EPI == EPI_AB ? j * 128 + wn * 32 : wn * 64 + j * 32);
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        bf16x4 v;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float x = acc[i][j][g * 4 + q];
-          if (EPI == EPI_SWIGLU) v[q] = (bf16_t)(silu(x) * acc[i][1][g * 4 + q]);
-          else v[q] = (bf16_t)x;
-        }
-        *(bf16x4*)(Cs + rl * CLD + col0 + g * 8 + cbase) = v;
-      }
-    }
-  }
-  __syncthreads();
-  constexpr int CPR = CS / 8;
-  for (int c = tid; c < GBM * CPR; c += 64 * XW) {
-    const int rr = c / CPR, cc = (c - rr * CPR) * 8;
-    if (rr >= rows) continue;
-    size_t col;
-    if (EPI == EPI_AB) col = cc < 128 ? (size_t)n0 + cc : (size_t)f + n0 + (cc - 128);
-    else col = (size_t)nt * CS + cc;
-    *(u32x4*)(C + (size_t)(row0 + rr) * Ncols + col) = *(const u32x4*)(Cs + rr * CLD + cc);
+  // SwiGLU: 128 h columns per tile; EPI_AB: A and B; plain: 256 columns;
+  // EPI_SWIGLU_AB: h into C, then A and B into C2 (row length 2f)
+  wide_store<(EPI == EPI_SWIGLU || EPI == EPI_SWIGLU_AB) ? WS_H : (EPI == EPI_AB ? WS_AB : WS_PLAIN)>(
+      acc, lds, C, Ncols, rows, row0, n0, nt, f);
+  if (EPI == EPI_SWIGLU_AB) {
+    __syncthreads();  // every thread is done reading the h tile
+    wide_store<WS_AB>(acc, lds, C2, 2 * f, rows, row0, n0, nt, f);
   }
 }
 
@@ -526,9 +546,10 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   template __global__ void gemm_bf16_wide<EPI, GATHER>(                                     \
       const bf16_t* __restrict__, const int32_t* __restrict__, int, const bf16_t* __restrict__, \
       bf16_t* __restrict__, const int32_t* __restrict__, const int32_t* __restrict__, int, int, \
-      int, int, int, int, int);
+      int, int, int, int, int, bf16_t* __restrict__);
 MOE_INST_WIDE(EPI_SWIGLU, false)
 MOE_INST_WIDE(EPI_SWIGLU, true)
+MOE_INST_WIDE(EPI_SWIGLU_AB, true)
 MOE_INST_WIDE(EPI_PLAIN, false)
 MOE_INST_WIDE(EPI_AB, true)
 #undef MOE_INST_WIDE
@@ -1787,7 +1808,7 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
       hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_SWIGLU, false>), dim3(G),
                          dim3(64 * XW), 0, st, (const bf16_t*)X_perm, nullptr, 0,
                          (const bf16_t*)W13, (bf16_t*)w.h, offsets, w.tile_start_big, c.E, N, c.d,
-                         c.d_ff, c.d_ff, nt, G);
+                         c.d_ff, c.d_ff, nt, G, nullptr);
     } else {
       const int nt = c.d_ff / 64;
       const int G = (mt_big * nt + 7) / 8 * 8;
@@ -1803,7 +1824,7 @@ extern "C" moe_status moe_expert_ffn(const moe_cfg* cfg, const void* X_perm,
       hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G),
                          dim3(64 * XW), 0, st, (const bf16_t*)w.h, nullptr, 0, (const bf16_t*)W2,
                          (bf16_t*)Y, offsets, w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt,
-                         G);
+                         G, nullptr);
     } else {
       const int nt = c.d / 128;
       const int G = (mt_big * nt + 7) / 8 * 8;
@@ -1878,11 +1899,14 @@ size_t ffn_bwd_ws_bytes(const moe_cfg& c) {
   return total;
 }
 
-extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
-                                         const int32_t* row_map, const int32_t* offsets,
-                                         const void* dY, const void* W13, const void* W2,
-                                         void* dX_perm, void* dW13, void* dW2, int grad_dtype,
-                                         void* ws, size_t ws_bytes, void* stream) {
+namespace {
+
+// The expert backward; AB (the forward's pre-activations) replaces the
+// recomputation of [A|B] when given.
+moe_status ffn_bwd_impl(const moe_cfg* cfg, const void* X, const int32_t* row_map,
+                        const int32_t* offsets, const void* dY, const void* W13, const void* W2,
+                        const void* AB, void* dX_perm, void* dW13, void* dW2, int grad_dtype,
+                        void* ws, size_t ws_bytes, void* stream) {
   moe_status stc = check_cfg_shape(cfg);
   if (stc != MOE_OK) return stc;
   const moe_cfg& c = *cfg;
@@ -1893,7 +1917,7 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
   if (c.T > 0 && (!X || !row_map || !dY || !dX_perm)) return MOE_EINVAL;
   if (!aligned(X, 16) || !aligned(dY, 16) || !aligned(W13, 16) || !aligned(W2, 16) ||
       !aligned(dX_perm, 16) || !aligned(dW13, 16) || !aligned(dW2, 16) || !aligned(offsets, 4) ||
-      !aligned(row_map, 4))
+      !aligned(row_map, 4) || !aligned(AB, 16))
     return MOE_EINVAL;
   if (ws_bytes < ffn_bwd_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
@@ -1911,18 +1935,22 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
                      (const bf16_t*)W2, w.W2T, d, f);
   const int mt = (N + GBM - 1) / GBM + E;
   if (N > 0) {
-    {  // [A|B] = Xp W13^T with the permute recomputed (f % 128 == 0)
+    // [A|B] = Xp W13^T with the permute recomputed (f % 128 == 0), unless
+    // the forward's are given
+    const bf16_t* ABp = (const bf16_t*)AB;
+    if (!ABp) {
       const int nt = f / 128, G = (mt * nt + 7) / 8 * 8;
       hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_AB, true>), dim3(G), dim3(64 * XW), 0,
                          st, Xb, row_map, c.T, (const bf16_t*)W13, w.AB, offsets, w.tile_start, E,
-                         N, d, f, 2 * f, nt, G);
+                         N, d, f, 2 * f, nt, G, nullptr);
+      ABp = w.AB;
     }
     {  // U = dY W2 (BF16, 256 columns of f per tile when f allows), then dA, dB, h
       if (f % XBN == 0) {
         const int nt = f / XBN, G = (mt * nt + 7) / 8 * 8;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G),
                            dim3(64 * XW), 0, st, dYb, nullptr, 0, w.W2T, w.U, offsets,
-                           w.tile_start, E, N, d, d, f, nt, G);
+                           w.tile_start, E, N, d, d, f, nt, G, nullptr);
       } else {
         const int nt = f / GBN, G = (mt * nt + 7) / 8 * 8;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_PLAIN, false>), dim3(G), dim3(256),
@@ -1930,14 +1958,14 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
                            f, nt, G);
       }
       const int m64 = (N + DE_TILE - 1) / DE_TILE + E;
-      hipLaunchKernelGGL(dgrad_elem, dim3(m64, f / DE_TILE), dim3(256), 0, st, w.U, w.AB, w.dAB,
+      hipLaunchKernelGGL(dgrad_elem, dim3(m64, f / DE_TILE), dim3(256), 0, st, w.U, ABp, w.dAB,
                          w.dABT, w.hT, w.ldT, offsets, w.tile64, w.ptile, E, N, f);
     }
     {  // dX_perm = [dA|dB] W13 (d % 256 == 0: the 256 x 256 tile)
       const int nt = d / 256, G = (mt * nt + 7) / 8 * 8;
       hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G),
                          dim3(64 * XW), 0, st, w.dAB, nullptr, 0, w.W13T, (bf16_t*)dX_perm,
-                         offsets, w.tile_start, E, N, 2 * f, f, d, nt, G);
+                         offsets, w.tile_start, E, N, 2 * f, f, d, nt, G, nullptr);
     }
     const int pblocks = (w.ldT + 63) / 64;
     hipLaunchKernelGGL(slot_transpose, dim3(pblocks, d / 64), dim3(256), 0, st, Xb, row_map, c.T,
@@ -1977,6 +2005,28 @@ extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
   return MOE_OK;
 }
 
+}  // namespace
+
+extern "C" moe_status moe_expert_ffn_bwd(const moe_cfg* cfg, const void* X,
+                                         const int32_t* row_map, const int32_t* offsets,
+                                         const void* dY, const void* W13, const void* W2,
+                                         void* dX_perm, void* dW13, void* dW2, int grad_dtype,
+                                         void* ws, size_t ws_bytes, void* stream) {
+  return ffn_bwd_impl(cfg, X, row_map, offsets, dY, W13, W2, nullptr, dX_perm, dW13, dW2,
+                      grad_dtype, ws, ws_bytes, stream);
+}
+
+extern "C" moe_status moe_expert_ffn_bwd_saved(const moe_cfg* cfg, const void* X,
+                                               const int32_t* row_map, const int32_t* offsets,
+                                               const void* dY, const void* W13, const void* W2,
+                                               const void* AB, void* dX_perm, void* dW13,
+                                               void* dW2, int grad_dtype, void* ws,
+                                               size_t ws_bytes, void* stream) {
+  if (cfg && cfg->T > 0 && !AB) return MOE_EINVAL;
+  return ffn_bwd_impl(cfg, X, row_map, offsets, dY, W13, W2, AB, dX_perm, dW13, dW2, grad_dtype,
+                      ws, ws_bytes, stream);
+}
+
 extern "C" moe_status moe_quantize_fp8(int rows, int cols, int block_rows, int src_dtype,
                                        const void* src, uint8_t* codes, float* scales,
                                        void* stream) {
@@ -2011,10 +2061,13 @@ extern "C" moe_status moe_quantize_fp8(int rows, int cols, int block_rows, int s
   return MOE_OK;
 }
 
-extern "C" moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X,
-                                            const int32_t* row_map, const int32_t* offsets,
-                                            const void* W13, const void* W2, void* Y, void* ws,
-                                            size_t ws_bytes, void* stream) {
+namespace {
+
+// The gather-fused BF16 expert products; with AB the first product also
+// stores its pre-activations [A|B] for the backward.
+moe_status ffn_gather_impl(const moe_cfg* cfg, const void* X, const int32_t* row_map,
+                           const int32_t* offsets, const void* W13, const void* W2, void* Y,
+                           void* AB, void* ws, size_t ws_bytes, void* stream) {
   moe_status stc = check_cfg_shape(cfg);
   if (stc != MOE_OK) return stc;
   const moe_cfg& c = *cfg;
@@ -2023,7 +2076,7 @@ extern "C" moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X,
   if (!offsets || !W13 || !W2) return MOE_EINVAL;
   if (c.T > 0 && (!X || !row_map || !Y)) return MOE_EINVAL;
   if (!aligned(X, 16) || !aligned(W13, 16) || !aligned(W2, 16) || !aligned(Y, 16) ||
-      !aligned(offsets, 4) || !aligned(row_map, 4))
+      !aligned(offsets, 4) || !aligned(row_map, 4) || !aligned(AB, 16))
     return MOE_EINVAL;
   if (ws_bytes < ffn_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
   if (c.T == 0) return MOE_OK;
@@ -2036,9 +2089,16 @@ extern "C" moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X,
     const int nt = c.d_ff / 128;
     const int G = (mt_big * nt + 7) / 8 * 8;
     PROF_BEGIN("gemm1_swiglu", st);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_SWIGLU, true>), dim3(G), dim3(64 * XW),
-                       0, st, (const bf16_t*)X, row_map, c.T, (const bf16_t*)W13, (bf16_t*)w.h,
-                       offsets, w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt, G);
+    if (AB)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_SWIGLU_AB, true>), dim3(G),
+                         dim3(64 * XW), 0, st, (const bf16_t*)X, row_map, c.T,
+                         (const bf16_t*)W13, (bf16_t*)w.h, offsets, w.tile_start_big, c.E, N, c.d,
+                         c.d_ff, c.d_ff, nt, G, (bf16_t*)AB);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_SWIGLU, true>), dim3(G),
+                         dim3(64 * XW), 0, st, (const bf16_t*)X, row_map, c.T,
+                         (const bf16_t*)W13, (bf16_t*)w.h, offsets, w.tile_start_big, c.E, N, c.d,
+                         c.d_ff, c.d_ff, nt, G, nullptr);
     PROF_END("gemm1_swiglu", st);
   }
   {
@@ -2047,11 +2107,29 @@ extern "C" moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X,
     PROF_BEGIN("gemm2", st);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G), dim3(64 * XW),
                        0, st, (const bf16_t*)w.h, nullptr, 0, (const bf16_t*)W2, (bf16_t*)Y,
-                       offsets, w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt, G);
+                       offsets, w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt, G, nullptr);
     PROF_END("gemm2", st);
   }
   MOE_LAUNCH_CHECK();
   return MOE_OK;
+}
+
+}  // namespace
+
+extern "C" moe_status moe_expert_ffn_gather(const moe_cfg* cfg, const void* X,
+                                            const int32_t* row_map, const int32_t* offsets,
+                                            const void* W13, const void* W2, void* Y, void* ws,
+                                            size_t ws_bytes, void* stream) {
+  return ffn_gather_impl(cfg, X, row_map, offsets, W13, W2, Y, nullptr, ws, ws_bytes, stream);
+}
+
+extern "C" moe_status moe_expert_ffn_gather_save(const moe_cfg* cfg, const void* X,
+                                                 const int32_t* row_map, const int32_t* offsets,
+                                                 const void* W13, const void* W2, void* Y,
+                                                 void* AB, void* ws, size_t ws_bytes,
+                                                 void* stream) {
+  if (cfg && cfg->T > 0 && !AB) return MOE_EINVAL;
+  return ffn_gather_impl(cfg, X, row_map, offsets, W13, W2, Y, AB, ws, ws_bytes, stream);
 }
 
 extern "C" moe_status moe_expert_ffn_gather_fp8(const moe_cfg* cfg, const uint8_t* X_codes,

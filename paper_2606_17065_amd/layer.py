@@ -220,7 +220,9 @@ def gather_fused(cfg) -> bool:
             and cfg.d % 256 == 0)
 
 
-def expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, ws=None):
+def expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, ws=None, save_ab=False):
+    """Y [N,d]; with save_ab, (Y, AB) where AB [N, 2f] holds the first
+    product's pre-activations [A|B] for expert_ffn_bwd."""
     N, d, E, f = cfg.T * cfg.k, cfg.d, cfg.E, cfg.d_ff
     _need(X, "X", _DT[cfg.act], (cfg.T, d))
     _need(row_map, "row_map", torch.int32, (N,))
@@ -229,9 +231,14 @@ def expert_ffn_gather(cfg, X, row_map, offsets, W13, W2, ws=None):
     _need(W2, "W2", _DT[cfg.w], (E, d, f))
     Y = torch.empty(N, d, dtype=X.dtype, device=X.device)
     ws = _WS.get(cfg, X.device) if ws is None else ws
-    L.moe_expert_ffn_gather(cfg, _p(X), _p(row_map), _p(offsets), _p(W13), _p(W2), _p(Y), _p(ws),
-                            ws.numel(), _stream())
-    return Y
+    if not save_ab:
+        L.moe_expert_ffn_gather(cfg, _p(X), _p(row_map), _p(offsets), _p(W13), _p(W2), _p(Y),
+                                _p(ws), ws.numel(), _stream())
+        return Y
+    AB = torch.empty(N, 2 * f, dtype=X.dtype, device=X.device)
+    L.moe_expert_ffn_gather_save(cfg, _p(X), _p(row_map), _p(offsets), _p(W13), _p(W2), _p(Y),
+                                 _p(AB), _p(ws), ws.numel(), _stream())
+    return Y, AB
 
 
 def gather_fused_fp8(cfg) -> bool:
@@ -269,9 +276,11 @@ def check_status(info, where="moe_route"):
 
 
 def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None, fuse=True,
-            check=True):
+            check=True, save_ab=False):
     """The whole layer forward; returns every intermediate (X_perm is None
-    when the permute is fused into the first expert product).
+    when the permute is fused into the first expert product).  save_ab: on
+    the gather-fused BF16 path, also keep the first product's
+    pre-activations as r["AB"] (for the backward; None on other paths).
 
     check: after enqueueing every stage, wait for the stream and raise
     MoEError if the routing failed on the device (a non-finite logit, or a
@@ -279,9 +288,14 @@ def forward(cfg, X, Wr, br, W13, W2, price=None, W13_scale=None, W2_scale=None, 
     nothing waits; a failed routing then carries NaN gate weights, so the
     layer output is NaN rather than a plausible-looking value."""
     r = route(cfg, X, Wr, br, price)
+    r["AB"] = None
     if fuse and gather_fused(cfg):
         dsp = dispatch(cfg, X, r["idx"], permute=False)
-        Y = expert_ffn_gather(cfg, X, dsp["row_map"], dsp["offsets"], W13, W2)
+        if save_ab:
+            Y, r["AB"] = expert_ffn_gather(cfg, X, dsp["row_map"], dsp["offsets"], W13, W2,
+                                           save_ab=True)
+        else:
+            Y = expert_ffn_gather(cfg, X, dsp["row_map"], dsp["offsets"], W13, W2)
     elif cfg.w in MX_DTYPES:
         # tokens MX-quantised once, gathered by the first product
         Xq, Xs = quantize_mx(X, cfg.w)
@@ -324,9 +338,12 @@ def combine_bwd(cfg, dOut, Y, inv_map, w):
 _GRAD_DT = {torch.float32: L.MOE_F32, torch.bfloat16: L.MOE_BF16}
 
 
-def expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, ws=None, grad_dtype=torch.float32):
+def expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, ws=None, grad_dtype=torch.float32,
+                   AB=None):
     """dX_perm [N,d] (act dtype) and the weight gradients dW13, dW2 stored in
-    grad_dtype (float32 or bfloat16; FP32 accumulation either way)."""
+    grad_dtype (float32 or bfloat16; FP32 accumulation either way).  AB: the
+    pre-activations expert_ffn_gather(save_ab=True) stored, read instead of
+    recomputed (same results)."""
     N, d, E, f = cfg.T * cfg.k, cfg.d, cfg.E, cfg.d_ff
     _need(X, "X", _DT[cfg.act], (cfg.T, d))
     _need(dY, "dY", _DT[cfg.act], (N, d))
@@ -335,8 +352,15 @@ def expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2, ws=None, grad_dtype=to
     dW13 = torch.empty(E, 2 * f, d, dtype=grad_dtype, device=dev)
     dW2 = torch.empty(E, d, f, dtype=grad_dtype, device=dev)
     ws = _WS.get(cfg, dev) if ws is None else ws
-    L.moe_expert_ffn_bwd(cfg, _p(X), _p(row_map), _p(offsets), _p(dY), _p(W13), _p(W2), _p(dXp),
-                         _p(dW13), _p(dW2), _GRAD_DT[grad_dtype], _p(ws), ws.numel(), _stream())
+    if AB is None:
+        L.moe_expert_ffn_bwd(cfg, _p(X), _p(row_map), _p(offsets), _p(dY), _p(W13), _p(W2),
+                             _p(dXp), _p(dW13), _p(dW2), _GRAD_DT[grad_dtype], _p(ws), ws.numel(),
+                             _stream())
+    else:
+        _need(AB, "AB", _DT[cfg.act], (N, 2 * f))
+        L.moe_expert_ffn_bwd_saved(cfg, _p(X), _p(row_map), _p(offsets), _p(dY), _p(W13),
+                                   _p(W2), _p(AB), _p(dXp), _p(dW13), _p(dW2),
+                                   _GRAD_DT[grad_dtype], _p(ws), ws.numel(), _stream())
     return dXp, dW13, dW2
 
 
@@ -361,32 +385,35 @@ def route_bwd(cfg, X, Wr, idx, w, dw, row_map, offsets, inv_map, dXp, ws=None,
 
 class MoEFunction(torch.autograd.Function):
     """The layer as one differentiable op.  Saves X, the routing (indices,
-    gate weights, slot maps) and Y; the permuted tokens and the first expert
-    GEMM are recomputed in the backward.  Gradients flow to X, W_r, b_r, W13
-    and W2; none flows into the prices or through the expert selection."""
+    gate weights, slot maps), Y and, with save_ab on the gather-fused BF16
+    path, the first expert product's pre-activations [A|B] (N x 2 d_ff
+    values, kept instead of recomputing that product in the backward; the
+    gradients are the same either way).  The permuted tokens are recomputed
+    through row_map.  Gradients flow to X, W_r, b_r, W13 and W2; none flows
+    into the prices or through the expert selection."""
 
     @staticmethod
-    def forward(ctx, X, Wr, br, W13, W2, cfg, check=True):
-        r = forward(cfg, X, Wr, br, W13, W2, check=check)
+    def forward(ctx, X, Wr, br, W13, W2, cfg, check=True, save_ab=True):
+        r = forward(cfg, X, Wr, br, W13, W2, check=check, save_ab=save_ab)
         ctx.cfg = cfg
         ctx.save_for_backward(X, Wr, W13, W2, r["idx"], r["w"], r["row_map"], r["offsets"],
-                              r["inv_map"], r["Y"])
+                              r["inv_map"], r["Y"], r["AB"])
         return r["out"]
 
     @staticmethod
     def backward(ctx, dOut):
-        X, Wr, W13, W2, idx, w, row_map, offsets, inv_map, Y = ctx.saved_tensors
+        X, Wr, W13, W2, idx, w, row_map, offsets, inv_map, Y, AB = ctx.saved_tensors
         cfg = ctx.cfg
         dOut = dOut.to(Y.dtype).contiguous()
         dY, dw = combine_bwd(cfg, dOut, Y, inv_map, w)
         # gradients stored directly in their parameters' dtypes (FP32 sums)
         dXp, dW13, dW2 = expert_ffn_bwd(cfg, X, row_map, offsets, dY, W13, W2,
-                                        grad_dtype=W13.dtype)
+                                        grad_dtype=W13.dtype, AB=AB)
         dX, dWr, dbr = route_bwd(cfg, X, Wr, idx, w, dw, row_map, offsets, inv_map, dXp,
                                  dx_dtype=X.dtype)
-        return (dX, dWr, dbr, dW13, dW2, None, None)
+        return (dX, dWr, dbr, dW13, dW2, None, None, None)
 
 
-def moe_layer(cfg, X, Wr, br, W13, W2, check=True):
+def moe_layer(cfg, X, Wr, br, W13, W2, check=True, save_ab=True):
     """Differentiable layer forward (see MoEFunction; check as in forward)."""
-    return MoEFunction.apply(X, Wr, br, W13, W2, cfg, check)
+    return MoEFunction.apply(X, Wr, br, W13, W2, cfg, check, save_ab)

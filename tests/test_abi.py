@@ -106,6 +106,23 @@ def test_entry_points_reject_bad_arguments_on_the_host():
         L.moe_expert_ffn_gather(_cfg(d=256, act=L.MOE_BF16, w=L.MOE_BF16), fake, None, fake, fake, fake,
                                 fake, fake, 1 << 30, None)
     assert e.value.status == L.MOE_EINVAL
+    bf = _cfg(d=256, act=L.MOE_BF16, w=L.MOE_BF16)
+    with pytest.raises(L.MoEError) as e:  # the saving forward needs the AB output
+        L.moe_expert_ffn_gather_save(bf, fake, fake, fake, fake, fake, fake, None, fake, 1 << 30,
+                                     None)
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:  # AB misaligned
+        L.moe_expert_ffn_gather_save(bf, fake, fake, fake, fake, fake, fake, fake + 8, fake,
+                                     1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:  # the saved-input backward needs AB
+        L.moe_expert_ffn_bwd_saved(bf, fake, fake, fake, fake, fake, fake, None, fake, fake, fake,
+                                   L.MOE_F32, fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EINVAL
+    with pytest.raises(L.MoEError) as e:  # BF16 only, as the recomputing backward
+        L.moe_expert_ffn_bwd_saved(_cfg(), fake, fake, fake, fake, fake, fake, fake, fake, fake,
+                                   fake, L.MOE_F32, fake, 1 << 30, None)
+    assert e.value.status == L.MOE_EUNSUPPORTED
     with pytest.raises(L.MoEError) as e:
         L.moe_quantize_fp8(4, 100, 1, L.MOE_BF16, fake, fake, fake, None)  # cols % 128
     assert e.value.status == L.MOE_EINVAL

@@ -101,6 +101,52 @@ def test_backward_bf16_outputs_are_the_rounded_fp32_results(shape, config):
                                       b.view(torch.int16).cpu().numpy(), err_msg=name)
 
 
+@pytest.mark.parametrize("shape,config", [(BWD, 36), (BWD2, 37), (BWD_K1, 38)])
+def test_saved_preactivations(shape, config):
+    """The training forward (moe_expert_ffn_gather_save) stores [A|B]: Y and
+    the layer output are bit-identical to the plain forward's; A and B are
+    the FP64 products Xp W1^T, Xp W3^T within BF16 rounding (element-wise);
+    and the backward that reads them (moe_expert_ffn_bwd_saved) returns the
+    recomputing backward's gradients bit for bit, FP32 and BF16."""
+    cfg, d, h, fw, dOut = _setup(shape, config)
+    fs = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"], save_ab=True)
+    torch.cuda.synchronize()
+    assert fs["AB"] is not None and fs["AB"].shape == (cfg.T * cfg.k, 2 * cfg.d_ff)
+    for key in ("Y", "out"):
+        np.testing.assert_array_equal(fs[key].view(torch.int16).cpu().numpy(),
+                                      fw[key].view(torch.int16).cpu().numpy(), err_msg=key)
+    off = fw["offsets"].cpu().numpy()
+    Xp = h["X"][fw["row_map"].cpu().numpy()]
+    f = cfg.d_ff
+    AB64 = np.zeros((cfg.T * cfg.k, 2 * f))
+    for e in range(cfg.E):
+        a, b = int(off[e]), int(off[e + 1])
+        AB64[a:b] = Xp[a:b] @ h["W13"][e].T
+    assert_close(fs["AB"].float().cpu().numpy(), AB64, 4e-3, "AB", max_tol=8e-3)
+    dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
+    for dt in (torch.float32, torch.bfloat16):
+        ref = layer.expert_ffn_bwd(cfg, d["X"], fw["row_map"], fw["offsets"], dY, d["W13"],
+                                   d["W2"], grad_dtype=dt)
+        got = layer.expert_ffn_bwd(cfg, d["X"], fw["row_map"], fw["offsets"], dY, d["W13"],
+                                   d["W2"], grad_dtype=dt, AB=fs["AB"])
+        torch.cuda.synchronize()
+        for name, a, b in zip(("dX_perm", "dW13", "dW2"), ref, got):
+            assert torch.equal(a, b), (name, dt)
+
+
+def test_autograd_with_and_without_saved_preactivations_agree():
+    cfg, d, h, fw, dOut = _setup(BWD2, 39)
+    grads = []
+    for save in (False, True):
+        leaves = [d[k].clone().requires_grad_(True) for k in ("X", "Wr", "br", "W13", "W2")]
+        out = layer.moe_layer(cfg, *leaves, save_ab=save)
+        out.backward(dOut)
+        torch.cuda.synchronize()
+        grads.append([t.grad for t in leaves])
+    for name, a, b in zip(("X", "Wr", "br", "W13", "W2"), *grads):
+        assert torch.equal(a, b), name
+
+
 def test_dispatch_backward_is_a_gather_sum():
     cfg, d, h, fw, dOut = _setup(BWD, 33)
     dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
