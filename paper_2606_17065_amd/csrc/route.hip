@@ -457,7 +457,9 @@ __device__ __forceinline__ void rank_pass(const float* __restrict__ sT,
   uint64_t V[L];
 #pragma unroll
   for (int j = 0; j < L; ++j) V[j] = 0ull;
-  if (cached && NV <= L) {
+  if (cached && NV <= 2 * L) {
+    // all NV keys sorted, the best L kept (for NV <= 2L fewer
+    // compare-exchanges than inserting the NV keys one by one)
     uint64_t W[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
