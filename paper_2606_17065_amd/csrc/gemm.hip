@@ -542,6 +542,139 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   }
 }
 
+// ------------------------------------- BF16 MFMA, 256x256, K-major B
+// The plain product C[r] = A[r] B_e with B_e stored K-major, [K, Ncols] row
+// by row (a weight matrix as it is stored, e.g. W2_e [d, f] for U = dY W2_e),
+// so no transposed copy of B is made.  A, the tiles, the wavefront layout,
+// the two-stage ring and the epilogue are those of gemm_bf16_wide.  A stage
+// holds 64 K-rows of 256 B-columns (512 bytes each); the 16-byte chunks of
+// K-row k are stored at chunk ^ 4 (k & 3), so the transpose reads below hit
+// distinct LDS banks within each half-wavefront.  A B fragment (32 columns
+// x 16 K) is two ds_read_b64_tr_b16: within a group of 16 lanes, lane i
+// receives element i % 4 of the 8-byte pieces the group's lanes 4q + i / 4
+// (q = 0..3) point at; lane p of the group points at K-row kb + p / 4 and
+// columns c + 4 (p % 4) .. + 3, so lane i holds four consecutive K of
+// column c + i.
+typedef short v4s_t __attribute__((ext_vector_type(4)));
+typedef short v8s_t __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) v4s_t lds_v4s_t;
+
+__device__ __forceinline__ int bkm_off(int k, int n) {
+  return k * 512 + ((((n >> 3) ^ (4 * (k & 3))) & 31) << 4) + ((n & 7) << 1);
+}
+
+__global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide_bkm(
+    const bf16_t* __restrict__ A, const bf16_t* __restrict__ B, bf16_t* __restrict__ C,
+    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start, int E, int N,
+    int K, int Ncols, int n_tiles, int grid_total) {
+  typedef __attribute__((address_space(3))) void lds_void;
+  __shared__ __attribute__((aligned(1024))) char lds[XLDS];
+  const int b = blockIdx.x;
+  const int per = grid_total >> 3;
+  const int Lt = (b & 7) * per + (b >> 3);
+  int e, row0, rows, nt;
+  if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 2, wn = wv & 3;
+  const int n0 = nt * 256;
+  const bf16_t* Be = B + (size_t)e * K * Ncols;
+  const bf16_t* asrc[XA_INS];
+  const bf16_t* bsrc[XB_INS];
+#pragma unroll
+  for (int i = 0; i < XA_INS; ++i) {
+    const int R = wv * (GBM / XW) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
+    asrc[i] = A + (size_t)(row0 + min(R, rows - 1)) * K + c * 8;
+  }
+  // B: instruction i of wavefront wv fills K-rows 8 wv + 2 i (lanes 0..31)
+  // and 8 wv + 2 i + 1 (lanes 32..63), lane chunk c at physical chunk c
+#pragma unroll
+  for (int i = 0; i < XB_INS; ++i) {
+    const int kr = wv * 8 + i * 2 + (lane >> 5);
+    const int c = (lane & 31) ^ (4 * (kr & 3));
+    bsrc[i] = Be + (size_t)kr * Ncols + n0 + c * 8;
+  }
+  const int fr = lane & 31, fh = lane >> 5;
+  int aoff[4], asw[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int R = wm * 128 + i * 32 + fr;
+    aoff[i] = R * 128;
+    asw[i] = (R >> 1) & 7;
+  }
+  // transpose-read offsets of the two B fragments (kk = 0; +4 K-rows for
+  // the second read), relative to the stage and the 16-K step
+  const int g = lane >> 4, p = lane & 15;
+  int boff[2][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      boff[j][h] = bkm_off(8 * (g >> 1) + 4 * h + (p >> 2), wn * 64 + j * 32 + 16 * (g & 1) + 4 * (p & 3));
+  f32x16 acc[4][2];
+  zero_acc(acc);
+  const int nk = K / XBK;
+#define K_ISSUE(kstep)                                                                         \
+  {                                                                                            \
+    char* st_ = lds + ((kstep) & 1) * XSTAGE;                                                  \
+    const int k0_ = (kstep) * XBK;                                                             \
+    _Pragma("unroll") for (int i = 0; i < XA_INS; ++i) __builtin_amdgcn_global_load_lds(       \
+        asrc[i] + k0_, (lds_void*)(st_ + (wv * (GBM / XW) + i * 8) * 128), 16, 0, 0);          \
+    _Pragma("unroll") for (int i = 0; i < XB_INS; ++i) __builtin_amdgcn_global_load_lds(       \
+        bsrc[i] + (size_t)k0_ * Ncols, (lds_void*)(st_ + XSTAGE_A + (wv * 8 + i * 2) * 512),   \
+        16, 0, 0);                                                                             \
+  }
+  // the K-row of a B fragment read moves by 16 per K step: 16 * 512 bytes,
+  // with (k & 3) unchanged, so the swizzle of the offsets above still holds
+#define K_READ(AF, BF, stp, ks)                                                              \
+  {                                                                                          \
+    const char* st_ = lds + ((stp) & 1) * XSTAGE;                                            \
+    const int c_ = (ks) * 2 + fh;                                                            \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) AF[i] =                                    \
+        *(const bf16x8*)(st_ + aoff[i] + ((c_ ^ asw[i]) << 4));                              \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                          \
+      const char* bb_ = st_ + XSTAGE_A + (ks) * 16 * 512;                                \
+      const v4s_t lo_ = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s_t*)(bb_ + boff[j][0])); \
+      const v4s_t hi_ = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s_t*)(bb_ + boff[j][1])); \
+      BF[j] = __builtin_bit_cast(bf16x8, (v8s_t){lo_[0], lo_[1], lo_[2], lo_[3], hi_[0], hi_[1], hi_[2], hi_[3]}); \
+    }                                                                                        \
+  }
+#define K_MFMA(AF, BF)                                                                   \
+  _Pragma("unroll") for (int i = 0; i < 4; ++i) _Pragma("unroll") for (int j = 0; j < 2; \
+                                                                       ++j) acc[i][j] =  \
+      __builtin_amdgcn_mfma_f32_32x32x16_bf16(BF[j], AF[i], acc[i][j], 0, 0, 0);
+  bf16x8 a0[4], b0[2], a1[4], b1[2];
+  K_ISSUE(0);
+  if (nk > 1) {
+    K_ISSUE(1);
+    WAIT_VM_LGKM0(XA_INS + XB_INS);
+  } else {
+    WAIT_VM_LGKM0(0);
+  }
+  stage_barrier();
+  K_READ(a0, b0, 0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    __builtin_amdgcn_iglp_opt(1);
+    K_READ(a1, b1, kt, 1);
+    K_MFMA(a0, b0);
+    K_READ(a0, b0, kt, 2);
+    K_MFMA(a1, b1);
+    K_READ(a1, b1, kt, 3);
+    K_MFMA(a0, b0);
+    WAIT_VM_LGKM0(0);
+    stage_barrier();
+    if (kt + 2 < nk) K_ISSUE(kt + 2);
+    if (kt + 1 < nk) K_READ(a0, b0, kt + 1, 0);
+    K_MFMA(a1, b1);
+  }
+#undef K_ISSUE
+#undef K_READ
+#undef K_MFMA
+  WAIT_VM_LGKM0(0);
+  stage_barrier();
+  wide_store<WS_PLAIN>(acc, lds, C, Ncols, rows, row0, 0, nt, 0);
+}
+
 #define MOE_INST_WIDE(EPI, GATHER)                                                          \
   template __global__ void gemm_bf16_wide<EPI, GATHER>(                                     \
       const bf16_t* __restrict__, const int32_t* __restrict__, int, const bf16_t* __restrict__, \
@@ -1243,18 +1376,20 @@ MOE_INST_MX(4)
 #undef MOE_INST_MX
 
 // ------------------------------------------------------------- backward
-// Recompute-based backward of the expert FFN for the rows of each expert
-// (dY = w * dOut in slot order, supplied by the combine backward):
-//   [A|B] = Xp W13^T               (gemm_bf16_wide<EPI_AB, gather>)
-//   U = dY W2 (BF16)               (gemm_bf16_wide<EPI_PLAIN> on W2^T)
+// Backward of the expert FFN for the rows of each expert (dY = w * dOut in
+// slot order, supplied by the combine backward):
+//   [A|B] = Xp W13^T  (gemm_bf16_wide<EPI_AB, gather>; or the forward's,
+//                      stored by gemm_bf16_wide<EPI_SWIGLU_AB, gather>)
+//   U = dY W2 (BF16)  (gemm_bf16_wide_bkm reading W2 K-major; on W2^T with
+//                      the 256 x 128 tile when d_ff % 256 != 0)
 //   h = silu(A) B, dA = U B silu'(A), dB = U silu(A)
-//                                   (dgrad_elem, reading U and [A|B])
-//   dX_perm = [dA|dB] W13          (gemm_bf16_wide<EPI_PLAIN> on W13^T)
+//                     (dgrad_elem, reading U and [A|B])
+//   dX_perm = [dA|dB] W13          (gemm_bf16_wide_bkm reading W13 K-major)
 //   dW13_e = [dA|dB]^T Xp,  dW2_e = dY^T h          (gemm_wgrad_wide)
-// Every product is "NT" with both operands contiguous along the reduction:
-// the weights are transposed once per call, and the activations that the
-// weight gradients reduce over are written transposed [channel][slot] with
-// each expert's slot range padded to a multiple of PADK with zeros.
+// The weight gradients are "NT" products with both operands contiguous
+// along the reduction: the activations they reduce over are written
+// transposed [channel][slot] with each expert's slot range padded to a
+// multiple of PADK with zeros.
 
 // Four consecutive weight-gradient values: FP32, or rounded to BF16.
 __device__ __forceinline__ void store4(float* p, float a, float b, float c, float d) {
@@ -1858,7 +1993,7 @@ struct FfnBwdWs {
   int32_t* tile_start;
   int32_t* ptile;
   int32_t* tile64;  // schedule of 64-row tiles (the dA/dB/h pass)
-  bf16_t *W13T, *W2T, *AB, *U, *dAB, *dABT, *hT, *XpT, *dYT;
+  bf16_t *W2T, *AB, *U, *dAB, *dABT, *hT, *XpT, *dYT;
   int ldT;
 };
 
@@ -1877,8 +2012,9 @@ FfnBwdWs carve_ffn_bwd(const moe_cfg& c, void* base, size_t* total) {
   r.tile_start = wc.take<int32_t>(E + 1);
   r.ptile = wc.take<int32_t>(E + 1);
   r.tile64 = wc.take<int32_t>(E + 1);
-  r.W13T = wc.take<bf16_t>(E * 2 * f * d);
-  r.W2T = wc.take<bf16_t>(E * f * d);
+  // W2 transposed only for the 256 x 128 tile of U (d_ff % 256 != 0); the
+  // other data-gradient products read the weights K-major as stored
+  r.W2T = f % XBN != 0 ? wc.take<bf16_t>(E * f * d) : nullptr;
   r.AB = wc.take<bf16_t>(N * 2 * f);
   r.U = wc.take<bf16_t>(N * f);
   r.dAB = wc.take<bf16_t>(N * 2 * f);
@@ -1929,10 +2065,11 @@ moe_status ffn_bwd_impl(const moe_cfg* cfg, const void* X, const int32_t* row_ma
   hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, GBM, w.tile_start);
   hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, PADK, w.ptile);
   hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, E, DE_TILE, w.tile64);
-  hipLaunchKernelGGL(batched_transpose, dim3(d / 64, 2 * f / 64, E), dim3(256), 0, st,
-                     (const bf16_t*)W13, w.W13T, 2 * f, d);
-  hipLaunchKernelGGL(batched_transpose, dim3(f / 64, d / 64, E), dim3(256), 0, st,
-                     (const bf16_t*)W2, w.W2T, d, f);
+  // the data-gradient products read W13 and W2 K-major as stored (no
+  // transposed copy), except U on the 256 x 128 tile (d_ff % 256 != 0)
+  if (f % XBN != 0)
+    hipLaunchKernelGGL(batched_transpose, dim3(f / 64, d / 64, E), dim3(256), 0, st,
+                       (const bf16_t*)W2, w.W2T, d, f);
   const int mt = (N + GBM - 1) / GBM + E;
   if (N > 0) {
     // [A|B] = Xp W13^T with the permute recomputed (f % 128 == 0), unless
@@ -1948,9 +2085,8 @@ moe_status ffn_bwd_impl(const moe_cfg* cfg, const void* X, const int32_t* row_ma
     {  // U = dY W2 (BF16, 256 columns of f per tile when f allows), then dA, dB, h
       if (f % XBN == 0) {
         const int nt = f / XBN, G = (mt * nt + 7) / 8 * 8;
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G),
-                           dim3(64 * XW), 0, st, dYb, nullptr, 0, w.W2T, w.U, offsets,
-                           w.tile_start, E, N, d, d, f, nt, G, nullptr);
+        hipLaunchKernelGGL(gemm_bf16_wide_bkm, dim3(G), dim3(64 * XW), 0, st, dYb,
+                           (const bf16_t*)W2, w.U, offsets, w.tile_start, E, N, d, f, nt, G);
       } else {
         const int nt = f / GBN, G = (mt * nt + 7) / 8 * 8;
         hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_big<EPI_PLAIN, false>), dim3(G), dim3(256),
@@ -1961,11 +2097,11 @@ moe_status ffn_bwd_impl(const moe_cfg* cfg, const void* X, const int32_t* row_ma
       hipLaunchKernelGGL(dgrad_elem, dim3(m64, f / DE_TILE), dim3(256), 0, st, w.U, ABp, w.dAB,
                          w.dABT, w.hT, w.ldT, offsets, w.tile64, w.ptile, E, N, f);
     }
-    {  // dX_perm = [dA|dB] W13 (d % 256 == 0: the 256 x 256 tile)
+    {  // dX_perm = [dA|dB] W13 (d % 256 == 0: the 256 x 256 tile, W13 K-major)
       const int nt = d / 256, G = (mt * nt + 7) / 8 * 8;
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_bf16_wide<EPI_PLAIN, false>), dim3(G),
-                         dim3(64 * XW), 0, st, w.dAB, nullptr, 0, w.W13T, (bf16_t*)dX_perm,
-                         offsets, w.tile_start, E, N, 2 * f, f, d, nt, G, nullptr);
+      hipLaunchKernelGGL(gemm_bf16_wide_bkm, dim3(G), dim3(64 * XW), 0, st, w.dAB,
+                         (const bf16_t*)W13, (bf16_t*)dX_perm, offsets, w.tile_start, E, N,
+                         2 * f, d, nt, G);
     }
     const int pblocks = (w.ldT + 63) / 64;
     hipLaunchKernelGGL(slot_transpose, dim3(pblocks, d / 64), dim3(256), 0, st, Xb, row_map, c.T,
