@@ -72,6 +72,31 @@ __global__ __launch_bounds__(256) void combine_bwd_kernel(const TA* __restrict__
 // ds is formed here from w and dw (and written to ds_out).  Without ROUTER
 // idx, w, dw, Wr and ds_out are not touched (they may be null).  One
 // wavefront per token.
+// Eight consecutive values as FP32 (16-byte aligned loads), and stored.
+__device__ __forceinline__ void ld8(const float* p, float (&v)[8]) {
+  const f32x4 a = *(const f32x4*)p, b = *(const f32x4*)(p + 4);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = a[i];
+    v[4 + i] = b[i];
+  }
+}
+__device__ __forceinline__ void ld8(const bf16_t* p, float (&v)[8]) {
+  const bf16x8 a = *(const bf16x8*)p;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = (float)a[i];
+}
+__device__ __forceinline__ void st8(float* p, const float (&v)[8]) {
+  *(f32x4*)p = (f32x4){v[0], v[1], v[2], v[3]};
+  *(f32x4*)(p + 4) = (f32x4){v[4], v[5], v[6], v[7]};
+}
+__device__ __forceinline__ void st8(bf16_t* p, const float (&v)[8]) {
+  bf16x8 a;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = (bf16_t)v[i];
+  *(bf16x8*)p = a;
+}
+
 template <typename TA, bool ROUTER, typename TO>
 __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
     const TA* __restrict__ dXp, int T, int d, int k, int E, const int32_t* __restrict__ inv_map,
@@ -107,27 +132,32 @@ __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
         if (j == lane) ds_out[(size_t)t * k + j] = ds[j];
     }
   }
-  for (int c0 = lane * 4; c0 < d; c0 += 64 * 4) {
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  // eight columns per lane and step (d % 8 == 0; 16-byte loads and stores)
+  for (int c0 = lane * 8; c0 < d; c0 += 64 * 8) {
+    float acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
 #pragma unroll
     for (int j = 0; j < MOE_MAX_K; ++j) {
       if (j < k) {
+        float v[8];
+        ld8(dXp + (size_t)slots[j] * d + c0, v);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = acc[i] + ActIO<TA>::ld(dXp, (size_t)slots[j] * d + c0 + i);
+        for (int i = 0; i < 8; ++i) acc[i] = acc[i] + v[i];
       }
     }
     if (ROUTER) {
 #pragma unroll
       for (int j = 0; j < MOE_MAX_K; ++j) {
         if (j < k) {
+          float v[8];
+          ld8(Wr + (size_t)ex[j] * d + c0, v);
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            acc[i] = __builtin_fmaf(ds[j], Wr[(size_t)ex[j] * d + c0 + i], acc[i]);
+          for (int i = 0; i < 8; ++i) acc[i] = __builtin_fmaf(ds[j], v[i], acc[i]);
         }
       }
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ActIO<TO>::st(dX, (size_t)t * d + c0 + i, acc[i]);
+    st8(dX + (size_t)t * d + c0, acc);
   }
 }
 
@@ -304,7 +334,7 @@ extern "C" moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const flo
                   !dX_perm || !dX))
     return MOE_EINVAL;
   if (!aligned(X, 16) || !aligned(dX_perm, 16) || !aligned(dX, 16) || !aligned(dWr, 4) ||
-      !aligned(dbr, 4) || !aligned(Wr, 4))
+      !aligned(dbr, 4) || !aligned(Wr, 16))
     return MOE_EINVAL;
   if (ws_bytes < route_bwd_ws_bytes(c) || !ws) return MOE_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
