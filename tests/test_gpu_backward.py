@@ -159,6 +159,28 @@ def test_dispatch_backward_is_a_gather_sum():
     assert_close(dX.cpu().numpy(), exp, 1e-6, "dX")
 
 
+@pytest.mark.parametrize("act", ["f32", "bf16"])
+def test_dispatch_backward_sums_in_slot_order_exactly(act):
+    """moe_dispatch_bwd: dX[t] = sum over j in order of dX_perm[inv_map[t, j]],
+    FP32 additions, bit for bit against the same additions on the host (FP32
+    and BF16 slot gradients; d = 136 is not a multiple of 64 lanes x 8)."""
+    T, d, E, k = 333, 136, 5, 3
+    shape = synth.MoEShape("dbwd", T=T, d=d, E=E, k=k, f=128, zipf=1.1, act=act, w=act)
+    cfg = cfg_for(shape)
+    rng = np.random.Generator(np.random.PCG64(77))
+    g = rng.standard_normal((T * k, d)).astype(np.float32)
+    inv = rng.permutation(T * k).astype(np.int32).reshape(T, k)
+    dt = torch.float32 if act == "f32" else torch.bfloat16
+    dXp = torch.from_numpy(g).to(dt).cuda()
+    dX = layer.dispatch_bwd(cfg, dXp, torch.from_numpy(inv).cuda())
+    torch.cuda.synchronize()
+    gv = dXp.float().cpu().numpy()
+    ref = np.zeros((T, d), np.float32)
+    for j in range(k):
+        ref = (ref + gv[inv[:, j]]).astype(np.float32)
+    np.testing.assert_array_equal(dX.cpu().numpy(), ref)
+
+
 def test_autograd_function_matches_oracle():
     shape = BWD
     inp = synth.make_inputs(shape, 34)
