@@ -270,8 +270,10 @@ def fwd_bwd(config, args, dev, torch, L, layer, synth):
                          "combine", "combine_bwd", "ffn_bwd", "route_bwd"))
     N, d, f = shape.N, shape.d, shape.f
     if "ffn_bwd" in st:
-        st["ffn_bwd"].update(flop=16.0 * N * d * f,
-                             tflops=16.0 * N * d * f / (st["ffn_bwd"]["ms"] * 1e9))
+        # the autograd layer keeps GEMM 1's pre-activations, so the expert
+        # backward multiplies U = dY W2, dX_perm, dW13 and dW2: 12 N d f
+        st["ffn_bwd"].update(flop=12.0 * N * d * f,
+                             tflops=12.0 * N * d * f / (st["ffn_bwd"]["ms"] * 1e9))
     return {"workload": f"moe-{shape.name}", "T": shape.T, "d_model": d, "E": shape.E,
             "top_k": shape.k, "d_ff": f, "steps": steps, "ms_per_step": ms,
             "tokens_per_s": shape.T / (ms / 1e3), "stages": st}
