@@ -44,6 +44,23 @@ overshot by up to one increment; the next stage climbs back with a smaller
 increment, so the certificate gap shrinks with each stage.  The iteration
 count reported is the sum over the stages.
 
+Variant rule, projected dual subgradient ("subgrad", reading stated here):
+prices start at zero and every expert's price moves along the negative
+subgradient of D, whose e-th component at p is C - load_e (load under the
+top-k ranking of step 1), projected back onto p >= 0.  Step 1 and the stop
+test of step 2 are those above; step 3 becomes, for every expert,
+
+      eta = fl32(eta0 / fl32(sqrt(fl32(iters + 1)))),  eta0 = fl32(256 * eps)
+      g_e = fl32(fl32(load_e - C) / fl32(C))
+      x   = fl32(p_e + fl32(eta * g_e)),  p_e = (x > 0 ? x : +0).
+
+The step is relative to the capacity and shrinks as 1/sqrt of the update
+count (the classic diminishing step of subgradient methods); eta0 is a
+quarter of the score standard deviation.  Prices of underloaded experts fall
+back towards zero, so unlike the ascending rule the prices are not
+monotone; the iteration can end at max_iters with some expert over
+capacity, and the repair then places the overflow.
+
 The routing returned is S_t of the last ranking, in rank order.  Gate
 weights are the softmax of the raw logits over the k chosen experts.  If the
 final routing still overloads an expert, ``enforce_capacity`` repairs it.
@@ -204,6 +221,35 @@ def acp_prices(s32, k, C, max_iters=50, p0=None, eps=None):
         iters += 1
 
 
+SUBGRAD_ETA0 = F32(256.0)  # subgradient step: eta0 = 256 increments
+
+
+def subgrad_prices(s32, k, C, max_iters=50, eps=None):
+    """Projected dual subgradient iteration (module header, "subgrad").
+
+    Returns dict(p, iters, converged, sel, load, eps)."""
+    s32 = np.ascontiguousarray(s32, dtype=F32)
+    T, E = s32.shape
+    p = np.zeros(E, dtype=F32)
+    if eps is None:
+        eps = price_eps(s32)
+    eps = F32(eps)
+    eta0 = F32(SUBGRAD_ETA0 * eps)
+    iters = 0
+    while True:
+        sel, _, _, _ = topk_under_prices(s32, p, k)
+        load = loads(sel, E)
+        if np.all(load <= C):
+            return dict(p=p, iters=iters, converged=True, sel=sel, load=load, eps=eps)
+        if iters >= max_iters:
+            return dict(p=p, iters=iters, converged=False, sel=sel, load=load, eps=eps)
+        eta = F32(eta0 / F32(np.sqrt(F32(iters + 1))))
+        g = (load - C).astype(F32) / F32(C)
+        x = (p + (eta * g).astype(F32)).astype(F32)
+        p = np.where(x > 0, x, F32(0.0)).astype(F32)
+        iters += 1
+
+
 SCALED_BACK = F32(4.0)    # restart: prices lowered by this many increments
 SCALED_SHRINK = F32(8.0)  # and the increment divided by this
 
@@ -310,8 +356,8 @@ def route(s32, k, C, max_iters=50, p0=None, mode="acp", stages=0):
     """The whole routing step on FP32 logits.
 
     mode: "none" (p = 0, no update), "acp" (from p0 or 0), "given" (p = p0,
-    no update).  stages > 0 (with "acp") runs the epsilon-scaled restarts
-    after the update.  Returns dict with sel, w (FP64), load, p, iters,
+    no update), "subgrad" (the projected dual subgradient from 0).  stages
+    > 0 (with "acp") runs the epsilon-scaled restarts after the update.  Returns dict with sel, w (FP64), load, p, iters,
     converged, enforced, status, eps, sigma."""
     s32 = np.ascontiguousarray(s32, dtype=F32)
     T, E = s32.shape
@@ -336,6 +382,10 @@ def route(s32, k, C, max_iters=50, p0=None, mode="acp", stages=0):
         else:
             r = acp_prices(s32, k, C, max_iters, p, eps)
         res["eps"] = r["eps"]  # the increment of the last stage
+        p, sel, load = r["p"], r["sel"], r["load"]
+        res["iters"], res["converged"] = r["iters"], r["converged"]
+    elif mode == "subgrad":
+        r = subgrad_prices(s32, k, C, max_iters, eps)
         p, sel, load = r["p"], r["sel"], r["load"]
         res["iters"], res["converged"] = r["iters"], r["converged"]
     else:
