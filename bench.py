@@ -57,6 +57,8 @@ def parse():
                     help="compare every precision form (tokens/s, error vs FP64) at one shape")
     ap.add_argument("--mx", type=int, default=1,
                     help="also time the MX-expert forms (e4m3, e2m3, e2m1) at the FP8 shape")
+    ap.add_argument("--rules", type=int, default=1,
+                    help="compare the price rules (clearing price, restarts, subgradient)")
     ap.add_argument("--price-batches", type=int, default=10000,
                     help="training batches of the price network (0 = skip that part)")
     ap.add_argument("--price-steps", type=int, default=4000)
@@ -211,6 +213,7 @@ def main():
             "unit": "TFLOP/s", "frac": ach / BF16_PEAK_TFLOPS, "traffic": traffic,
             "algorithmic_flop_per_launch": gemm1_flop}
 
+    rules = price_rules(args, cfg, out["logits"], torch, L) if args.rules else None
     fb = None
     if args.bwd_config:
         fb = fwd_bwd(args.bwd_config, args, dev, torch, L, layer, synth)
@@ -240,7 +243,8 @@ def main():
                    "parallelism": "single-gpu"},
         "price_iters": int(info[0]), "converged": bool(info[1]),
         "slots_per_s": value * shape.k, "wall_s": wall,
-        "roofline": roof, "stages": stages, "fwd_bwd": fb, "fp8": f8, "mx": mxr, "forms": forms,
+        "roofline": roof, "stages": stages, "price_rules": rules, "fwd_bwd": fb, "fp8": f8,
+        "mx": mxr, "forms": forms,
         "learned_price": lp,
         "cpu_baseline": cpu,
     }
@@ -280,6 +284,35 @@ def fwd_bwd(config, args, dev, torch, L, layer, synth):
 
 
 MX_PEAK_TFLOPS = {"e4m3": 5000.0, "e2m3": 10100.0, "e2m1": 10100.0}
+
+
+def price_rules(args, cfg, logits, torch, L):
+    """The price rules on the forward workload's own logits: the ascending
+    clearing price, the same with three epsilon-scaled restarts, and the
+    projected dual subgradient (all with at most 50 updates per run).  Per
+    rule: routing time (logits to routing, the repair included), updates,
+    whether the last ranking met every capacity, whether the repair ran,
+    and the certificate's relative gap (D(p) - sum s x) / |D(p)|."""
+    from paper_2606_17065_amd import price as P
+    res = {}
+    for name, mode, stages in (("clearing_price", L.MOE_PRICE_ACP, 0),
+                               ("clearing_price_3_restarts", L.MOE_PRICE_ACP, 3),
+                               ("subgradient", L.MOE_PRICE_SUBGRAD, 0)):
+        c = L.make_cfg(cfg.T, cfg.d, cfg.E, cfg.k, cfg.d_ff, cfg.capacity, 50, cfg.act, cfg.w,
+                       mode, 0.9, stages)
+        holder = {}
+
+        def run():
+            holder["r"] = P.route_logits(c, logits)
+
+        ms, _ = timed(run, 10, 2, torch, L)
+        r = holder["r"]
+        cert = P.certify(c, logits, r["price"], r["idx"]).cpu().numpy()
+        info = r["info"].cpu().numpy()
+        res[name] = {"ms": ms / 10, "iters": int(info[L.INFO_ITERS]),
+                     "converged": bool(info[L.INFO_CONVERGED]),
+                     "repaired": bool(info[L.INFO_REPAIRED]), "gap_rel": float(cert[2])}
+    return res
 
 
 def forms_comparison(args, dev, torch, L, layer, synth):

@@ -72,18 +72,19 @@ typedef enum {
   MOE_PRICE_NONE = 0,  /* p = 0: plain top-k (then capacity repair)        */
   MOE_PRICE_ACP = 1,   /* ascending clearing price from p = 0              */
   MOE_PRICE_GIVEN = 2, /* p = price[] as passed, no update                  */
-  MOE_PRICE_WARM = 3   /* ascending clearing price from p = warm_gamma*price */
+  MOE_PRICE_WARM = 3,  /* ascending clearing price from p = warm_gamma*price */
+  MOE_PRICE_SUBGRAD = 4 /* projected dual subgradient from p = 0            */
 } moe_price_mode;
 
 typedef struct {
   int32_t T, d, E, k, d_ff;
   int32_t capacity;   /* C */
-  int32_t max_iters;  /* cap on price updates (MOE_PRICE_ACP / _WARM) */
+  int32_t max_iters;  /* cap on price updates (MOE_PRICE_ACP / _WARM / _SUBGRAD) */
   int32_t act;        /* moe_dtype of activations: MOE_F32 or MOE_BF16 */
   int32_t w;          /* moe_dtype of expert weights */
   int32_t price_mode; /* moe_price_mode */
   float warm_gamma;   /* MOE_PRICE_WARM scale of the given prices */
-  int32_t price_stages; /* epsilon-scaled restarts after the update (0..8; 0 = none) */
+  int32_t price_stages; /* epsilon-scaled restarts after the ascending update (0..8; 0 = none) */
 } moe_cfg;
 
 /* info[] layout written by moe_route (device int32[8]). */
@@ -115,6 +116,15 @@ moe_status moe_workspace_bytes(const moe_cfg* cfg /* host */, size_t* bytes /* h
  *       overloaded e, q = (C+1)-th largest of the margins
  *       m_t = s_te - (e in S_t ? kappa2_t : kappa1_t) and
  *       p_e = max(p_e, nextafter(q, +inf) + eps).
+ *   projected dual subgradient (price-rule variant, MOE_PRICE_SUBGRAD):
+ *     the same ranking and stop test; the update moves every price along
+ *     the negative subgradient of the dual, C - load_e, scaled by the
+ *     capacity and projected onto p >= 0:
+ *       eta = fl32(eta0 / fl32(sqrt(fl32(u + 1)))), eta0 = fl32(256 * eps),
+ *       g_e = fl32(fl32(load_e - C) / fl32(C)), x = fl32(p_e + fl32(eta g_e)),
+ *       p_e = x > 0 ? x : +0                  (u = updates so far)
+ *     It can stop at max_iters with an expert over capacity (the repair
+ *     then places the overflow); cfg.price_stages does not apply.
  *   epsilon-scaled restarts (price-rule variant, cfg.price_stages = R > 0,
  *     with max_iters > 0): after the update, while it ended converged with
  *     some expert priced above zero and loaded below C (a nonzero

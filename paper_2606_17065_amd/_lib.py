@@ -23,7 +23,7 @@ MOE_ECAPACITY = -7
 
 MOE_F32, MOE_BF16, MOE_FP8E4M3 = 0, 1, 2
 MOE_MXFP8E4M3, MOE_MXFP6E2M3, MOE_MXFP4E2M1 = 3, 4, 5
-MOE_PRICE_NONE, MOE_PRICE_ACP, MOE_PRICE_GIVEN, MOE_PRICE_WARM = 0, 1, 2, 3
+MOE_PRICE_NONE, MOE_PRICE_ACP, MOE_PRICE_GIVEN, MOE_PRICE_WARM, MOE_PRICE_SUBGRAD = 0, 1, 2, 3, 4
 
 INFO_ITERS, INFO_CONVERGED, INFO_OVERFLOW, INFO_STATUS = 0, 1, 2, 3
 INFO_ROUNDS, INFO_SIGMA, INFO_EPS, INFO_REPAIRED = 4, 5, 6, 7

@@ -30,7 +30,8 @@ __global__ void route_init(int32_t* state, int E, float* price, int mode, float 
   int tid = threadIdx.x;
   if (tid < ST_LEN) state[tid] = 0;
   for (int e = tid; e < E; e += blockDim.x) {
-    if (mode == MOE_PRICE_NONE || mode == MOE_PRICE_ACP) price[e] = 0.0f;
+    if (mode == MOE_PRICE_NONE || mode == MOE_PRICE_ACP || mode == MOE_PRICE_SUBGRAD)
+      price[e] = 0.0f;
     else if (mode == MOE_PRICE_WARM) price[e] = gamma * price[e];
   }
 }
@@ -821,10 +822,12 @@ __device__ __forceinline__ void select_update(const uint32_t* __restrict__ col,
   }
 }
 
+// subgrad != 0: the projected dual subgradient rule instead (every block
+// moves its expert's price by the capacity-relative excess, no selection).
 __global__ __launch_bounds__(SEL_THREADS) void acp_select(
     const uint32_t* __restrict__ mT, float* __restrict__ price, int T, int E, int C, int it,
     int max_iters, int nblk, const int32_t* __restrict__ cnt, int32_t* __restrict__ state,
-    int32_t* __restrict__ load_out) {
+    int32_t* __restrict__ load_out, int subgrad) {
   __shared__ SelShared sh;
   __shared__ int ld[MOE_MAX_E];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -892,6 +895,15 @@ __global__ __launch_bounds__(SEL_THREADS) void acp_select(
           state[ST_DONE] = 1;
         }
       }
+    }
+    return;
+  }
+  if (subgrad) {
+    if (tid == 0) {
+      const float eta = (256.0f * eps) / sqrtf((float)(it + 1));
+      const float g = (float)(ld[e] - C) / (float)C;
+      const float x = p_e + eta * g;
+      price[e] = x > 0.0f ? x : 0.0f;
     }
     return;
   }
@@ -1218,7 +1230,7 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
   const int per = (E + RW - 1) / RW;
   // one ranking and one update kernel per iteration, each exiting at once
   // after the loop has stopped; epsilon-scaled restarts repeat the loop
-  const int stages = max_iters > 0 ? c.price_stages : 0;
+  const int stages = max_iters > 0 && c.price_mode != MOE_PRICE_SUBGRAD ? c.price_stages : 0;
   for (int stage = 0; stage <= stages; ++stage) {
   if (stage > 0)
     hipLaunchKernelGGL(scaled_restart, dim3(1), dim3(256), 0, st, ws.state, price, load, E, C);
@@ -1240,7 +1252,8 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
       hipLaunchKernelGGL(HIP_KERNEL_NAME(acp_rank<L, 64, TG, RW>), dim3(nblk), rb, 0, st, ws.sT,
                          price, T, E, k, ws.state, ws.mT, idx, ws.cnt);
     hipLaunchKernelGGL(acp_select, dim3(E), dim3(SEL_THREADS), 0, st, ws.mT, price, T, E, C, it,
-                       max_iters, nblk, ws.cnt, ws.state, load);
+                       max_iters, nblk, ws.cnt, ws.state, load,
+                       (int)(c.price_mode == MOE_PRICE_SUBGRAD));
   }
   }
   hipLaunchKernelGGL(route_weights, dim3((T + 255) / 256), dim3(256), 0, st, logits, idx, T, E, k,
@@ -1297,7 +1310,7 @@ moe_status route_check(const moe_cfg* cfg, const float* logits, float* price, in
   moe_status stc = check_cfg_shape(cfg);
   if (stc != MOE_OK) return stc;
   const moe_cfg& c = *cfg;
-  if (c.price_mode < MOE_PRICE_NONE || c.price_mode > MOE_PRICE_WARM) return MOE_EINVAL;
+  if (c.price_mode < MOE_PRICE_NONE || c.price_mode > MOE_PRICE_SUBGRAD) return MOE_EINVAL;
   if (c.max_iters < 0) return MOE_EINVAL;
   if (!price || !load || !info) return MOE_EINVAL;
   if (c.T > 0 && (!logits || !topk_idx || !topk_w)) return MOE_EINVAL;
@@ -1382,8 +1395,10 @@ moe_status route_from_scores(const moe_cfg& c, const RouteWs& w, const float* lo
   hipLaunchKernelGGL(score_partials, dim3(nb), dim3(SIG_BLOCK), 0, st, w.sT, c.T, c.E, w.part);
   hipLaunchKernelGGL(score_sigma, dim3(1), dim3(SIG_BLOCK), 0, st, w.part, nb,
                      (double)c.T * (double)c.E, w.state);
-  const int iters =
-      (c.price_mode == MOE_PRICE_ACP || c.price_mode == MOE_PRICE_WARM) ? c.max_iters : 0;
+  const int iters = (c.price_mode == MOE_PRICE_ACP || c.price_mode == MOE_PRICE_WARM ||
+                     c.price_mode == MOE_PRICE_SUBGRAD)
+                        ? c.max_iters
+                        : 0;
   PROF_BEGIN("price_loop", st);
   launch_loop(c, w, logits, price, topk_idx, topk_w, load, iters, st);
   PROF_END("price_loop", st);

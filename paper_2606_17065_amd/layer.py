@@ -50,7 +50,7 @@ def _fresh_price(cfg, dev):
     """Price buffer when the caller gives none: the clearing-price and the
     no-price modes start from p = 0 inside the routing kernels, so the
     buffer needs no fill; given and warm-started prices read it (zeros)."""
-    if cfg.price_mode in (L.MOE_PRICE_ACP, L.MOE_PRICE_NONE):
+    if cfg.price_mode in (L.MOE_PRICE_ACP, L.MOE_PRICE_NONE, L.MOE_PRICE_SUBGRAD):
         return torch.empty(cfg.E, dtype=torch.float32, device=dev)
     return torch.zeros(cfg.E, dtype=torch.float32, device=dev)
 

@@ -11,7 +11,7 @@ from paper_2606_17065_amd import synth
 F32 = np.float32
 
 MODE_NAME = {L.MOE_PRICE_NONE: "none", L.MOE_PRICE_ACP: "acp", L.MOE_PRICE_GIVEN: "given",
-             L.MOE_PRICE_WARM: "acp"}
+             L.MOE_PRICE_WARM: "acp", L.MOE_PRICE_SUBGRAD: "subgrad"}
 
 
 def cfg_for(shape: synth.MoEShape, price_mode=L.MOE_PRICE_ACP, max_iters=None, capacity=None,
@@ -98,8 +98,10 @@ def replica_route(cfg, logits32, price_in=None):
         p0 = np.asarray(price_in, F32)
     elif mode == L.MOE_PRICE_WARM:
         p0 = (F32(cfg.warm_gamma) * np.asarray(price_in, F32)).astype(F32)
-    iters = cfg.max_iters if mode in (L.MOE_PRICE_ACP, L.MOE_PRICE_WARM) else 0
-    return R.route(logits32, cfg.k, cfg.capacity, iters, p0, MODE_NAME[mode], cfg.price_stages)
+    iters = cfg.max_iters if mode in (L.MOE_PRICE_ACP, L.MOE_PRICE_WARM,
+                                      L.MOE_PRICE_SUBGRAD) else 0
+    stages = cfg.price_stages if mode != L.MOE_PRICE_SUBGRAD else 0
+    return R.route(logits32, cfg.k, cfg.capacity, iters, p0, MODE_NAME[mode], stages)
 
 
 def assert_route_matches(cfg, r_gpu, ref):

@@ -79,7 +79,7 @@ def test_entry_points_reject_bad_arguments_on_the_host():
     with pytest.raises(L.MoEError) as e:
         L.moe_route(cfg, fake, fake, fake, fake, fake, fake, fake, fake, fake, fake, 16, None)
     assert e.value.status == L.MOE_EWORKSPACE
-    bad = _cfg(price_mode=9)
+    bad = _cfg(price_mode=L.MOE_PRICE_SUBGRAD + 1)
     with pytest.raises(L.MoEError) as e:
         L.moe_route(bad, fake, fake, fake, fake, fake, fake, fake, fake, fake, fake, 1 << 30, None)
     assert e.value.status == L.MOE_EINVAL
