@@ -605,7 +605,8 @@ __global__ __launch_bounds__(256) void route_weights(const float* __restrict__ l
 // r-th largest (1-based) key among the items i in [0, n) for which get(i,
 // key) is true.  Digits of 11, 11 and 10 bits, a 2048-bin LDS histogram
 // per pass.  Requires 1 <= r <= number of such items.  Returns the key and
-// writes the number of items with a strictly larger key to *greater.
+// writes the number of items with a strictly larger key to *greater and the
+// number of items with exactly that key to *ties.
 
 struct SelScratch {
   uint32_t hist[2048];
@@ -614,7 +615,8 @@ struct SelScratch {
 };
 
 template <typename Get>
-__device__ uint32_t block_select_rth(int n, int r, Get get, SelScratch& sc, int* greater) {
+__device__ uint32_t block_select_rth(int n, int r, Get get, SelScratch& sc, int* greater,
+                                     int* ties) {
   const int tid = threadIdx.x, bd = blockDim.x;
   uint32_t prefix = 0, mask = 0;
   int rr = r;
@@ -655,6 +657,7 @@ __device__ uint32_t block_select_rth(int n, int r, Get get, SelScratch& sc, int*
     __syncthreads();
     const int dsel = sc.pick_digit;
     const uint32_t above = sc.pick_above;
+    if (pass == 2) *ties = (int)sc.hist[dsel];  // the last digit's bin: the equal keys
     __syncthreads();
     rr -= (int)above;
     prefix |= (uint32_t)dsel << sh;
@@ -1007,7 +1010,7 @@ __global__ __launch_bounds__(REP_THREADS) void capacity_repair(
   // 1) overloaded experts keep their C best holders (key desc, token asc)
   for (int e = 0; e < E; ++e) {
     if (S.load[e] <= C) continue;
-    int greater;
+    int greater, ties;
     uint32_t kstar = block_select_rth(
         T, C,
         [&](int t, uint32_t& key) {
@@ -1015,8 +1018,22 @@ __global__ __launch_bounds__(REP_THREADS) void capacity_repair(
           key = keyof(t, e);
           return true;
         },
-        S.sc, &greater);
+        S.sc, &greater, &ties);
     const int need = C - greater;
+    if (ties == need) {
+      // every holder with the C-th key stays: no order among equal keys is
+      // needed, each token is decided by its own key
+      for (int t = tid; t < T; t += bd) {
+        if (has(held, t, e) && keyof(t, e) < kstar) {
+          held[(size_t)t * W + (e >> 5)] &= ~(1u << (e & 31));
+          missing[t] += 1;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) S.load[e] = C;
+      __syncthreads();
+      continue;
+    }
     int run = 0;
     for (int t0 = 0; t0 < T; t0 += bd) {
       const int t = t0 + tid;
@@ -1074,7 +1091,7 @@ __global__ __launch_bounds__(REP_THREADS) void capacity_repair(
       if (P == 0) continue;
       const int room = C - S.load[e];
       uint32_t kstar = 0;
-      int need = 0;
+      int need = 0, ties = 0;
       bool all = P <= room;
       if (!all && room > 0) {
         int greater;
@@ -1085,8 +1102,26 @@ __global__ __launch_bounds__(REP_THREADS) void capacity_repair(
               key = keyof(t, e);
               return true;
             },
-            S.sc, &greater);
+            S.sc, &greater, &ties);
         need = room - greater;
+      }
+      if (all || room <= 0 || ties == need) {
+        // every proposal accepted, none, or all at or above the room-th key
+        // (the equal keys fit): each token is decided by its own key
+        int accepted = 0;
+        for (int t = tid; t < T; t += bd) {
+          if (!has(prop, t, e)) continue;
+          prop[(size_t)t * W + (e >> 5)] &= ~(1u << (e & 31));
+          if (room > 0 && (all || keyof(t, e) >= kstar)) {
+            held[(size_t)t * W + (e >> 5)] |= 1u << (e & 31);
+            missing[t] -= 1;
+            ++accepted;
+          }
+        }
+        const int acc_tot = block_sum(accepted, S.red);
+        if (tid == 0) S.load[e] += acc_tot;
+        __syncthreads();
+        continue;
       }
       int run = 0, accepted = 0;
       for (int t0 = 0; t0 < T; t0 += bd) {

@@ -222,6 +222,25 @@ def test_route_logits_bit_exact_with_tied_logits(T, E, k, seed):
     assert_route_matches(cfg, r, ref)
 
 
+# the capacity repair on logits with exact ties (grid of 0.25): evictions
+# and acceptances where equal keys straddle the capacity take the ordered
+# path (token order among equal keys), the others decide each token by its
+# own key; plain top-k (cap 0), one update, and the subgradient rule
+@pytest.mark.parametrize("T,E,k,seed,mode,cap", [
+    (1000, 64, 8, 87, L.MOE_PRICE_ACP, 0), (3000, 16, 2, 88, L.MOE_PRICE_ACP, 1),
+    (1200, 32, 4, 89, L.MOE_PRICE_SUBGRAD, 3), (700, 24, 3, 90, L.MOE_PRICE_NONE, 0)])
+def test_capacity_repair_bit_exact_with_tied_logits(T, E, k, seed, mode, cap):
+    s = (np.round(synth.make_logits(T, E, 1.3, seed) * 4.0) / 4.0).astype(np.float32)
+    sd = torch.from_numpy(s).cuda()
+    cfg = _cfg(T, E, k, mode=mode, max_iters=cap)
+    r = P.route_logits(cfg, sd)
+    torch.cuda.synchronize()
+    ref = replica_route(cfg, s)
+    assert ref["status"] == R.OK and ref["enforced"]
+    assert_route_matches(cfg, r, ref)
+    assert int(r["info"][L.INFO_ROUNDS]) == ref["rounds"]
+
+
 # every instantiation of the ranking kernel: top-k lists padded to 3, 5, 9
 # or 17 entries (k = 2, 4, 8, 10), eight expert ranges for k <= 8 and four
 # above, and each register cache of 4, 8, 16, 32 or 64 logits per lane (the
