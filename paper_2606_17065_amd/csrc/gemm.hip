@@ -91,6 +91,16 @@ __device__ __forceinline__ bool find_tile_grouped(const int32_t* __restrict__ ti
   return rows > 0;
 }
 
+// Logical tile of block b: XCD b % 8 takes the b / 8-th tile of its run of
+// ceil(tiles / 8) consecutive tiles, so the 8 XCDs get equal shares of the
+// tiles that exist however far the grid (sized for the worst-case routing)
+// exceeds them.  Blocks past the end get an index find_tile_grouped rejects.
+__device__ __forceinline__ int xcd_tile(const int32_t* __restrict__ tile_start, int E,
+                                        int n_tiles, int grid_total, int b) {
+  const int per = min((tile_start[E] * n_tiles + 7) >> 3, grid_total >> 3);
+  const int j = b >> 3;
+  return j < per ? (b & 7) * per + j : 0x7fffffff;
+}
 
 // ------------------------------------------------------- BF16 MFMA, 256x128
 // Macro tile 256 token rows x 128 weight rows, 4 wavefronts (2 x 2) each
@@ -112,7 +122,9 @@ __device__ __forceinline__ bool find_tile_grouped(const int32_t* __restrict__ ti
 // of the same 32 outputs.  Rows of a partial row tile load a clamped
 // (valid) row; their results are never stored.
 // Blocks are remapped so that each XCD (the hardware deals blocks to the 8
-// XCDs round-robin) walks a contiguous run of the grouped tile order.
+// XCDs round-robin) walks a contiguous run of the grouped tile order; the
+// runs split the tiles that exist (counted on the device), not the grid,
+// which is sized for the worst case of the routing.
 
 constexpr int GBM = 256, GBN = 128, GBK = 32, NSTAGE = 3;
 constexpr int STAGE_A = GBM * GBK * 2;   // bytes of the token operand in a stage
@@ -257,8 +269,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_big(
   constexpr bool PAIRED = EPI != EPI_PLAIN;  // B-tile holds W1/W3 halves
   __shared__ __attribute__((aligned(1024))) char lds[DMA_LDS];
   const int b = blockIdx.x;
-  const int per = grid_total >> 3;
-  const int Lt = (b & 7) * per + (b >> 3);
+  const int Lt = xcd_tile(tile_start, E, n_tiles, grid_total, b);
   int e, row0, rows, nt;
   if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -433,8 +444,7 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide(
   constexpr bool PAIRED = EPI != EPI_PLAIN;
   __shared__ __attribute__((aligned(1024))) char lds[XLDS];
   const int b = blockIdx.x;
-  const int per = grid_total >> 3;
-  const int Lt = (b & 7) * per + (b >> 3);
+  const int Lt = xcd_tile(tile_start, E, n_tiles, grid_total, b);
   int e, row0, rows, nt;
   if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -570,8 +580,7 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_bf16_wide_bkm(
   typedef __attribute__((address_space(3))) void lds_void;
   __shared__ __attribute__((aligned(1024))) char lds[XLDS];
   const int b = blockIdx.x;
-  const int per = grid_total >> 3;
-  const int Lt = (b & 7) * per + (b >> 3);
+  const int Lt = xcd_tile(tile_start, E, n_tiles, grid_total, b);
   int e, row0, rows, nt;
   if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -797,8 +806,7 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   constexpr bool PAIRED = EPI == EPI_SWIGLU;
   __shared__ __attribute__((aligned(1024))) char lds[F8_LDS];
   const int b = blockIdx.x;
-  const int per = grid_total >> 3;
-  const int Lt = (b & 7) * per + (b >> 3);
+  const int Lt = xcd_tile(tile_start, E, n_tiles, grid_total, b);
   int e, row0, rows, nt;
   if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1148,8 +1156,7 @@ __global__ __launch_bounds__(64 * XW, 1) void gemm_mx_wide(
   constexpr int BPS = KPS / 32;              // scale blocks per stage
   __shared__ __attribute__((aligned(1024))) char lds[XLDS];
   const int b = blockIdx.x;
-  const int per = grid_total >> 3;
-  const int Lt = (b & 7) * per + (b >> 3);
+  const int Lt = xcd_tile(tile_start, E, n_tiles, grid_total, b);
   int e, row0, rows, nt;
   if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
