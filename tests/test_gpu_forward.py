@@ -236,13 +236,16 @@ def test_layer_forward_tiny_batches(T, base):
     assert_close(r["out"].float().cpu().numpy(), ref["out"], 1.5e-2, "out")
 
 
-def test_fused_gather_matches_separate_permute():
+@pytest.mark.parametrize("which", ["bigtile", "scale"])
+def test_fused_gather_matches_separate_permute(which):
     """The first expert product reading X through row_map gives the same
-    bits as the explicit permute followed by the product."""
-    shape = BIG_TILES
+    bits as the explicit permute followed by the product, at a small shape
+    and at 16384 tokens (E = 64, top-8), whose 256-row tiles fill the XCDs'
+    runs unevenly."""
+    shape = BIG_TILES if which == "bigtile" else synth.SHAPES[2]
     cfg = cfg_for(shape)
     assert layer.gather_fused(cfg)
-    inp = synth.make_inputs(shape, 23)
+    inp = synth.make_inputs(shape, 23 if which == "bigtile" else 2)
     d, _ = device_inputs(shape, inp, host_weights=False)
     a = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"], fuse=True)
     b = layer.forward(cfg, d["X"], d["Wr"], d["br"], d["W13"], d["W2"], fuse=False)
