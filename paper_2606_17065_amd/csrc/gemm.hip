@@ -775,9 +775,9 @@ __global__ __launch_bounds__(256) void fp8_quant_tiles(const TA* __restrict__ X,
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-// FP8 grouped GEMM with per-block scales: A codes [N,K] with scales
-// [N, K/128] (1 x 128 blocks), B codes [E, Brows, K] with scales
-// [E, Brows/128, K/128] (128 x 128 blocks).  Tiles and tile order as
+// FP8 grouped GEMM 2 with per-block scales: A codes [N,K] (h) with scales
+// [N, K/128] (1 x 128 blocks), B codes [E, Ncols, K] with scales
+// [E, Ncols/128, K/128] (128 x 128 blocks).  Tiles and tile order as
 // gemm_bf16_big (256 tokens x 128 weight rows, 4 wavefronts of 128 x 64);
 // one stage is one 128-wide K block: 128-byte LDS rows (a full cache line
 // per row) with the chunk swizzle physical = logical ^ ((row >> 1) & 7) of
@@ -786,24 +786,19 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 // v_mfma_f32_32x32x64_f8f6f4 accumulate the block on its own, which is then
 // promoted into the FP32 result: acc += partial * (sa * sb).  A lane holds
 // one token row of each tile, so sa is one value per row tile and sb one
-// value per column tile (wavefront-uniform).  GATHER: token row r of the A
-// operand (codes and scales) is row row_map[r] of the per-token arrays
-// (the permute fused into the operand DMA).
+// value per column tile (wavefront-uniform).
 constexpr int F8_STAGE_A = GBM * 128, F8_STAGE_B = GBN * 128;
 constexpr int F8_STAGE = F8_STAGE_A + F8_STAGE_B;
 constexpr int F8_NSTAGE = 3;
 constexpr int F8_LDS = F8_NSTAGE * F8_STAGE > EPI_BYTES ? F8_NSTAGE * F8_STAGE : EPI_BYTES;
 constexpr int F8_A_INS = GBM * 128 / 1024 / 4, F8_B_INS = GBN * 128 / 1024 / 4;
 
-template <int EPI, bool GATHER>
 __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
-    const fp8_t* __restrict__ A, const float* __restrict__ As,
-    const int32_t* __restrict__ row_map, int T, const fp8_t* __restrict__ B,
+    const fp8_t* __restrict__ A, const float* __restrict__ As, const fp8_t* __restrict__ B,
     const float* __restrict__ Bs, bf16_t* __restrict__ C, const int32_t* __restrict__ offsets,
-    const int32_t* __restrict__ tile_start, int E, int N, int K, int f, int Ncols, int n_tiles,
+    const int32_t* __restrict__ tile_start, int E, int N, int K, int Ncols, int n_tiles,
     int grid_total) {
   typedef __attribute__((address_space(3))) void lds_void;
-  constexpr bool PAIRED = EPI == EPI_SWIGLU;
   __shared__ __attribute__((aligned(1024))) char lds[F8_LDS];
   const int b = blockIdx.x;
   const int Lt = xcd_tile(tile_start, E, n_tiles, grid_total, b);
@@ -811,8 +806,8 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   if (!find_tile_grouped(tile_start, offsets, E, GBM, N, n_tiles, Lt, e, row0, rows, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = __builtin_amdgcn_readfirstlane(wv & 1);
-  const int n0 = nt * (PAIRED ? 64 : 128);
-  const int Brows_e = PAIRED ? 2 * f : Ncols;
+  const int n0 = nt * 128;
+  const int Brows_e = Ncols;
   const int nkb = K / 128;
   const fp8_t* Be = B + (size_t)e * Brows_e * K;
   // DMA: one instruction = 8 rows x 128 bytes; lane -> (row + lane/8,
@@ -823,15 +818,14 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   for (int i = 0; i < F8_A_INS; ++i) {
     const int R = wv * (GBM / 4) + i * 8 + (lane >> 3);
     const int c = (lane & 7) ^ ((R >> 1) & 7);
-    const int r = row0 + min(R, rows - 1);
-    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
+    const size_t arow = (size_t)(row0 + min(R, rows - 1));
     asrc[i] = A + arow * K + c * 16;
   }
 #pragma unroll
   for (int i = 0; i < F8_B_INS; ++i) {
     const int R = wv * (GBN / 4) + i * 8 + (lane >> 3);
     const int c = (lane & 7) ^ ((R >> 1) & 7);
-    const int wrow = PAIRED ? (R < 64 ? n0 + R : f + n0 + (R - 64)) : n0 + R;
+    const int wrow = n0 + R;
     bsrc[i] = Be + (size_t)wrow * K + c * 16;
   }
   const int fr = lane & 31, fh = lane >> 5;
@@ -844,7 +838,7 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const int R = (PAIRED ? (j == 0 ? wn * 32 : 64 + wn * 32) : wn * 64 + j * 32) + fr;
+    const int R = wn * 64 + j * 32 + fr;
     boff[j] = F8_STAGE_A + R * 128;
     bsw[j] = (R >> 1) & 7;
   }
@@ -853,12 +847,9 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   const float* sa_row[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int r = row0 + min(wm * 128 + i * 32 + fr, rows - 1);
-    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
-    sa_row[i] = As + arow * nkb;
+    sa_row[i] = As + (size_t)(row0 + min(wm * 128 + i * 32 + fr, rows - 1)) * nkb;
   }
-  const int wr0 = PAIRED ? n0 + wn * 32 : n0 + wn * 64;
-  const int wr1 = PAIRED ? f + n0 + wn * 32 : n0 + wn * 64 + 32;
+  const int wr0 = n0 + wn * 64, wr1 = n0 + wn * 64 + 32;
   const float* sb_row0 = Bs + ((size_t)e * (Brows_e / 128) + wr0 / 128) * nkb;
   const float* sb_row1 = Bs + ((size_t)e * (Brows_e / 128) + wr1 / 128) * nkb;
 
@@ -957,7 +948,7 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   WAIT_VM_LGKM0(0);
   stage_barrier();
 
-  constexpr int CS = EPI == EPI_SWIGLU ? 64 : 128;
+  constexpr int CS = 128;
   constexpr int CLD = CS + 8;
   bf16_t* Cs = (bf16_t*)lds;
   const int cbase = (lane >> 5) * 4;
@@ -965,17 +956,13 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   for (int i = 0; i < 4; ++i) {
     const int rl = wm * 128 + i * 32 + fr;
 #pragma unroll
-    for (int j = 0; j < (EPI == EPI_SWIGLU ? 1 : 2); ++j) {
-      const int col0 = EPI == EPI_SWIGLU ? wn * 32 : wn * 64 + j * 32;
+    for (int j = 0; j < 2; ++j) {
+      const int col0 = wn * 64 + j * 32;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         bf16x4 v;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float x = acc[i][j][g * 4 + q];
-          if (EPI == EPI_SWIGLU) v[q] = (bf16_t)(silu(x) * acc[i][1][g * 4 + q]);
-          else v[q] = (bf16_t)x;
-        }
+        for (int q = 0; q < 4; ++q) v[q] = (bf16_t)acc[i][j][g * 4 + q];
         *(bf16x4*)(Cs + rl * CLD + col0 + g * 8 + cbase) = v;
       }
     }
@@ -990,16 +977,248 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
   }
 }
 
-#define MOE_INST_F8(EPI, GATHER)                                                             \
-  template __global__ void gemm_fp8_big<EPI, GATHER>(                                        \
-      const fp8_t* __restrict__, const float* __restrict__, const int32_t* __restrict__, int, \
-      const fp8_t* __restrict__, const float* __restrict__, bf16_t* __restrict__,            \
-      const int32_t* __restrict__, const int32_t* __restrict__, int, int, int, int, int, int, \
-      int);
-MOE_INST_F8(EPI_SWIGLU, false)
-MOE_INST_F8(EPI_SWIGLU, true)
-MOE_INST_F8(EPI_PLAIN, false)
-#undef MOE_INST_F8
+
+// FP8 GEMM 1 + SwiGLU with h quantised in the epilogue: the tile is 128
+// token rows x 256 weight rows (W1 rows n0..n0+127 and the matching W3
+// rows), so each tile owns whole 1 x 128 blocks of h and writes its codes
+// and scales directly (no BF16 h round trip).  4 wavefronts, 2 (token
+// halves of 64) x 2 (h-column halves of 64); each holds 2 x 4 tiles of
+// 32x32 (W1 column tiles j = 0, 1 and their W3 partners j = 2, 3), the
+// same 128 + 128 accumulator registers as the 256 x 128 tile.  Stages,
+// swizzle and per-K-block promotion are those of gemm_fp8_big; h is the
+// BF16 rounding of silu(A) * B, quantised exactly as fp8_quant_rows does
+// (block amax, inverse, codes, scale).  A token row's amax meets in LDS:
+// a lane holds 32 of the row's 128 values, its partner lane (lane ^ 32) 32
+// more, the other column-half wavefront the rest.  GATHER: token row r of
+// the A operand (codes and scales) is row row_map[r] of the per-token
+// arrays (the permute fused into the operand DMA).
+constexpr int FQ_BM = 128, FQ_BN = 256;
+constexpr int FQ_STAGE_A = FQ_BM * 128, FQ_STAGE_B = FQ_BN * 128;
+constexpr int FQ_STAGE = FQ_STAGE_A + FQ_STAGE_B;
+constexpr int FQ_A_INS = FQ_BM * 128 / 1024 / 4, FQ_B_INS = FQ_BN * 128 / 1024 / 4;
+constexpr int FQ_CLD = 144;  // bytes per staged code row (16-byte aligned)
+static_assert(FQ_BM * FQ_CLD + 2 * FQ_BM * 4 <= F8_NSTAGE * FQ_STAGE, "epilogue fits the ring");
+
+template <bool GATHER>
+__global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
+    const fp8_t* __restrict__ A, const float* __restrict__ As,
+    const int32_t* __restrict__ row_map, int T, const fp8_t* __restrict__ B,
+    const float* __restrict__ Bs, fp8_t* __restrict__ Hq, float* __restrict__ Hs,
+    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start, int E, int N,
+    int K, int f, int n_tiles, int grid_total) {
+  typedef __attribute__((address_space(3))) void lds_void;
+  __shared__ __attribute__((aligned(1024))) char lds[F8_NSTAGE * FQ_STAGE];
+  const int b = blockIdx.x;
+  const int Lt = xcd_tile(tile_start, E, n_tiles, grid_total, b);
+  int e, row0, rows, nt;
+  if (!find_tile_grouped(tile_start, offsets, E, FQ_BM, N, n_tiles, Lt, e, row0, rows, nt))
+    return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = __builtin_amdgcn_readfirstlane(wv & 1);
+  const int n0 = nt * 128;
+  const int nkb = K / 128;
+  const fp8_t* Be = B + (size_t)e * 2 * f * K;
+  const fp8_t* asrc[FQ_A_INS];
+  const fp8_t* bsrc[FQ_B_INS];
+#pragma unroll
+  for (int i = 0; i < FQ_A_INS; ++i) {
+    const int R = wv * (FQ_BM / 4) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
+    const int r = row0 + min(R, rows - 1);
+    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
+    asrc[i] = A + arow * K + c * 16;
+  }
+#pragma unroll
+  for (int i = 0; i < FQ_B_INS; ++i) {
+    const int R = wv * (FQ_BN / 4) + i * 8 + (lane >> 3);
+    const int c = (lane & 7) ^ ((R >> 1) & 7);
+    const int wrow = R < 128 ? n0 + R : f + n0 + (R - 128);
+    bsrc[i] = Be + (size_t)wrow * K + c * 16;
+  }
+  const int fr = lane & 31, fh = lane >> 5;
+  int aoff[2], asw[2], boff[4], bsw[4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int R = wm * 64 + i * 32 + fr;
+    aoff[i] = R * 128;
+    asw[i] = (R >> 1) & 7;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int R = (j < 2 ? wn * 64 + j * 32 : 128 + wn * 64 + (j - 2) * 32) + fr;
+    boff[j] = FQ_STAGE_A + R * 128;
+    bsw[j] = (R >> 1) & 7;
+  }
+  const float* sa_row[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int r = row0 + min(wm * 64 + i * 32 + fr, rows - 1);
+    const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
+    sa_row[i] = As + arow * nkb;
+  }
+  // weight scale rows: the W1 block and the W3 block of the tile
+  const float* sb_row0 = Bs + ((size_t)e * (2 * f / 128) + n0 / 128) * nkb;
+  const float* sb_row1 = Bs + ((size_t)e * (2 * f / 128) + (f + n0) / 128) * nkb;
+
+  f32x16 acc[2][4], part[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = part[i][j][q] = 0.0f;
+  const int nk = nkb;
+  constexpr int VMS = FQ_A_INS + FQ_B_INS;
+#define FQ_ISSUE(kstep)                                                                        \
+  {                                                                                            \
+    char* st_ = lds + ((kstep) % F8_NSTAGE) * FQ_STAGE;                                        \
+    const int k0_ = (kstep) * 128;                                                             \
+    _Pragma("unroll") for (int i = 0; i < FQ_A_INS; ++i) __builtin_amdgcn_global_load_lds(     \
+        asrc[i] + k0_, (lds_void*)(st_ + (wv * (FQ_BM / 4) + i * 8) * 128), 16, 0, 0);         \
+    _Pragma("unroll") for (int i = 0; i < FQ_B_INS; ++i) __builtin_amdgcn_global_load_lds(     \
+        bsrc[i] + k0_, (lds_void*)(st_ + FQ_STAGE_A + (wv * (FQ_BN / 4) + i * 8) * 128), 16,   \
+        0, 0);                                                                                 \
+  }
+#define FQ_READ(AF, BF, stp, h)                                                               \
+  {                                                                                           \
+    const char* st_ = lds + ((stp) % F8_NSTAGE) * FQ_STAGE;                                   \
+    const int c0_ = 4 * (h) + fh, c1_ = 4 * (h) + 2 + fh;                                     \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                           \
+      const u32x4 lo_ = *(const u32x4*)(st_ + aoff[i] + ((c0_ ^ asw[i]) << 4));               \
+      const u32x4 hi_ = *(const u32x4*)(st_ + aoff[i] + ((c1_ ^ asw[i]) << 4));               \
+      AF[i] = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                     \
+                      (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};                    \
+    }                                                                                         \
+    _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                           \
+      const u32x4 lo_ = *(const u32x4*)(st_ + boff[j] + ((c0_ ^ bsw[j]) << 4));               \
+      const u32x4 hi_ = *(const u32x4*)(st_ + boff[j] + ((c1_ ^ bsw[j]) << 4));               \
+      BF[j] = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                     \
+                      (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};                    \
+    }                                                                                         \
+  }
+#define FQ_MFMA(AF, BF)                                                                       \
+  _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 4; ++j) \
+      part[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(BF[j], AF[i], part[i][j], \
+                                                                    0, 0, 0, 0, 0, 0);
+#define FQ_WAITN(n_)                         \
+  switch (n_) {                              \
+    case 0: WAIT_VM_LGKM0(0); break;         \
+    case 1: WAIT_VM_LGKM0(VMS); break;       \
+    default: WAIT_VM_LGKM0(2 * VMS); break;  \
+  }
+  i32x8 a0[2], b0[4], a1[2], b1[4];
+  float sa[2], sb[2], san[2], sbn[2];
+  const int pre = nk < F8_NSTAGE ? nk : F8_NSTAGE;
+  for (int s_ = 0; s_ < pre; ++s_) FQ_ISSUE(s_);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) san[i] = sa_row[i][0];
+  sbn[0] = sb_row0[0];
+  sbn[1] = sb_row1[0];
+  FQ_WAITN(pre - 1);
+  stage_barrier();
+  FQ_READ(a0, b0, 0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) sa[i] = san[i];
+    sb[0] = sbn[0];
+    sb[1] = sbn[1];
+    FQ_READ(a1, b1, kt, 1);
+    FQ_MFMA(a0, b0);
+    if (kt + 1 < nk) {
+      const int last = nk - 1 < kt + F8_NSTAGE - 1 ? nk - 1 : kt + F8_NSTAGE - 1;
+      FQ_WAITN(last - (kt + 1));
+      stage_barrier();
+#pragma unroll
+      for (int i = 0; i < 2; ++i) san[i] = sa_row[i][kt + 1];
+      sbn[0] = sb_row0[kt + 1];
+      sbn[1] = sb_row1[kt + 1];
+      if (kt + F8_NSTAGE < nk) FQ_ISSUE(kt + F8_NSTAGE);
+      FQ_READ(a0, b0, kt + 1, 0);
+    }
+    FQ_MFMA(a1, b1);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float sc = sa[i] * sb[j >> 1];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          acc[i][j][q] = fmaf(part[i][j][q], sc, acc[i][j][q]);
+          part[i][j][q] = 0.0f;
+        }
+      }
+  }
+#undef FQ_ISSUE
+#undef FQ_READ
+#undef FQ_MFMA
+#undef FQ_WAITN
+  WAIT_VM_LGKM0(0);
+  stage_barrier();
+
+  // h = silu(A) * B rounded to BF16 (lane: token row wm*64 + 32 i + fr,
+  // h columns wn*64 + 32 j + 8 (q/4) + 4 fh + q%4 of the tile), the row's
+  // amax over the 128 columns, then the codes through LDS
+  uint8_t* Cs = (uint8_t*)lds;
+  float* red = (float*)(lds + FQ_BM * FQ_CLD);  // [2][FQ_BM]
+  float hv[2][2][16];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    float m = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const float v = (float)(bf16_t)(silu(acc[i][j][q]) * acc[i][j + 2][q]);
+        hv[i][j][q] = v;
+        m = fmaxf(m, fabsf(v));
+      }
+    m = fmaxf(m, __shfl_xor(m, 32, 64));
+    if (fh == 0) red[wn * FQ_BM + wm * 64 + i * 32 + fr] = m;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int rl = wm * 64 + i * 32 + fr;
+    const float a = fmaxf(red[rl], red[FQ_BM + rl]);
+    const bool nz = a > 0.0f;
+    const float inv = nz ? 448.0f / a : 1.0f;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        uint32_t w = 0u;
+        if (nz) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w |= fp8_encode(hv[i][j][g * 4 + q] * inv) << (8 * q);
+        }
+        *(uint32_t*)(Cs + rl * FQ_CLD + wn * 64 + j * 32 + g * 8 + fh * 4) = w;
+      }
+    if (wn == 0 && fh == 0 && rl < rows)
+      Hs[(size_t)(row0 + rl) * (f / 128) + nt] = nz ? a / 448.0f : 1.0f;
+  }
+  __syncthreads();
+  for (int c = tid; c < FQ_BM * 8; c += 256) {
+    const int rr = c >> 3, cc = (c & 7) * 16;
+    if (rr >= rows) continue;
+    *(u32x4*)(Hq + (size_t)(row0 + rr) * f + n0 + cc) = *(const u32x4*)(Cs + rr * FQ_CLD + cc);
+  }
+}
+template __global__ void gemm_fp8_swiglu_q<false>(const fp8_t* __restrict__,
+                                                  const float* __restrict__,
+                                                  const int32_t* __restrict__, int,
+                                                  const fp8_t* __restrict__,
+                                                  const float* __restrict__, fp8_t* __restrict__,
+                                                  float* __restrict__, const int32_t* __restrict__,
+                                                  const int32_t* __restrict__, int, int, int, int,
+                                                  int, int);
+template __global__ void gemm_fp8_swiglu_q<true>(const fp8_t* __restrict__,
+                                                 const float* __restrict__,
+                                                 const int32_t* __restrict__, int,
+                                                 const fp8_t* __restrict__,
+                                                 const float* __restrict__, fp8_t* __restrict__,
+                                                 float* __restrict__, const int32_t* __restrict__,
+                                                 const int32_t* __restrict__, int, int, int, int,
+                                                 int, int);
 
 // ============================================================ MX formats
 // OCP Microscaling blocks: 32 consecutive elements along K share an E8M0
@@ -1848,8 +2067,10 @@ FfnWs carve_ffn(const moe_cfg& c, void* base, size_t* total) {
   r.tile_start_big = wc.take<int32_t>((size_t)c.E + 1);
   const size_t N = (size_t)c.T * c.k;
   const int mxf = mx_format(c.w);
-  r.h = wc.take<char>(mxf >= 0 ? N * mx_row_bytes(mxf, (size_t)c.d_ff)
-                               : N * (size_t)c.d_ff * act_bytes(c.act));
+  // FP8 experts keep h only as codes and scales (quantised by GEMM 1)
+  r.h = wc.take<char>(mxf >= 0                ? N * mx_row_bytes(mxf, (size_t)c.d_ff)
+                      : c.w == MOE_FP8E4M3 ? 0
+                                           : N * (size_t)c.d_ff * act_bytes(c.act));
   r.hq = nullptr;
   r.hs = nullptr;
   r.hx = mxf >= 0 ? wc.take<uint8_t>(N * (size_t)(c.d_ff / 32)) : nullptr;
@@ -1872,37 +2093,37 @@ size_t ffn_ws_bytes(const moe_cfg& c) {
 
 namespace moe_gemm {
 
-// The FP8 expert products: GEMM 1 + SwiGLU (token rows gathered through
-// row_map when it is given), the 1 x 128 quantisation of h, GEMM 2.
+// The FP8 expert products: GEMM 1 + SwiGLU with the 1 x 128 quantisation
+// of h in its epilogue (token rows gathered through row_map when it is
+// given), GEMM 2.
 void launch_fp8_ffn(const moe_cfg& c, const FfnWs& w, const fp8_t* Aq, const float* As,
                     const int32_t* row_map, const int32_t* offsets, const fp8_t* W13,
                     const float* W13_scale, const fp8_t* W2, const float* W2_scale, bf16_t* Y,
                     hipStream_t st) {
   const int N = c.T * c.k;
+  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, FQ_BM, w.tile_start);
   hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
   const int mt_big = (N + GBM - 1) / GBM + c.E;
-  const int nt1 = c.d_ff / 64;
-  const int G1 = (mt_big * nt1 + 7) / 8 * 8;
+  const int mt1 = (N + FQ_BM - 1) / FQ_BM + c.E;
+  const int nt1 = c.d_ff / 128;
+  const int G1 = (mt1 * nt1 + 7) / 8 * 8;
+  // h leaves GEMM 1 as its 1 x 128 FP8 codes and scales
   PROF_BEGIN("gemm1_swiglu", st);
   if (row_map)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_SWIGLU, true>), dim3(G1), dim3(256), 0,
-                       st, Aq, As, row_map, c.T, W13, W13_scale, (bf16_t*)w.h, offsets,
-                       w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt1, G1);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_swiglu_q<true>), dim3(G1), dim3(256), 0, st, Aq,
+                       As, row_map, c.T, W13, W13_scale, w.hq, w.hs, offsets, w.tile_start, c.E,
+                       N, c.d, c.d_ff, nt1, G1);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_SWIGLU, false>), dim3(G1), dim3(256), 0,
-                       st, Aq, As, nullptr, 0, W13, W13_scale, (bf16_t*)w.h, offsets,
-                       w.tile_start_big, c.E, N, c.d, c.d_ff, c.d_ff, nt1, G1);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_swiglu_q<false>), dim3(G1), dim3(256), 0, st,
+                       Aq, As, nullptr, 0, W13, W13_scale, w.hq, w.hs, offsets, w.tile_start,
+                       c.E, N, c.d, c.d_ff, nt1, G1);
   PROF_END("gemm1_swiglu", st);
-  PROF_BEGIN("quant_h", st);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(fp8_quant_rows<bf16_t>), dim3((N + 3) / 4), dim3(256), 0, st,
-                     (const bf16_t*)w.h, N, c.d_ff, w.hq, w.hs);
-  PROF_END("quant_h", st);
   const int nt2 = c.d / 128;
   const int G2 = (mt_big * nt2 + 7) / 8 * 8;
   PROF_BEGIN("gemm2", st);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_big<EPI_PLAIN, false>), dim3(G2), dim3(256), 0, st,
-                     (const fp8_t*)w.hq, (const float*)w.hs, nullptr, 0, W2, W2_scale, Y, offsets,
-                     w.tile_start_big, c.E, N, c.d_ff, c.d_ff, c.d, nt2, G2);
+  hipLaunchKernelGGL(gemm_fp8_big, dim3(G2), dim3(256), 0, st,
+                     (const fp8_t*)w.hq, (const float*)w.hs, W2, W2_scale, Y, offsets,
+                     w.tile_start_big, c.E, N, c.d_ff, c.d, nt2, G2);
   PROF_END("gemm2", st);
 }
 
