@@ -16,15 +16,45 @@ namespace {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Eight consecutive values as FP32 (16-byte aligned loads), and stored.
+__device__ __forceinline__ void ld8(const float* p, float (&v)[8]) {
+  const f32x4 a = *(const f32x4*)p, b = *(const f32x4*)(p + 4);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = a[i];
+    v[4 + i] = b[i];
+  }
+}
+__device__ __forceinline__ void ld8(const bf16_t* p, float (&v)[8]) {
+  const bf16x8 a = *(const bf16x8*)p;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = (float)a[i];
+}
+__device__ __forceinline__ void st8(float* p, const float (&v)[8]) {
+  *(f32x4*)p = (f32x4){v[0], v[1], v[2], v[3]};
+  *(f32x4*)(p + 4) = (f32x4){v[4], v[5], v[6], v[7]};
+}
+__device__ __forceinline__ void st8(bf16_t* p, const float (&v)[8]) {
+  bf16x8 a;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = (bf16_t)v[i];
+  *(bf16x8*)p = a;
+}
+
 // One wavefront per token: dw by a fixed-order dot product (lane partials in
 // ascending column order, then a fixed butterfly), dY rows scaled by w.
-template <typename TA>
+// KT > 0: k == KT known at compile time (the k slot rows are loaded with no
+// branch between them, all in flight together); KT == 0: any k.  The same
+// operations in the same order either way.
+template <typename TA, int KT>
 __global__ __launch_bounds__(256) void combine_bwd_kernel(const TA* __restrict__ dOut,
                                                           const TA* __restrict__ Y, int T, int d,
-                                                          int k, const int32_t* __restrict__ inv_map,
+                                                          int k_rt,
+                                                          const int32_t* __restrict__ inv_map,
                                                           const float* __restrict__ w,
                                                           TA* __restrict__ dY,
                                                           float* __restrict__ dw) {
+  const int k = KT > 0 ? KT : k_rt;
   // one wavefront per token, 8 consecutive elements per lane and step: the
   // dOut segment is read once for all k slots; each slot's dot product
   // runs over the elements in the same order as a slot-by-slot loop
@@ -44,6 +74,22 @@ __global__ __launch_bounds__(256) void combine_bwd_kernel(const TA* __restrict__
     float g[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) g[i] = ActIO<TA>::ld(dOut, (size_t)t * d + c0 + i);
+    if (KT > 0) {
+      // all k segments requested before the first dY store
+      float yv[KT > 0 ? KT : 1][8];
+#pragma unroll
+      for (int j = 0; j < KT; ++j) ld8(Y + (size_t)slots[j] * d + c0, yv[j]);
+#pragma unroll
+      for (int j = 0; j < KT; ++j) {
+        TA* dyr = dY + (size_t)slots[j] * d + c0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          part[j] = __builtin_fmaf(g[i], yv[j][i], part[j]);
+          ActIO<TA>::st(dyr, i, ws_[j] * g[i]);
+        }
+      }
+      continue;
+    }
 #pragma unroll
     for (int j = 0; j < MOE_MAX_K; ++j) {
       if (j < k) {
@@ -71,37 +117,14 @@ __global__ __launch_bounds__(256) void combine_bwd_kernel(const TA* __restrict__
 // FP32.  With ROUTER the second sum is the router backward into the tokens;
 // ds is formed here from w and dw (and written to ds_out).  Without ROUTER
 // idx, w, dw, Wr and ds_out are not touched (they may be null).  One
-// wavefront per token.
-// Eight consecutive values as FP32 (16-byte aligned loads), and stored.
-__device__ __forceinline__ void ld8(const float* p, float (&v)[8]) {
-  const f32x4 a = *(const f32x4*)p, b = *(const f32x4*)(p + 4);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    v[i] = a[i];
-    v[4 + i] = b[i];
-  }
-}
-__device__ __forceinline__ void ld8(const bf16_t* p, float (&v)[8]) {
-  const bf16x8 a = *(const bf16x8*)p;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) v[i] = (float)a[i];
-}
-__device__ __forceinline__ void st8(float* p, const float (&v)[8]) {
-  *(f32x4*)p = (f32x4){v[0], v[1], v[2], v[3]};
-  *(f32x4*)(p + 4) = (f32x4){v[4], v[5], v[6], v[7]};
-}
-__device__ __forceinline__ void st8(bf16_t* p, const float (&v)[8]) {
-  bf16x8 a;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) a[i] = (bf16_t)v[i];
-  *(bf16x8*)p = a;
-}
-
-template <typename TA, bool ROUTER, typename TO>
+// wavefront per token.  KT as in combine_bwd_kernel.
+template <typename TA, bool ROUTER, typename TO, int KT>
 __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
-    const TA* __restrict__ dXp, int T, int d, int k, int E, const int32_t* __restrict__ inv_map,
-    const int32_t* __restrict__ idx, const float* __restrict__ w, const float* __restrict__ dw,
-    const float* __restrict__ Wr, TO* __restrict__ dX, float* __restrict__ ds_out) {
+    const TA* __restrict__ dXp, int T, int d, int k_rt, int E,
+    const int32_t* __restrict__ inv_map, const int32_t* __restrict__ idx,
+    const float* __restrict__ w, const float* __restrict__ dw, const float* __restrict__ Wr,
+    TO* __restrict__ dX, float* __restrict__ ds_out) {
+  const int k = KT > 0 ? KT : k_rt;
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= T) return;
@@ -137,6 +160,30 @@ __global__ __launch_bounds__(256) void dispatch_bwd_kernel(
     float acc[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) acc[i] = 0.0f;
+    if (KT > 0) {
+      // every slot segment (and router row) requested before the sums
+      float v[KT > 0 ? KT : 1][8], r[ROUTER && KT > 0 ? KT : 1][8];
+#pragma unroll
+      for (int j = 0; j < KT; ++j) ld8(dXp + (size_t)slots[j] * d + c0, v[j]);
+      if (ROUTER) {
+#pragma unroll
+        for (int j = 0; j < KT; ++j) ld8(Wr + (size_t)ex[j] * d + c0, r[j]);
+      }
+      // keep the scheduler from sinking the loads back between the sums
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < KT; ++j)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = acc[i] + v[j][i];
+      if (ROUTER) {
+#pragma unroll
+        for (int j = 0; j < KT; ++j)
+#pragma unroll
+          for (int i = 0; i < 8; ++i) acc[i] = __builtin_fmaf(ds[j], r[j][i], acc[i]);
+      }
+      st8(dX + (size_t)t * d + c0, acc);
+      continue;
+    }
 #pragma unroll
     for (int j = 0; j < MOE_MAX_K; ++j) {
       if (j < k) {
@@ -283,14 +330,16 @@ extern "C" moe_status moe_combine_bwd(const moe_cfg* cfg, const void* dOut, cons
     return MOE_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   PROF_BEGIN("combine_bwd", st);
-  if (c.act == MOE_F32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_bwd_kernel<float>), dim3((c.T + 3) / 4), dim3(256),
-                       0, st, (const float*)dOut, (const float*)Y, c.T, c.d, c.k, inv_map, topk_w,
-                       (float*)dY, dtopk_w);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_bwd_kernel<bf16_t>), dim3((c.T + 3) / 4), dim3(256),
-                       0, st, (const bf16_t*)dOut, (const bf16_t*)Y, c.T, c.d, c.k, inv_map,
-                       topk_w, (bf16_t*)dY, dtopk_w);
+#define CBWD(TA, KT)                                                                           \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_bwd_kernel<TA, KT>), dim3((c.T + 3) / 4),          \
+                     dim3(256), 0, st, (const TA*)dOut, (const TA*)Y, c.T, c.d, c.k, inv_map,    \
+                     topk_w, (TA*)dY, dtopk_w);
+  if (c.act == MOE_F32) {
+    if (c.k == 8) CBWD(float, 8) else CBWD(float, 0)
+  } else {
+    if (c.k == 8) CBWD(bf16_t, 8) else CBWD(bf16_t, 0)
+  }
+#undef CBWD
   PROF_END("combine_bwd", st);
   MOE_LAUNCH_CHECK();
   return MOE_OK;
@@ -306,14 +355,16 @@ extern "C" moe_status moe_dispatch_bwd(const moe_cfg* cfg, const void* dX_perm,
   if (!aligned(dX_perm, 16) || !aligned(dX, 16) || !aligned(inv_map, 4)) return MOE_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   PROF_BEGIN("dispatch_bwd", st);
-  if (c.act == MOE_F32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<float, false, float>), dim3((c.T + 3) / 4),
-                       dim3(256), 0, st, (const float*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr, nullptr,
-                       nullptr, nullptr, dX, nullptr);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<bf16_t, false, float>), dim3((c.T + 3) / 4),
-                       dim3(256), 0, st, (const bf16_t*)dX_perm, c.T, c.d, c.k, c.E, inv_map, nullptr,
-                       nullptr, nullptr, nullptr, dX, nullptr);
+#define DBWD0(TA, KT)                                                                          \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<TA, false, float, KT>),               \
+                     dim3((c.T + 3) / 4), dim3(256), 0, st, (const TA*)dX_perm, c.T, c.d, c.k,  \
+                     c.E, inv_map, nullptr, nullptr, nullptr, nullptr, dX, nullptr);
+  if (c.act == MOE_F32) {
+    if (c.k == 8) DBWD0(float, 8) else DBWD0(float, 0)
+  } else {
+    if (c.k == 8) DBWD0(bf16_t, 8) else DBWD0(bf16_t, 0)
+  }
+#undef DBWD0
   PROF_END("dispatch_bwd", st);
   MOE_LAUNCH_CHECK();
   return MOE_OK;
@@ -345,9 +396,16 @@ extern "C" moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const flo
     hipLaunchKernelGGL(slot_source, dim3((N + 255) / 256), dim3(256), 0, st, inv_map, N,
                        w.slot_src);
 #define DBWD(TA, TO)                                                                          \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<TA, true, TO>), dim3((c.T + 3) / 4),    \
-                     dim3(256), 0, st, (const TA*)dX_perm, c.T, c.d, c.k, c.E, inv_map, topk_idx, \
-                     topk_w, dtopk_w, Wr, (TO*)dX, w.ds);
+  {                                                                                           \
+    if (c.k == 8)                                                                             \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<TA, true, TO, 8>),               \
+                         dim3((c.T + 3) / 4), dim3(256), 0, st, (const TA*)dX_perm, c.T, c.d,  \
+                         c.k, c.E, inv_map, topk_idx, topk_w, dtopk_w, Wr, (TO*)dX, w.ds);    \
+    else                                                                                      \
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(dispatch_bwd_kernel<TA, true, TO, 0>),               \
+                         dim3((c.T + 3) / 4), dim3(256), 0, st, (const TA*)dX_perm, c.T, c.d,  \
+                         c.k, c.E, inv_map, topk_idx, topk_w, dtopk_w, Wr, (TO*)dX, w.ds);    \
+  }
     if (c.act == MOE_F32) {
       if (dx_dtype == MOE_F32) DBWD(float, float) else DBWD(float, bf16_t)
     } else {

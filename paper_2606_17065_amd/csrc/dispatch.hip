@@ -192,12 +192,16 @@ __global__ __launch_bounds__(256) void dispatch_gather_fp8(const TA* __restrict_
 }
 
 // out[t] = sum_j w[t,j] * Y[inv_map[t,j]], FP32 in j order; one wavefront
-// per token, 8 elements per lane per step.
-template <typename TA>
+// per token, 8 elements per lane per step.  KT > 0: k == KT known at
+// compile time, so the k row loads carry no branches and are all in flight
+// together (with a run-time k each sits behind its own guard and waits for
+// the previous one); KT == 0: any k.
+template <typename TA, int KT>
 __global__ __launch_bounds__(256) void combine_kernel(const TA* __restrict__ Y, int T, int d,
-                                                      int k, const int32_t* __restrict__ inv_map,
+                                                      int k_rt, const int32_t* __restrict__ inv_map,
                                                       const float* __restrict__ w,
                                                       TA* __restrict__ out) {
+  const int k = KT > 0 ? KT : k_rt;
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= T) return;
@@ -369,12 +373,21 @@ extern "C" moe_status moe_combine(const moe_cfg* cfg, const void* Y, const int32
   hipStream_t st = (hipStream_t)stream;
   dim3 g((c.T + 3) / 4);
   PROF_BEGIN("combine", st);
-  if (c.act == MOE_F32)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_kernel<float>), g, dim3(256), 0, st, (const float*)Y,
-                       c.T, c.d, c.k, inv_map, topk_w, (float*)out);
-  else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_kernel<bf16_t>), g, dim3(256), 0, st,
-                       (const bf16_t*)Y, c.T, c.d, c.k, inv_map, topk_w, (bf16_t*)out);
+  if (c.act == MOE_F32) {
+    if (c.k == 8)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_kernel<float, 8>), g, dim3(256), 0, st,
+                         (const float*)Y, c.T, c.d, c.k, inv_map, topk_w, (float*)out);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_kernel<float, 0>), g, dim3(256), 0, st,
+                         (const float*)Y, c.T, c.d, c.k, inv_map, topk_w, (float*)out);
+  } else {
+    if (c.k == 8)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_kernel<bf16_t, 8>), g, dim3(256), 0, st,
+                         (const bf16_t*)Y, c.T, c.d, c.k, inv_map, topk_w, (bf16_t*)out);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(combine_kernel<bf16_t, 0>), g, dim3(256), 0, st,
+                         (const bf16_t*)Y, c.T, c.d, c.k, inv_map, topk_w, (bf16_t*)out);
+  }
   PROF_END("combine", st);
   MOE_LAUNCH_CHECK();
   return MOE_OK;

@@ -28,6 +28,8 @@ BWD2 = synth.MoEShape("bf16-bwd-k4", T=1100, d=512, E=16, k=4, f=384, zipf=1.3, 
 # softmax weight is identically 1) and top-3 over seven experts
 BWD_K1 = synth.MoEShape("bf16-bwd-k1", T=333, d=256, E=5, k=1, f=128, zipf=1.1, act="bf16", w="bf16")
 BWD_K3 = synth.MoEShape("bf16-bwd-k3", T=250, d=256, E=7, k=3, f=256, zipf=1.2, act="bf16", w="bf16")
+# top-8 (the slot count the combine and dispatch backward kernels unroll)
+BWD_K8 = synth.MoEShape("bf16-bwd-k8", T=600, d=512, E=16, k=8, f=128, zipf=1.2, act="bf16", w="bf16")
 
 
 def _setup(shape, config):
@@ -40,7 +42,8 @@ def _setup(shape, config):
     return cfg, d, h, fw, dOut
 
 
-@pytest.mark.parametrize("shape,config", [(BWD, 31), (BWD2, 32), (BWD_K1, 34), (BWD_K3, 35)])
+@pytest.mark.parametrize("shape,config", [(BWD, 31), (BWD2, 32), (BWD_K1, 34), (BWD_K3, 35),
+                                          (BWD_K8, 36)])
 def test_backward_pieces_match_oracle(shape, config):
     cfg, d, h, fw, dOut = _setup(shape, config)
     dY, dw = layer.combine_bwd(cfg, dOut, fw["Y"], fw["inv_map"], fw["w"])
@@ -160,11 +163,13 @@ def test_dispatch_backward_is_a_gather_sum():
 
 
 @pytest.mark.parametrize("act", ["f32", "bf16"])
-def test_dispatch_backward_sums_in_slot_order_exactly(act):
+@pytest.mark.parametrize("k", [3, 8])
+def test_dispatch_backward_sums_in_slot_order_exactly(act, k):
     """moe_dispatch_bwd: dX[t] = sum over j in order of dX_perm[inv_map[t, j]],
     FP32 additions, bit for bit against the same additions on the host (FP32
-    and BF16 slot gradients; d = 136 is not a multiple of 64 lanes x 8)."""
-    T, d, E, k = 333, 136, 5, 3
+    and BF16 slot gradients; d = 136 is not a multiple of 64 lanes x 8; top-8
+    runs the kernel with the slot count fixed at compile time)."""
+    T, d, E = 333, 136, 9
     shape = synth.MoEShape("dbwd", T=T, d=d, E=E, k=k, f=128, zipf=1.1, act=act, w=act)
     cfg = cfg_for(shape)
     rng = np.random.Generator(np.random.PCG64(77))

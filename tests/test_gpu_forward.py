@@ -30,6 +30,8 @@ MID = synth.MoEShape("bf16-ragged", T=3000, d=256, E=16, k=4, f=192, zipf=1.2, a
 SMALL_BF16 = synth.MoEShape("bf16-tiny", T=200, d=128, E=8, k=2, f=64, zipf=1.0, act="bf16", w="bf16")
 # every expert GEMM on the 256-row tile path, several ragged row tiles per expert
 BIG_TILES = synth.MoEShape("bf16-bigtile", T=2100, d=512, E=8, k=2, f=384, zipf=1.1, act="bf16", w="bf16")
+# top-8 (the slot count the combine kernel unrolls)
+TOP8 = synth.MoEShape("bf16-top8", T=700, d=256, E=16, k=8, f=128, zipf=1.2, act="bf16", w="bf16")
 
 
 def _run_route(shape, config, mode=L.MOE_PRICE_ACP, max_iters=None, price=None, rep=0):
@@ -170,8 +172,8 @@ def test_layer_forward_bf16_tiny():
     _layer_check(SMALL_BF16, 19, 1.5e-2)
 
 
-def test_combine_matches_oracle_on_gpu_y():
-    shape = MID
+@pytest.mark.parametrize("shape", [MID, TOP8], ids=["top4", "top8"])
+def test_combine_matches_oracle_on_gpu_y(shape):
     inp = synth.make_inputs(shape, 20)
     d, h = device_inputs(shape, inp)
     cfg = cfg_for(shape)
