@@ -1899,59 +1899,79 @@ __global__ __launch_bounds__(256) void batched_transpose(const bf16_t* __restric
     *(bf16x8*)(out + base + (size_t)(c0 + c) * R + r0 + rr) = y;
   }
 }
+// Channels per block of slot_transpose: ST_CH chunks of 64, all loaded
+// before the transposed stores, so the slot lookup (a search over the
+// expert tiles) is shared by them and their loads are in flight together.
+constexpr int ST_CH = 4;
 __global__ __launch_bounds__(256) void slot_transpose(const bf16_t* __restrict__ src,
                                                       const int32_t* __restrict__ row_map, int T,
                                                       int C, const int32_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ ptile, int E,
                                                       bf16_t* __restrict__ outT, int ldT) {
-  // 64 padded slots x 64 channels per block; 16-byte loads of token rows,
-  // 16-byte stores along the slots (C, ldT and the slot offset are
-  // multiples of 64)
-  __shared__ __attribute__((aligned(16))) bf16_t tile[64][72];
+  // 64 padded slots x ST_CH * 64 channels per block; 16-byte loads of
+  // token rows, 16-byte stores along the slots (C, ldT and the slot offset
+  // are multiples of 64)
+  __shared__ __attribute__((aligned(16))) bf16_t tile[ST_CH][64][72];
   __shared__ int srow[64];
-  const int p0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  __shared__ int sp[MOE_MAX_E + 1];
+  const int tid = threadIdx.x;
+  const int p0 = blockIdx.x * 64, cb = blockIdx.y * 64 * ST_CH;
   const int total = ptile[E] * PADK;
   if (p0 >= total) return;
-  if (threadIdx.x < 64) {
-    const int p = p0 + threadIdx.x;
+  for (int i = tid; i <= E; i += 256) sp[i] = ptile[i];
+  __syncthreads();
+  if (tid < 64) {
+    const int p = p0 + tid;
     int r = -1;
     if (p < total) {
       int lo = 0, hi = E - 1;  // largest e with pad_off[e] <= p
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (ptile[mid] * PADK <= p) lo = mid;
+        if (sp[mid] * PADK <= p) lo = mid;
         else hi = mid - 1;
       }
-      const int i = p - ptile[lo] * PADK;
+      const int i = p - sp[lo] * PADK;
       if (i < offsets[lo + 1] - offsets[lo]) {
         r = offsets[lo] + i;
         if (row_map) r = min(max(row_map[r], 0), T - 1);
       }
     }
-    srow[threadIdx.x] = r;
+    srow[tid] = r;
   }
   __syncthreads();
-  for (int v = threadIdx.x; v < 512; v += 256) {
-    const int pl = v >> 3, cc = (v & 7) * 8;
-    const int r = srow[pl];
-    bf16x8 x;
-    if (r >= 0) {
-      x = *(const bf16x8*)(src + (size_t)r * C + c0 + cc);
-    } else {
+  const int nch = min(ST_CH, (C - cb) / 64);
+  bf16x8 x[ST_CH][2];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = (bf16_t)0.0f;
+  for (int q = 0; q < ST_CH; ++q)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int v = tid + 256 * h, pl = v >> 3, cc = (v & 7) * 8;
+      const int r = srow[pl];
+      if (q < nch && r >= 0) {
+        x[q][h] = *(const bf16x8*)(src + (size_t)r * C + cb + q * 64 + cc);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[q][h][u] = (bf16_t)0.0f;
+      }
     }
-    *(bf16x8*)&tile[pl][cc] = x;
-  }
-  __syncthreads();
-  for (int v = threadIdx.x; v < 512; v += 256) {
-    const int c = v >> 3, pr = (v & 7) * 8;
-    if (p0 + pr >= total) continue;
-    bf16x8 y;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) y[u] = tile[pr + u][c];
-    *(bf16x8*)(outT + (size_t)(c0 + c) * ldT + p0 + pr) = y;
-  }
+  for (int q = 0; q < ST_CH; ++q)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int v = tid + 256 * h, pl = v >> 3, cc = (v & 7) * 8;
+      *(bf16x8*)&tile[q][pl][cc] = x[q][h];
+    }
+  __syncthreads();
+  for (int q = 0; q < nch; ++q)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int v = tid + 256 * h, c = v >> 3, pr = (v & 7) * 8;
+      if (p0 + pr >= total) continue;
+      bf16x8 y;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) y[u] = tile[q][pr + u][c];
+      *(bf16x8*)(outT + (size_t)(cb + q * 64 + c) * ldT + p0 + pr) = y;
+    }
 }
 
 // Zero each expert's pad columns [pad_off[e] + rows_e, pad_off[e+1]) of a
@@ -2332,10 +2352,11 @@ moe_status ffn_bwd_impl(const moe_cfg* cfg, const void* X, const int32_t* row_ma
                          2 * f, d, nt, G);
     }
     const int pblocks = (w.ldT + 63) / 64;
-    hipLaunchKernelGGL(slot_transpose, dim3(pblocks, d / 64), dim3(256), 0, st, Xb, row_map, c.T,
-                       d, offsets, w.ptile, E, w.XpT, w.ldT);
-    hipLaunchKernelGGL(slot_transpose, dim3(pblocks, d / 64), dim3(256), 0, st, dYb, nullptr, N,
-                       d, offsets, w.ptile, E, w.dYT, w.ldT);
+    const dim3 gst(pblocks, (d / 64 + ST_CH - 1) / ST_CH);
+    hipLaunchKernelGGL(slot_transpose, gst, dim3(256), 0, st, Xb, row_map, c.T, d, offsets,
+                       w.ptile, E, w.XpT, w.ldT);
+    hipLaunchKernelGGL(slot_transpose, gst, dim3(256), 0, st, dYb, nullptr, N, d, offsets,
+                       w.ptile, E, w.dYT, w.ldT);
     hipLaunchKernelGGL(pad_zero, dim3(E, (2 * f + 255) / 256), dim3(256), 0, st, w.dABT, 2 * f,
                        w.ldT, offsets, w.ptile);
     hipLaunchKernelGGL(pad_zero, dim3(E, (f + 255) / 256), dim3(256), 0, st, w.hT, f, w.ldT,
