@@ -775,8 +775,9 @@ __global__ __launch_bounds__(256) void fp8_quant_tiles(const TA* __restrict__ X,
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-// FP8 grouped GEMM 2 with per-block scales: A codes [N,K] (h) with scales
-// [N, K/128] (1 x 128 blocks), B codes [E, Ncols, K] with scales
+// FP8 grouped GEMM 2 when d % 256 != 0, with per-block scales: A codes
+// [N,K] (h) with scales [N, K/128] (1 x 128 blocks), B codes [E, Ncols, K]
+// with scales
 // [E, Ncols/128, K/128] (128 x 128 blocks).  Tiles and tile order as
 // gemm_bf16_big (256 tokens x 128 weight rows, 4 wavefronts of 128 x 64);
 // one stage is one 128-wide K block: 128-byte LDS rows (a full cache line
@@ -978,34 +979,41 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_big(
 }
 
 
-// FP8 GEMM 1 + SwiGLU with h quantised in the epilogue: the tile is 128
-// token rows x 256 weight rows (W1 rows n0..n0+127 and the matching W3
-// rows), so each tile owns whole 1 x 128 blocks of h and writes its codes
-// and scales directly (no BF16 h round trip).  4 wavefronts, 2 (token
-// halves of 64) x 2 (h-column halves of 64); each holds 2 x 4 tiles of
-// 32x32 (W1 column tiles j = 0, 1 and their W3 partners j = 2, 3), the
-// same 128 + 128 accumulator registers as the 256 x 128 tile.  Stages,
-// swizzle and per-K-block promotion are those of gemm_fp8_big; h is the
-// BF16 rounding of silu(A) * B, quantised exactly as fp8_quant_rows does
-// (block amax, inverse, codes, scale).  A token row's amax meets in LDS:
-// a lane holds 32 of the row's 128 values, its partner lane (lane ^ 32) 32
-// more, the other column-half wavefront the rest.  GATHER: token row r of
-// the A operand (codes and scales) is row row_map[r] of the per-token
-// arrays (the permute fused into the operand DMA).
+// FP8 expert products on a 128-token x 256-weight-row tile with 8
+// wavefronts, two per SIMD, so one wavefront's per-K-block promotion FMAs
+// run under the other's MFMAs (one wavefront per SIMD, as in gemm_fp8_big,
+// serialises them).  Each wavefront holds 2 x 2 tiles of 32x32 (64 tokens)
+// with a block and a running accumulator set (128 + 128 registers).
+// Stages, swizzle and per-K-block promotion are those of gemm_fp8_big.
+//   GEMM 1 (PLAIN false): weight rows W1 n0..n0+127 and their W3 partners,
+//     wavefront (wm, wn) = 64 tokens x h columns wn*32..wn*32+31 (W1 tile
+//     j = 0, W3 tile j = 1), so a tile owns whole 1 x 128 blocks of h and
+//     writes its codes and scales directly (no BF16 h round trip): h is the
+//     BF16 rounding of silu(A) * B, quantised exactly as fp8_quant_rows
+//     does (block amax, inverse, codes, scale); a token row's amax meets in
+//     LDS from a lane, its partner lane (lane ^ 32) and the other three
+//     column-quarter wavefronts.
+//   GEMM 2 (PLAIN true): 256 consecutive weight rows (output columns, f is
+//     the output width), wavefront = 64 tokens x 64 columns; Y stored in
+//     BF16 through LDS.
+// GATHER: token row r of the A operand (codes and scales) is row
+// row_map[r] of the per-token arrays (the permute fused into the DMA).
 constexpr int FQ_BM = 128, FQ_BN = 256;
 constexpr int FQ_STAGE_A = FQ_BM * 128, FQ_STAGE_B = FQ_BN * 128;
 constexpr int FQ_STAGE = FQ_STAGE_A + FQ_STAGE_B;
-constexpr int FQ_A_INS = FQ_BM * 128 / 1024 / 4, FQ_B_INS = FQ_BN * 128 / 1024 / 4;
+constexpr int FQ_W = 8;  // wavefronts: 2 (token halves) x 4 (column quarters)
+constexpr int FQ_A_INS = FQ_BM * 128 / 1024 / FQ_W, FQ_B_INS = FQ_BN * 128 / 1024 / FQ_W;
 constexpr int FQ_CLD = 144;  // bytes per staged code row (16-byte aligned)
-static_assert(FQ_BM * FQ_CLD + 2 * FQ_BM * 4 <= F8_NSTAGE * FQ_STAGE, "epilogue fits the ring");
+static_assert(FQ_BM * FQ_CLD + 4 * FQ_BM * 4 <= F8_NSTAGE * FQ_STAGE, "epilogue fits the ring");
 
-template <bool GATHER>
-__global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
+template <bool GATHER, bool PLAIN>
+__global__ __launch_bounds__(512, 1) void gemm_fp8_q(
     const fp8_t* __restrict__ A, const float* __restrict__ As,
     const int32_t* __restrict__ row_map, int T, const fp8_t* __restrict__ B,
     const float* __restrict__ Bs, fp8_t* __restrict__ Hq, float* __restrict__ Hs,
-    const int32_t* __restrict__ offsets, const int32_t* __restrict__ tile_start, int E, int N,
-    int K, int f, int n_tiles, int grid_total) {
+    bf16_t* __restrict__ Y, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ tile_start, int E, int N, int K, int f, int n_tiles,
+    int grid_total) {
   typedef __attribute__((address_space(3))) void lds_void;
   __shared__ __attribute__((aligned(1024))) char lds[F8_NSTAGE * FQ_STAGE];
   const int b = blockIdx.x;
@@ -1014,15 +1022,16 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
   if (!find_tile_grouped(tile_start, offsets, E, FQ_BM, N, n_tiles, Lt, e, row0, rows, nt))
     return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = __builtin_amdgcn_readfirstlane(wv & 1);
-  const int n0 = nt * 128;
+  const int wm = wv >> 2, wn = __builtin_amdgcn_readfirstlane(wv & 3);
+  const int n0 = nt * (PLAIN ? 256 : 128);
   const int nkb = K / 128;
-  const fp8_t* Be = B + (size_t)e * 2 * f * K;
+  const int Brows_e = PLAIN ? f : 2 * f;  // PLAIN: f is the output width
+  const fp8_t* Be = B + (size_t)e * Brows_e * K;
   const fp8_t* asrc[FQ_A_INS];
   const fp8_t* bsrc[FQ_B_INS];
 #pragma unroll
   for (int i = 0; i < FQ_A_INS; ++i) {
-    const int R = wv * (FQ_BM / 4) + i * 8 + (lane >> 3);
+    const int R = wv * (FQ_BM / FQ_W) + i * 8 + (lane >> 3);
     const int c = (lane & 7) ^ ((R >> 1) & 7);
     const int r = row0 + min(R, rows - 1);
     const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
@@ -1030,13 +1039,13 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
   }
 #pragma unroll
   for (int i = 0; i < FQ_B_INS; ++i) {
-    const int R = wv * (FQ_BN / 4) + i * 8 + (lane >> 3);
+    const int R = wv * (FQ_BN / FQ_W) + i * 8 + (lane >> 3);
     const int c = (lane & 7) ^ ((R >> 1) & 7);
-    const int wrow = R < 128 ? n0 + R : f + n0 + (R - 128);
+    const int wrow = PLAIN ? n0 + R : (R < 128 ? n0 + R : f + n0 + (R - 128));
     bsrc[i] = Be + (size_t)wrow * K + c * 16;
   }
   const int fr = lane & 31, fh = lane >> 5;
-  int aoff[2], asw[2], boff[4], bsw[4];
+  int aoff[2], asw[2], boff[2], bsw[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int R = wm * 64 + i * 32 + fr;
@@ -1044,8 +1053,9 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
     asw[i] = (R >> 1) & 7;
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int R = (j < 2 ? wn * 64 + j * 32 : 128 + wn * 64 + (j - 2) * 32) + fr;
+  for (int j = 0; j < 2; ++j) {
+    // SwiGLU: W1 rows, then their W3 partners; plain: 64 consecutive rows
+    const int R = (PLAIN ? wn * 64 + j * 32 : j * 128 + wn * 32) + fr;
     boff[j] = FQ_STAGE_A + R * 128;
     bsw[j] = (R >> 1) & 7;
   }
@@ -1056,15 +1066,18 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
     const size_t arow = GATHER ? (size_t)min(max(row_map[r], 0), T - 1) : (size_t)r;
     sa_row[i] = As + arow * nkb;
   }
-  // weight scale rows: the W1 block and the W3 block of the tile
-  const float* sb_row0 = Bs + ((size_t)e * (2 * f / 128) + n0 / 128) * nkb;
-  const float* sb_row1 = Bs + ((size_t)e * (2 * f / 128) + (f + n0) / 128) * nkb;
+  // weight scale rows: the W1 block and the W3 block of the tile; plain:
+  // the block of the wavefront's 64 rows (both of its column tiles)
+  const float* sb_row0 =
+      Bs + ((size_t)e * (Brows_e / 128) + (PLAIN ? n0 + wn * 64 : n0) / 128) * nkb;
+  const float* sb_row1 =
+      PLAIN ? sb_row0 : Bs + ((size_t)e * (Brows_e / 128) + (f + n0) / 128) * nkb;
 
-  f32x16 acc[2][4], part[2][4];
+  f32x16 acc[2][2], part[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[i][j][q] = part[i][j][q] = 0.0f;
   const int nk = nkb;
@@ -1074,9 +1087,9 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
     char* st_ = lds + ((kstep) % F8_NSTAGE) * FQ_STAGE;                                        \
     const int k0_ = (kstep) * 128;                                                             \
     _Pragma("unroll") for (int i = 0; i < FQ_A_INS; ++i) __builtin_amdgcn_global_load_lds(     \
-        asrc[i] + k0_, (lds_void*)(st_ + (wv * (FQ_BM / 4) + i * 8) * 128), 16, 0, 0);         \
+        asrc[i] + k0_, (lds_void*)(st_ + (wv * (FQ_BM / FQ_W) + i * 8) * 128), 16, 0, 0);      \
     _Pragma("unroll") for (int i = 0; i < FQ_B_INS; ++i) __builtin_amdgcn_global_load_lds(     \
-        bsrc[i] + k0_, (lds_void*)(st_ + FQ_STAGE_A + (wv * (FQ_BN / 4) + i * 8) * 128), 16,   \
+        bsrc[i] + k0_, (lds_void*)(st_ + FQ_STAGE_A + (wv * (FQ_BN / FQ_W) + i * 8) * 128), 16,\
         0, 0);                                                                                 \
   }
 #define FQ_READ(AF, BF, stp, h)                                                               \
@@ -1089,7 +1102,7 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
       AF[i] = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                     \
                       (int)hi_[0], (int)hi_[1], (int)hi_[2], (int)hi_[3]};                    \
     }                                                                                         \
-    _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                           \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                           \
       const u32x4 lo_ = *(const u32x4*)(st_ + boff[j] + ((c0_ ^ bsw[j]) << 4));               \
       const u32x4 hi_ = *(const u32x4*)(st_ + boff[j] + ((c1_ ^ bsw[j]) << 4));               \
       BF[j] = (i32x8){(int)lo_[0], (int)lo_[1], (int)lo_[2], (int)lo_[3],                     \
@@ -1097,7 +1110,7 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
     }                                                                                         \
   }
 #define FQ_MFMA(AF, BF)                                                                       \
-  _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 4; ++j) \
+  _Pragma("unroll") for (int i = 0; i < 2; ++i) _Pragma("unroll") for (int j = 0; j < 2; ++j) \
       part[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(BF[j], AF[i], part[i][j], \
                                                                     0, 0, 0, 0, 0, 0);
 #define FQ_WAITN(n_)                         \
@@ -1106,7 +1119,7 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
     case 1: WAIT_VM_LGKM0(VMS); break;       \
     default: WAIT_VM_LGKM0(2 * VMS); break;  \
   }
-  i32x8 a0[2], b0[4], a1[2], b1[4];
+  i32x8 a0[2], b0[2], a1[2], b1[2];
   float sa[2], sb[2], san[2], sbn[2];
   const int pre = nk < F8_NSTAGE ? nk : F8_NSTAGE;
   for (int s_ = 0; s_ < pre; ++s_) FQ_ISSUE(s_);
@@ -1139,8 +1152,8 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float sc = sa[i] * sb[j >> 1];
+      for (int j = 0; j < 2; ++j) {
+        const float sc = sa[i] * sb[j];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           acc[i][j][q] = fmaf(part[i][j][q], sc, acc[i][j][q]);
@@ -1155,23 +1168,46 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
   WAIT_VM_LGKM0(0);
   stage_barrier();
 
+  if (PLAIN) {
+    // Y tile (BF16) through LDS: lane holds token row wm*64 + 32 i + fr,
+    // columns wn*64 + 32 j + 8 (q/4) + 4 fh + q%4
+    constexpr int YLD = 256 + 8;
+    bf16_t* Ys = (bf16_t*)lds;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          bf16x4 v;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = (bf16_t)acc[i][j][g * 4 + q];
+          *(bf16x4*)(Ys + (wm * 64 + i * 32 + fr) * YLD + wn * 64 + j * 32 + g * 8 + fh * 4) = v;
+        }
+    __syncthreads();
+    for (int c = tid; c < FQ_BM * 32; c += 64 * FQ_W) {
+      const int rr = c >> 5, cc = (c & 31) * 8;
+      if (rr >= rows) continue;
+      *(u32x4*)(Y + (size_t)(row0 + rr) * f + n0 + cc) = *(const u32x4*)(Ys + rr * YLD + cc);
+    }
+    return;
+  }
+
   // h = silu(A) * B rounded to BF16 (lane: token row wm*64 + 32 i + fr,
-  // h columns wn*64 + 32 j + 8 (q/4) + 4 fh + q%4 of the tile), the row's
-  // amax over the 128 columns, then the codes through LDS
+  // h columns wn*32 + 8 (q/4) + 4 fh + q%4 of the tile), the row's amax
+  // over the 128 columns, then the codes through LDS
   uint8_t* Cs = (uint8_t*)lds;
-  float* red = (float*)(lds + FQ_BM * FQ_CLD);  // [2][FQ_BM]
-  float hv[2][2][16];
+  float* red = (float*)(lds + FQ_BM * FQ_CLD);  // [FQ_W / 2][FQ_BM]
+  float hv[2][16];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     float m = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const float v = (float)(bf16_t)(silu(acc[i][j][q]) * acc[i][j + 2][q]);
-        hv[i][j][q] = v;
-        m = fmaxf(m, fabsf(v));
-      }
+    for (int q = 0; q < 16; ++q) {
+      const float v = (float)(bf16_t)(silu(acc[i][0][q]) * acc[i][1][q]);
+      hv[i][q] = v;
+      m = fmaxf(m, fabsf(v));
+    }
     m = fmaxf(m, __shfl_xor(m, 32, 64));
     if (fh == 0) red[wn * FQ_BM + wm * 64 + i * 32 + fr] = m;
   }
@@ -1179,46 +1215,44 @@ __global__ __launch_bounds__(256, 1) void gemm_fp8_swiglu_q(
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int rl = wm * 64 + i * 32 + fr;
-    const float a = fmaxf(red[rl], red[FQ_BM + rl]);
+    const float a = fmaxf(fmaxf(red[rl], red[FQ_BM + rl]),
+                          fmaxf(red[2 * FQ_BM + rl], red[3 * FQ_BM + rl]));
     const bool nz = a > 0.0f;
     const float inv = nz ? 448.0f / a : 1.0f;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int g = 0; g < 4; ++g) {
+      uint32_t w = 0u;
+      if (nz) {
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        uint32_t w = 0u;
-        if (nz) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) w |= fp8_encode(hv[i][j][g * 4 + q] * inv) << (8 * q);
-        }
-        *(uint32_t*)(Cs + rl * FQ_CLD + wn * 64 + j * 32 + g * 8 + fh * 4) = w;
+        for (int q = 0; q < 4; ++q) w |= fp8_encode(hv[i][g * 4 + q] * inv) << (8 * q);
       }
+      *(uint32_t*)(Cs + rl * FQ_CLD + wn * 32 + g * 8 + fh * 4) = w;
+    }
     if (wn == 0 && fh == 0 && rl < rows)
       Hs[(size_t)(row0 + rl) * (f / 128) + nt] = nz ? a / 448.0f : 1.0f;
   }
   __syncthreads();
-  for (int c = tid; c < FQ_BM * 8; c += 256) {
+  for (int c = tid; c < FQ_BM * 8; c += 64 * FQ_W) {
     const int rr = c >> 3, cc = (c & 7) * 16;
     if (rr >= rows) continue;
     *(u32x4*)(Hq + (size_t)(row0 + rr) * f + n0 + cc) = *(const u32x4*)(Cs + rr * FQ_CLD + cc);
   }
 }
-template __global__ void gemm_fp8_swiglu_q<false>(const fp8_t* __restrict__,
-                                                  const float* __restrict__,
-                                                  const int32_t* __restrict__, int,
-                                                  const fp8_t* __restrict__,
-                                                  const float* __restrict__, fp8_t* __restrict__,
-                                                  float* __restrict__, const int32_t* __restrict__,
-                                                  const int32_t* __restrict__, int, int, int, int,
-                                                  int, int);
-template __global__ void gemm_fp8_swiglu_q<true>(const fp8_t* __restrict__,
-                                                 const float* __restrict__,
-                                                 const int32_t* __restrict__, int,
-                                                 const fp8_t* __restrict__,
-                                                 const float* __restrict__, fp8_t* __restrict__,
-                                                 float* __restrict__, const int32_t* __restrict__,
-                                                 const int32_t* __restrict__, int, int, int, int,
-                                                 int, int);
+template __global__ void gemm_fp8_q<false, false>(
+    const fp8_t* __restrict__, const float* __restrict__, const int32_t* __restrict__, int,
+    const fp8_t* __restrict__, const float* __restrict__, fp8_t* __restrict__, float* __restrict__,
+    bf16_t* __restrict__, const int32_t* __restrict__, const int32_t* __restrict__, int, int, int,
+    int, int, int);
+template __global__ void gemm_fp8_q<true, false>(
+    const fp8_t* __restrict__, const float* __restrict__, const int32_t* __restrict__, int,
+    const fp8_t* __restrict__, const float* __restrict__, fp8_t* __restrict__, float* __restrict__,
+    bf16_t* __restrict__, const int32_t* __restrict__, const int32_t* __restrict__, int, int, int,
+    int, int, int);
+template __global__ void gemm_fp8_q<false, true>(
+    const fp8_t* __restrict__, const float* __restrict__, const int32_t* __restrict__, int,
+    const fp8_t* __restrict__, const float* __restrict__, fp8_t* __restrict__, float* __restrict__,
+    bf16_t* __restrict__, const int32_t* __restrict__, const int32_t* __restrict__, int, int, int,
+    int, int, int);
 
 // ============================================================ MX formats
 // OCP Microscaling blocks: 32 consecutive elements along K share an E8M0
@@ -2122,28 +2156,38 @@ void launch_fp8_ffn(const moe_cfg& c, const FfnWs& w, const fp8_t* Aq, const flo
                     hipStream_t st) {
   const int N = c.T * c.k;
   hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, FQ_BM, w.tile_start);
-  hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM, w.tile_start_big);
-  const int mt_big = (N + GBM - 1) / GBM + c.E;
   const int mt1 = (N + FQ_BM - 1) / FQ_BM + c.E;
   const int nt1 = c.d_ff / 128;
   const int G1 = (mt1 * nt1 + 7) / 8 * 8;
   // h leaves GEMM 1 as its 1 x 128 FP8 codes and scales
   PROF_BEGIN("gemm1_swiglu", st);
   if (row_map)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_swiglu_q<true>), dim3(G1), dim3(256), 0, st, Aq,
-                       As, row_map, c.T, W13, W13_scale, w.hq, w.hs, offsets, w.tile_start, c.E,
-                       N, c.d, c.d_ff, nt1, G1);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_q<true, false>), dim3(G1), dim3(64 * FQ_W), 0,
+                       st, Aq, As, row_map, c.T, W13, W13_scale, w.hq, w.hs, nullptr, offsets,
+                       w.tile_start, c.E, N, c.d, c.d_ff, nt1, G1);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_swiglu_q<false>), dim3(G1), dim3(256), 0, st,
-                       Aq, As, nullptr, 0, W13, W13_scale, w.hq, w.hs, offsets, w.tile_start,
-                       c.E, N, c.d, c.d_ff, nt1, G1);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_q<false, false>), dim3(G1), dim3(64 * FQ_W), 0,
+                       st, Aq, As, nullptr, 0, W13, W13_scale, w.hq, w.hs, nullptr, offsets,
+                       w.tile_start, c.E, N, c.d, c.d_ff, nt1, G1);
   PROF_END("gemm1_swiglu", st);
-  const int nt2 = c.d / 128;
-  const int G2 = (mt_big * nt2 + 7) / 8 * 8;
   PROF_BEGIN("gemm2", st);
-  hipLaunchKernelGGL(gemm_fp8_big, dim3(G2), dim3(256), 0, st,
-                     (const fp8_t*)w.hq, (const float*)w.hs, W2, W2_scale, Y, offsets,
-                     w.tile_start_big, c.E, N, c.d_ff, c.d, nt2, G2);
+  if (c.d % 256 == 0) {
+    // 128 slot rows x 256 output columns per tile, the same tile schedule
+    const int nt2 = c.d / 256;
+    const int G2 = (mt1 * nt2 + 7) / 8 * 8;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(gemm_fp8_q<false, true>), dim3(G2), dim3(64 * FQ_W), 0,
+                       st, (const fp8_t*)w.hq, (const float*)w.hs, nullptr, 0, W2, W2_scale,
+                       nullptr, nullptr, Y, offsets, w.tile_start, c.E, N, c.d_ff, c.d, nt2, G2);
+  } else {
+    hipLaunchKernelGGL(ffn_tiles, dim3(1), dim3(1024), 0, st, offsets, c.E, GBM,
+                       w.tile_start_big);
+    const int mt_big = (N + GBM - 1) / GBM + c.E;
+    const int nt2 = c.d / 128;
+    const int G2 = (mt_big * nt2 + 7) / 8 * 8;
+    hipLaunchKernelGGL(gemm_fp8_big, dim3(G2), dim3(256), 0, st, (const fp8_t*)w.hq,
+                       (const float*)w.hs, W2, W2_scale, Y, offsets, w.tile_start_big, c.E, N,
+                       c.d_ff, c.d, nt2, G2);
+  }
   PROF_END("gemm2", st);
 }
 

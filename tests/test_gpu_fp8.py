@@ -93,6 +93,10 @@ FP8_WIDE = synth.MoEShape("fp8-wide", T=1300, d=512, E=8, k=2, f=384, zipf=1.2, 
 # T not a multiple of the 4 rows a quantising block handles, an odd number
 # of experts, top-3, one 128-wide K block in GEMM 2
 FP8_ODD = synth.MoEShape("fp8-odd", T=333, d=256, E=5, k=3, f=128, zipf=1.1, act="bf16", w="fp8")
+# d % 256 != 0: the second product on 256 x 128 tiles instead of 128 x 256,
+# top-8 (the compile-time slot count of the combine)
+FP8_D384 = synth.MoEShape("fp8-d384", T=500, d=384, E=12, k=8, f=256, zipf=1.2, act="bf16",
+                          w="fp8")
 
 
 def _fp8_case(shape, config):
@@ -111,7 +115,8 @@ def dataclass_bf16(shape):
     return dataclasses.replace(shape, w="bf16")
 
 
-@pytest.mark.parametrize("shape,config", [(FP8_SMALL, 31), (FP8_WIDE, 32), (FP8_ODD, 33)])
+@pytest.mark.parametrize("shape,config", [(FP8_SMALL, 31), (FP8_WIDE, 32), (FP8_ODD, 33),
+                                          (FP8_D384, 34)])
 def test_fp8_layer_matches_emulating_oracle(shape, config):
     cfg, inp, d, h, W13d, W2d, q13, s13, q2, s2 = _fp8_case(shape, config)
     r = layer.forward(cfg, d["X"], d["Wr"], d["br"], q13, q2, W13_scale=s13, W2_scale=s2)
