@@ -586,9 +586,9 @@ moe_status moe_route_bwd(const moe_cfg* cfg, const void* X, const float* Wr,
  * thread-safe).  When enabled, each instrumented kernel launch is bracketed
  * by a HIP event pair on its stream.  moe_prof_get waits for the recorded
  * events and returns the summed elapsed time and the launch count of one
- * kernel name: "router_logits", "price_loop", "dispatch", "gemm1_swiglu",
- * "gemm2", "quant_h" (FP8 experts), "combine", "combine_bwd", "ffn_bwd",
- * "dispatch_bwd", "route_bwd".
+ * kernel name: "router_logits", "price_loop", "dispatch", "quant_rows" (FP8
+ * token quantisation), "quant_mx" (MX token quantisation), "gemm1_swiglu",
+ * "gemm2", "combine", "combine_bwd", "ffn_bwd", "dispatch_bwd", "route_bwd".
  * moe_prof_reset forgets every record.
  */
 moe_status moe_prof_enable(int on);
