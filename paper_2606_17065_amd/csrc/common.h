@@ -75,6 +75,24 @@ __device__ __forceinline__ uint32_t fp8_encode(float v) {
   return code | sign;
 }
 
+// Four fp8_encode codes packed in a word (value i in byte i) by gfx950's
+// conversion instruction, which rounds exactly as fp8_encode for every FP32
+// value of magnitude at most 464 (measured over all of them on the
+// MI355X); larger magnitudes, infinities and NaN get fp8_encode's
+// saturation to +-448 with the sign kept.
+__device__ __forceinline__ uint32_t fp8_encode4(float a, float b, float c, float d) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  uint32_t r = (uint32_t)w;
+  const float v[4] = {a, b, c, d};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t sat = ((__float_as_uint(v[i]) >> 24) & 0x80u) | 0x7Eu;
+    r = fabsf(v[i]) <= 464.0f ? r : ((r & ~(0xFFu << (8 * i))) | (sat << (8 * i)));
+  }
+  return r;
+}
+
 typedef uint8_t fp8_t;
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 

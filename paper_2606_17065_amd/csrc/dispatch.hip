@@ -176,8 +176,8 @@ __global__ __launch_bounds__(256) void dispatch_gather_fp8(const TA* __restrict_
     u32x2 q;
     q[0] = q[1] = 0u;
     if (nz) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) q[i >> 2] |= fp8_encode(v[i] * inv) << (8 * (i & 3));
+      q[0] = fp8_encode4(v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv);
+      q[1] = fp8_encode4(v[4] * inv, v[5] * inv, v[6] * inv, v[7] * inv);
     }
     if (act) {
 #pragma unroll

@@ -725,8 +725,8 @@ __global__ __launch_bounds__(256) void fp8_quant_rows(const TA* __restrict__ X, 
     u32x2 q;
     q[0] = q[1] = 0u;
     if (nz) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) q[i >> 2] |= fp8_encode(v[i] * inv) << (8 * (i & 3));
+      q[0] = fp8_encode4(v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv);
+      q[1] = fp8_encode4(v[4] * inv, v[5] * inv, v[6] * inv, v[7] * inv);
     }
     if (act) {
       *(u32x2*)(Q + (size_t)r * C + col) = q;
@@ -1222,10 +1222,9 @@ __global__ __launch_bounds__(512, 1) void gemm_fp8_q(
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       uint32_t w = 0u;
-      if (nz) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) w |= fp8_encode(hv[i][g * 4 + q] * inv) << (8 * q);
-      }
+      if (nz)
+        w = fp8_encode4(hv[i][g * 4] * inv, hv[i][g * 4 + 1] * inv, hv[i][g * 4 + 2] * inv,
+                        hv[i][g * 4 + 3] * inv);
       *(uint32_t*)(Cs + rl * FQ_CLD + wn * 32 + g * 8 + fh * 4) = w;
     }
     if (wn == 0 && fh == 0 && rl < rows)
