@@ -61,6 +61,35 @@ def test_quantize_rows_bit_exact(dtype):
     np.testing.assert_array_equal(s.cpu().numpy().view(np.uint32), rs.view(np.uint32))
 
 
+def test_quantize_rows_codes_at_every_rounding_midpoint():
+    """Every e4m3 value, every midpoint between neighbours (ties to even)
+    and the FP32 values just beside each midpoint, both signs: in 1 x 128
+    blocks whose largest magnitude is 448, so the
+    inverse scale is exactly 1 and each code is the encoding of the value
+    itself; the GPU codes must equal the oracle's."""
+    mags = fp8.decode(np.arange(0, 127, dtype=np.uint8)).astype(np.float64)  # 0 .. 448
+    mids = (mags[:-1] + mags[1:]) / 2.0
+    m32 = mids.astype(F32)
+    assert np.array_equal(m32.astype(np.float64), mids)  # midpoints are FP32 values
+    below = np.nextafter(m32, F32(0.0))
+    above = np.nextafter(m32, F32(np.inf))
+    pos = np.concatenate([mags.astype(F32), m32, below, above, F32([2.0 ** -10, 2.0 ** -12])])
+    pos = pos[pos <= 448.0]
+    v = np.concatenate([pos, -pos]).astype(F32)
+    per = 127  # values per block; the block's first element is 448
+    nb = -(-v.size // per)
+    x = np.zeros((nb, 128), F32)
+    x[:, 0] = 448.0
+    x.reshape(-1)[np.arange(v.size) // per * 128 + 1 + np.arange(v.size) % per] = v
+    xd = torch.from_numpy(x).cuda()
+    q, s_ = layer.quantize_fp8(xd, 1)
+    torch.cuda.synchronize()
+    rq, rs = fp8.quantize_blocks(x, 1, 128)
+    assert np.all(rs == 1.0)
+    np.testing.assert_array_equal(q.cpu().numpy(), rq)
+    np.testing.assert_array_equal(s_.cpu().numpy().view(np.uint32), rs.view(np.uint32))
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 def test_quantize_expert_tiles_bit_exact(dtype):
     rng = np.random.Generator(np.random.PCG64(2))
