@@ -569,11 +569,15 @@ __global__ __launch_bounds__(64 * RW * TG) void acp_rank(
 // token's k chosen experts (FP32, max-subtracted).  After a non-finite
 // logit no ranking has run: every token gets the defined routing
 // idx[t][j] = j with NaN weights, so that nothing downstream reads
-// unwritten memory and every output the routing feeds is NaN.
+// unwritten memory and every output the routing feeds is NaN.  KT > 0:
+// k == KT known at compile time, so the k index loads (and then the k
+// logit loads) are in flight together instead of one behind each guard.
+template <int KT>
 __global__ __launch_bounds__(256) void route_weights(const float* __restrict__ logits,
                                                      int32_t* __restrict__ idx, int T, int E,
-                                                     int k, const int32_t* __restrict__ state,
+                                                     int k_rt, const int32_t* __restrict__ state,
                                                      float* __restrict__ w) {
+  const int k = KT > 0 ? KT : k_rt;
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= T || state[ST_SKIP_WEIGHTS]) return;
   if (state[ST_STATUS] != MOE_OK) {
@@ -1291,8 +1295,12 @@ void launch_rank_select_repair(const moe_cfg& c, const RouteWs& ws, const float*
                        (int)(c.price_mode == MOE_PRICE_SUBGRAD));
   }
   }
-  hipLaunchKernelGGL(route_weights, dim3((T + 255) / 256), dim3(256), 0, st, logits, idx, T, E, k,
-                     ws.state, w);
+  if (k == 8)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(route_weights<8>), dim3((T + 255) / 256), dim3(256), 0, st,
+                       logits, idx, T, E, k, ws.state, w);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(route_weights<0>), dim3((T + 255) / 256), dim3(256), 0, st,
+                       logits, idx, T, E, k, ws.state, w);
   hipLaunchKernelGGL(HIP_KERNEL_NAME(capacity_repair<L>), dim3(1), dim3(REP_THREADS), 0, st,
                      ws.sT, logits, price, T, E, k, C, ws.state, idx, w, load, ws.held, ws.tried,
                      ws.prop, ws.missing);
